@@ -1,0 +1,219 @@
+"""Plain float64 reference of one RSOL MHD-PIC step (gather, kick, exchange
+deposit, drift), the CR moments and the timestep rule.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  Every array operation
+here is written to accept complex128 as well as float64 so that the same code
+yields complex-step derivatives; floors and the periodic wrap act on the real
+part only.
+
+Layouts: grid quantities are (C, n_cells) or (C, nz, ny, nx) with x fastest,
+cell = ix + nx*(iy + ny*iz); packets are (3, Np).  Fields are cell-centred:
+the node of cell i sits at (i + 1/2) dx.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class Params:
+    """Run parameters of the packet integrator (all in the workload's code units)."""
+    nx: int
+    ny: int
+    nz: int
+    dx: float
+    shape: str          # "cic" or "tsc": the spatial kernel W of the packet decomposition
+    c: float            # true speed of light
+    c_tilde: float      # reduced speed of light
+    qomc: float         # q / (m_s c) of the CR species
+    dt: float
+    mass: float         # packet mass weight M_j = N_j <m_s>
+
+    @property
+    def n_cells(self):
+        return self.nx * self.ny * self.nz
+
+    @property
+    def volume(self):
+        return self.dx ** 3
+
+
+def lorentz_gamma(u):
+    """True Lorentz factor of a packet from u = gamma*beta (Sec. 2, Eqs. (7)-(8)):
+    gamma = 1/sqrt(1 - beta.beta) = sqrt(1 + u.u)."""
+    return np.sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2])
+
+
+def electric_field(u_gas, B, c):
+    """Ideal-MHD electric field E = -(u/c) x B with the TRUE c (Sec. 2, the
+    definition following Eq. (5))."""
+    return -np.cross(u_gas, B, axis=0) / c
+
+
+def courant_dt(u, B, c, c_tilde, qomc, dx, courant):
+    """One global RSOL timestep (Sec. 4, timestep constraints; Sec. 2, closing
+    discussion).  Gyro limit dt < C / Omega_eff with Omega_eff = (c_tilde/c) q|B|/(gamma m c)
+    and cell-crossing limit dt < C dx / |v_eff| with v_eff = c_tilde beta.
+    Both carry the factor c/c_tilde relative to c_tilde = c."""
+    gamma = lorentz_gamma(u)
+    beta = np.sqrt(u[0] ** 2 + u[1] ** 2 + u[2] ** 2) / gamma
+    bmag = np.sqrt(np.sum(np.asarray(B).reshape(3, -1) ** 2, axis=0))
+    dt_cell = courant * dx / (c_tilde * np.max(beta))
+    omega_max = (c_tilde / c) * qomc * np.max(bmag) / np.min(gamma)
+    dt_gyro = courant / omega_max
+    return float(min(dt_cell, dt_gyro))
+
+
+def _axis_weights(s, n, shape):
+    """Node indices and weights along one axis for a position s = x/dx.
+
+    CIC: nodes i0, i0+1 with i0 = floor(s - 1/2), weights (1-f, f).
+    TSC: nodes i-1, i, i+1 around the home cell i = floor(s), with
+    d = s - i - 1/2, weights (1/2 (1/2-d)^2, 3/4 - d^2, 1/2 (1/2+d)^2).
+    These are the standard Hockney-Eastwood assignment functions standing in
+    for the paper's spatial kernel W of the packet decomposition (Sec. 2, Eq. (4)).
+    """
+    if shape == "cic":
+        sp = s - 0.5
+        i0 = np.floor(np.real(sp)).astype(np.int64)
+        f = sp - i0
+        nodes = [i0, i0 + 1]
+        wts = [1.0 - f, f]
+    elif shape == "tsc":
+        i = np.floor(np.real(s)).astype(np.int64)
+        d = s - i - 0.5
+        nodes = [i - 1, i, i + 1]
+        wts = [0.5 * (0.5 - d) ** 2, 0.75 - d * d, 0.5 * (0.5 + d) ** 2]
+    else:
+        raise ValueError(shape)
+    return [np.mod(a, n) for a in nodes], wts
+
+
+def shape_weights(x, p: Params):
+    """Flat node indices (Np, K) and tensor-product weights (Np, K) of every
+    packet, K = 8 (CIC) or 27 (TSC); column k = a + m*(b + m*c) for the x, y, z
+    offsets a, b, c of an m-point stencil."""
+    ix, wx = _axis_weights(x[0] / p.dx, p.nx, p.shape)
+    iy, wy = _axis_weights(x[1] / p.dx, p.ny, p.shape)
+    iz, wz = _axis_weights(x[2] / p.dx, p.nz, p.shape)
+    idx, w = [], []
+    for c in range(len(iz)):
+        for b in range(len(iy)):
+            for a in range(len(ix)):
+                idx.append(ix[a] + p.nx * (iy[b] + p.ny * iz[c]))
+                w.append(wx[a] * wy[b] * wz[c])
+    return np.stack(idx, axis=1), np.stack(w, axis=1)
+
+
+def gather(F, idx, w):
+    """Field at each packet, F_p = sum_i W(x_p - x_i) F_i (the kernel-weighted
+    field average that Eq. (5) evaluates at the packet, Sec. 2).
+    F is (C, n_cells); returns (C, Np)."""
+    return np.einsum("cnk,nk->cn", F[:, idx], w)
+
+
+def deposit(idx, w, vals, n_cells):
+    """Scatter sum_j W(x_j - x_i) vals_j onto the grid (the sum over packets in
+    Eq. (12) and in the moments of Sec. 2).  vals is (C, Np); returns (C, n_cells)."""
+    flat = idx.ravel()
+    out = []
+    for v in vals:
+        contrib = (w * v[:, None]).ravel()
+        if np.iscomplexobj(contrib):
+            r = np.bincount(flat, weights=contrib.real, minlength=n_cells)
+            i = np.bincount(flat, weights=contrib.imag, minlength=n_cells)
+            out.append(r + 1j * i)
+        else:
+            out.append(np.bincount(flat, weights=contrib, minlength=n_cells))
+    return np.stack(out)
+
+
+def boris_kick(u, Ep, Bp, h):
+    """Advance u = gamma*beta by one step of Eq. (11),
+    d(gamma beta)/dt = (c_tilde/c) (q/(m c)) [E + beta x B],
+    with the relativistic Boris scheme (half electric kick, magnetic rotation
+    about B with gamma taken after the half kick, half electric kick).
+    h = (c_tilde/c) (q/(m c)) dt / 2; returns u at the next half step."""
+    um = u + h * Ep
+    gm = lorentz_gamma(um)
+    t = (h / gm) * Bp
+    tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2]
+    s = 2.0 * t / (1.0 + tt)
+    up = um + np.cross(um, t, axis=0)
+    uplus = um + np.cross(up, s, axis=0)
+    return uplus + h * Ep
+
+
+def exchange(u_old, u_new, p: Params):
+    """Momentum and energy each packet hands to the gas over one step.
+    Momentum: Eq. (12), d(rho u)/dt = -sum_j (1/V_j)(c/c_tilde) d_t P_j with
+    P_j = M_j c u_j (Sec. 2, Eq. (10) and the packet totals).  Energy: the
+    same equal-and-opposite rule applied to the packet energy M_j c^2 gamma_j
+    (Eq. (9)).  Returns (dP (3, Np), dE (Np)) per packet, before weighting."""
+    f = -(p.c / p.c_tilde) * p.mass * p.c
+    dP = f * (u_new - u_old)
+    dE = f * p.c * (lorentz_gamma(u_new) - lorentz_gamma(u_old))
+    return dP, dE
+
+
+def wrap(x, length):
+    """Periodic wrap into [0, length); a result equal to length maps to 0."""
+    y = x - length * np.floor(np.real(x) / length)
+    return np.where(np.real(y) >= length, y - length, y)
+
+
+def drift(x, u_new, p: Params):
+    """Position update of Sec. 2: d<x>/dt = (c_tilde/c) <v> = c_tilde beta,
+    i.e. x^{n+1} = x^n + c_tilde dt u^{n+1/2} / gamma^{n+1/2}."""
+    g = lorentz_gamma(u_new)
+    out = x + (p.c_tilde * p.dt) * u_new / g
+    box = (p.nx * p.dx, p.ny * p.dx, p.nz * p.dx)
+    return np.stack([wrap(out[d], box[d]) for d in range(3)])
+
+
+def moments(x, u, p: Params):
+    """CR mass, momentum and energy densities on the grid from the packet totals
+    M_j, P_j = M_j c u_j and E_j = M_j c^2 gamma_j (Sec. 2, after Eq. (10)),
+    spread by the kernel W and divided by the cell volume."""
+    idx, w = shape_weights(x, p)
+    g = lorentz_gamma(u)
+    m = p.mass * np.ones(u.shape[1], dtype=u.dtype)
+    vals = np.concatenate([m[None], p.mass * p.c * u, (p.mass * p.c * p.c * g)[None]])
+    d = deposit(idx, w, vals, p.n_cells) / p.volume
+    return d[0], d[1:4], d[4]
+
+
+def step(x, u, E, B, p: Params):
+    """One packet step: gather E, B at x^n, kick u^{n-1/2} -> u^{n+1/2}, deposit
+    the exchange at x^n with the same weights, drift to x^{n+1}.
+    E, B are (3, n_cells).  Returns (x^{n+1}, u^{n+1/2}, dM (3, n_cells), dE (n_cells))
+    where dM, dE are this step's momentum and energy given to the gas per unit volume."""
+    idx, w = shape_weights(x, p)
+    Ep = gather(E, idx, w)
+    Bp = gather(B, idx, w)
+    h = 0.5 * (p.c_tilde / p.c) * p.qomc * p.dt
+    u_new = boris_kick(u, Ep, Bp, h)
+    dP, dEn = exchange(u, u_new, p)
+    dep = deposit(idx, w, np.concatenate([dP, dEn[None]]), p.n_cells) / p.volume
+    x_new = drift(x, u_new, p)
+    return x_new, u_new, dep[0:3], dep[3]
+
+
+def rollout(x, u, E, B, p: Params, nsteps, keep_history=False):
+    """nsteps packet steps from (x^0, u^{-1/2}).  Returns a dict with the final
+    state, the last step's exchange, the exchange summed over all steps and,
+    on request, the state before every step."""
+    dM_sum = np.zeros((3, p.n_cells), dtype=np.result_type(x, u, E, B))
+    dE_sum = np.zeros(p.n_cells, dtype=dM_sum.dtype)
+    dM = dE = None
+    hist = []
+    for _ in range(nsteps):
+        if keep_history:
+            hist.append((x, u))
+        x, u, dM, dE = step(x, u, E, B, p)
+        dM_sum = dM_sum + dM
+        dE_sum = dE_sum + dE
+    return dict(x=x, u=u, dM=dM, dE=dE, dM_sum=dM_sum, dE_sum=dE_sum, history=hist)

@@ -1,0 +1,410 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix,
+independent of the oracle's own formulas: closed forms of the gyro motion and
+the E x B drift, invariants, the c_tilde-scaling laws of the RSOL
+formulation, textbook assignment weights, a high-order ODE solve of the
+continuous equations, and brute-force cross checks."""
+
+from fractions import Fraction
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.integrate import solve_ivp
+
+import oracle
+from oracle import adjoint
+from workloads import make_workload
+from tests.helpers import oracle_params, oracle_fields
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _uniform_params(n, shape, ratio, dt=None, c=1000.0, qomc=4000.0, mass=1.0):
+    return oracle.Params(n, n, n, 1.0, shape, c, c / ratio, qomc, dt if dt is not None else 0.0, mass)
+
+
+def _uniform_fields(n, B=(1.0, 0.0, 0.0), u_gas=(0.0, 0.0, 0.0), c=1000.0):
+    nc = n ** 3
+    Bg = np.tile(np.asarray(B, float)[:, None], (1, nc))
+    ug = np.tile(np.asarray(u_gas, float)[:, None], (1, nc))
+    return oracle.electric_field(ug, Bg, c), Bg
+
+
+# ---------------------------------------------------------------- spatial kernel W
+
+def test_shape_weights_golden():
+    """Hand-worked CIC/TSC weights (tests/golden/shape_weights.txt, Hockney & Eastwood
+    Sec. 5-3), the kernel W of the packet decomposition, Sec. 2 Eq. (4).  The packet sits at
+    (s, s, s) so the 3-D weight of node (a, b, c) is w_a w_b w_c."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "shape_weights.txt")) if l.strip() and not l.startswith("#")]
+    assert len(rows) >= 8
+    n = 16
+    for r in rows:
+        shape, s, first = r[0], float(r[1]), int(r[2])
+        want = [float(Fraction(v)) for v in r[3:]]
+        m = len(want)
+        p = _uniform_params(n, shape, 1.0)
+        idx, w = oracle.shape_weights(np.array([[s], [s], [s]]), p)
+        assert idx.shape == (1, m ** 3)
+        for c in range(m):
+            for b in range(m):
+                for a in range(m):
+                    k = a + m * (b + m * c)
+                    assert idx[0, k] == (first + a) + n * ((first + b) + n * (first + c))
+                    assert w[0, k] == pytest.approx(want[a] * want[b] * want[c], abs=1e-15)
+
+
+@pytest.mark.parametrize("shape", ["cic", "tsc"])
+def test_partition_of_unity_and_linear_reproduction(shape):
+    """Sum_i W_i = 1, and a field linear in position is reproduced exactly away from the
+    periodic seam: both kernels are exact for linear functions (textbook property)."""
+    n = 16
+    p = _uniform_params(n, shape, 1.0)
+    rng = np.random.default_rng(1)
+    x = rng.uniform(3.0, 12.0, (3, 2000))
+    idx, w = oracle.shape_weights(x, p)
+    assert np.max(np.abs(w.sum(axis=1) - 1.0)) < 1e-14
+    ic = np.arange(n ** 3)
+    centres = np.stack([ic % n, (ic // n) % n, ic // n ** 2]) + 0.5
+    a, b = np.array([0.3, -1.1, 2.0]), np.array([[0.7, 0.1, -0.2], [0.0, 1.3, 0.4], [-0.5, 0.2, 0.9]])
+    F = a[:, None] + b @ centres
+    Fp = oracle.gather(F, idx, w)
+    assert np.max(np.abs(Fp - (a[:, None] + b @ x))) < 1e-12
+
+
+@pytest.mark.parametrize("shape", ["cic", "tsc"])
+def test_gather_deposit_adjoint(shape):
+    """<b, D a> = <G b, a>: the deposit is the transpose of the gather (exact identity)."""
+    n = 8
+    p = _uniform_params(n, shape, 1.0)
+    rng = np.random.default_rng(2)
+    x = rng.uniform(0.0, n, (3, 500))
+    idx, w = oracle.shape_weights(x, p)
+    a = rng.standard_normal((1, 500))
+    b = rng.standard_normal((1, n ** 3))
+    lhs = np.sum(b * oracle.deposit(idx, w, a, n ** 3))
+    rhs = np.sum(oracle.gather(b, idx, w) * a)
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + 1.0)
+
+
+# ---------------------------------------------------------------- gyro motion (Sec. 2 closing discussion)
+
+def _run_single(x0, u0, E, B, p, nsteps):
+    xs, us = [x0], [u0]
+    x, u = x0, u0
+    for _ in range(nsteps):
+        x, u, _, _ = oracle.step(x, u, E, B, p)
+        xs.append(x)
+        us.append(u)
+    return np.array(xs)[:, :, 0], np.array(us)[:, :, 0]
+
+
+@pytest.mark.parametrize("ratio", [1.0, 10.0, 100.0])
+def test_gyration_angle_per_step(ratio):
+    """In uniform B the packet momentum rotates by 2 atan(Omega_eff dt / 2) per step with
+    Omega_eff = (c_tilde/c) q B/(gamma m c) (Sec. 2: the gyro-frequency is reduced by
+    c_tilde/c); clockwise about B for q > 0; the parallel momentum is untouched."""
+    n = 16
+    E, B = _uniform_fields(n)
+    c, qomc = 1000.0, 4000.0
+    u0 = np.array([[3.0], [8.0], [-2.0]])
+    gamma = math.sqrt(1.0 + float(np.sum(u0 ** 2)))
+    p = _uniform_params(n, "cic", ratio, dt=2.0e-3 / ratio * 10.0)
+    xs, us = _run_single(np.array([[8.0], [8.0], [8.0]]), u0, E, B, p, 60)
+    omega_eff = (p.c_tilde / c) * qomc * 1.0 / gamma
+    want = -2.0 * math.atan(0.5 * omega_eff * p.dt)
+    ang = np.arctan2(us[:-1, 1] * us[1:, 2] - us[:-1, 2] * us[1:, 1], us[:-1, 1] * us[1:, 1] + us[:-1, 2] * us[1:, 2])
+    assert np.max(np.abs(ang - want)) < 1e-12 * abs(want) + 1e-15
+    assert np.all(us[:, 0] == u0[0, 0])
+
+
+def _circle_radius(y, z):
+    """Algebraic least-squares circle fit."""
+    A = np.stack([2 * y, 2 * z, np.ones_like(y)], axis=1)
+    sol, *_ = np.linalg.lstsq(A, y * y + z * z, rcond=None)
+    a, b, k = sol
+    return math.sqrt(k + a * a + b * b), np.sqrt((y - a) ** 2 + (z - b) ** 2)
+
+
+def test_gyroradius_on_grid_independent_of_ctilde():
+    """Positions lie on a circle of radius r_g sqrt(1 + (Omega_eff dt/2)^2) (leapfrog chord
+    geometry) with r_g = c u_perp / (q B/(m c) c)... = c u_perp/(qomc B), the same for every
+    c_tilde when dt scales as 1/c_tilde (Sec. 2: gyro radius on the grid independent of c_tilde)."""
+    n = 16
+    E, B = _uniform_fields(n)
+    c, qomc = 1000.0, 4000.0
+    u0 = np.array([[0.0], [10.0], [0.0]])
+    gamma = math.sqrt(101.0)
+    radii = []
+    for ratio in (1.0, 3.0, 10.0, 100.0):
+        p = _uniform_params(n, "cic", ratio, dt=0.03 / (c / ratio))
+        xs, _ = _run_single(np.array([[8.0], [8.0], [8.0]]), u0, E, B, p, 400)
+        R, r_each = _circle_radius(xs[:, 1], xs[:, 2])
+        assert np.max(np.abs(r_each - R)) < 1e-11 * R
+        a = 0.5 * (p.c_tilde / c) * qomc / gamma * p.dt
+        want = c * 10.0 / qomc * math.sqrt(1.0 + a * a)
+        assert R == pytest.approx(want, rel=1e-12)
+        radii.append(R)
+    assert max(radii) - min(radii) < 1e-12 * radii[0]
+
+
+def test_momentum_magnitude_conserved_in_pure_B():
+    """|u| is conserved in a pure magnetic field: B does no work (Eq. (1)); the Boris rotation
+    preserves the norm."""
+    w = make_workload(1, n=8, ppc=4, nsteps=200)
+    p = oracle_params(w)
+    E, B = oracle_fields(w)
+    x, u = w.x, w.u
+    n0 = np.linalg.norm(u, axis=0)
+    for _ in range(200):
+        x, u, _, _ = oracle.step(x, u, E, B, p)
+    assert np.max(np.abs(np.linalg.norm(u, axis=0) - n0) / n0) < 1e-14
+
+
+# ---------------------------------------------------------------- E x B drift (Sec. 2, E = -(u/c) x B)
+
+def _unwrapped(xs, box):
+    d = np.diff(xs, axis=0)
+    d -= box * np.round(d / box)
+    return xs[0] + np.concatenate([np.zeros((1, 3)), np.cumsum(d, axis=0)])
+
+
+@pytest.mark.parametrize("ratio", [1.0, 10.0, 100.0])
+def test_exb_drift_on_grid(ratio):
+    """A packet at rest in the frame moving with the gas drifts across the grid at
+    (c_tilde/c) u_gas_perp: the frozen-in E x B velocity is the gas velocity, and the RSOL
+    slows every CR advection by c_tilde/c (Sec. 2, v_eff = (c_tilde/c) v)."""
+    n, U, c = 8, 1.0, 1000.0
+    E, B = _uniform_fields(n, B=(1.0, 0.0, 0.0), u_gas=(0.0, U, 0.0))
+    beta_e = U / c
+    u0 = np.array([[0.0], [beta_e / math.sqrt(1 - beta_e ** 2)], [0.0]])
+    p = _uniform_params(n, "cic", ratio, dt=0.3 / (c / ratio))
+    xs, _ = _run_single(np.array([[4.0], [4.0], [4.0]]), u0, E, B, p, 200)
+    xu = _unwrapped(xs, np.array([n, n, n], float))
+    v = (xu[-1] - xu[0]) / (200 * p.dt)
+    assert v[1] == pytest.approx((p.c_tilde / c) * U, rel=1e-6)
+    assert abs(v[0]) < 1e-12 and abs(v[2]) < 1e-6 * (p.c_tilde / c) * U
+
+
+def test_exb_drift_of_gyrating_guiding_centre():
+    """A gyrating p = 10 packet's guiding centre R = x + (c/qomc)(u - gamma u_gas/c) x B / B^2
+    drifts at (c_tilde/c) u_gas_perp; the relativistic Boris scheme reaches that value at
+    second order in dt (its E x B error for gyrating relativistic packets is O(dt^2))."""
+    n, U, c, qomc, ratio = 16, 1.0, 1000.0, 4000.0, 10.0
+    E, B = _uniform_fields(n, B=(1.0, 0.0, 0.0), u_gas=(0.0, U, 0.0))
+    errs = []
+    for f in (1, 2):
+        u0 = np.array([[2.0], [6.0], [7.7]])
+        p = _uniform_params(n, "cic", ratio, dt=0.3 / (c / ratio) / f)
+        xs, us = _run_single(np.array([[8.0], [8.0], [8.0]]), u0, E, B, p, 4000 * f)
+        xu = _unwrapped(xs, np.array([n, n, n], float))
+        g = np.sqrt(1.0 + np.sum(us * us, axis=1))
+        # u is staggered half a step behind x; average the two neighbouring half steps
+        um = 0.5 * (us[:-1] + us[1:])
+        gm = 0.5 * (g[:-1] + g[1:])
+        w = um - gm[:, None] * np.array([0.0, U, 0.0])[None, :] / c
+        R = xu[:-1] + (c / qomc) * np.cross(w, np.array([1.0, 0.0, 0.0]))
+        # least-squares slope over ~75 gyro periods averages out the residual gyro wobble of R
+        t = np.arange(len(R)) * p.dt
+        vy = np.polyfit(t, R[:, 1], 1)[0]
+        vz = np.polyfit(t, R[:, 2], 1)[0]
+        want = (p.c_tilde / c) * U
+        assert abs(vz) < 1e-4 * want
+        errs.append(vy / want - 1.0)
+    assert abs(errs[1]) < 3e-5
+    assert 3.0 < errs[0] / errs[1] < 6.0, errs
+
+
+# ---------------------------------------------------------------- integrator vs continuous equations
+
+def _analytic_field(x, c):
+    """Three transverse modes along x (period 64) on B0 = x-hat; u_gas = -dB, E = -(u/c) x B."""
+    ks = 2 * np.pi * np.array([1, 2, 3]) / 64.0
+    amp = np.array([0.2, 0.1, 0.05])
+    ph = np.array([0.3, 1.7, 4.0])
+    psi = np.array([0.5, 2.0, 3.1])
+    dB = np.zeros(3)
+    for k, a, f, s in zip(ks, amp, ph, psi):
+        prof = a * math.cos(k * x[0] + f)
+        dB[1] += math.cos(s) * prof
+        dB[2] += math.sin(s) * prof
+    Bv = np.array([1.0, 0.0, 0.0]) + dB
+    E = oracle.electric_field((-dB)[:, None], Bv[:, None], c)[:, 0]
+    return E, Bv
+
+
+def test_second_order_convergence_to_continuous_rsol_equations():
+    """Kick + drift converge at second order to the continuous packet equations of Sec. 2:
+    dx/dt = c_tilde u/gamma and d(u)/dt = (c_tilde/c)(q/(m c))[E + beta x B] (Eq. (11)),
+    solved independently by scipy's DOP853 at tight tolerance."""
+    c, qomc, ratio = 1000.0, 4000.0, 10.0
+    ct = c / ratio
+
+    def rhs(t, y):
+        x, u = y[:3], y[3:]
+        g = math.sqrt(1.0 + u @ u)
+        E, Bv = _analytic_field(x, c)
+        return np.concatenate([ct * u / g, (ct / c) * qomc * (E + np.cross(u / g, Bv))])
+
+    x0 = np.array([10.0, 3.0, 2.0])
+    u0 = np.array([5.0, 7.0, -4.0])
+    T = 0.3
+    ref = solve_ivp(rhs, (0.0, T), np.concatenate([x0, u0]), method="DOP853", rtol=1e-13, atol=1e-12)
+    xT = ref.y[:3, -1]
+    errs = []
+    p = oracle.Params(64, 64, 64, 1.0, "cic", c, ct, qomc, 0.0, 1.0)
+    for nsteps in (200, 400, 800):
+        dt = T / nsteps
+        p.dt = dt
+        back = solve_ivp(rhs, (0.0, -0.5 * dt), np.concatenate([x0, u0]), method="DOP853", rtol=1e-13, atol=1e-12)
+        x = x0[:, None].copy()
+        u = back.y[3:, -1][:, None].copy()
+        h = 0.5 * (ct / c) * qomc * dt
+        for _ in range(nsteps):
+            E, Bv = _analytic_field(x[:, 0], c)
+            u = oracle.boris_kick(u, E[:, None], Bv[:, None], h)
+            x = oracle.drift(x, u, p)
+        d = x[:, 0] - xT
+        d -= 64.0 * np.round(d / 64.0)
+        errs.append(np.linalg.norm(d))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.7 < r1 < 4.3 and 3.7 < r2 < 4.3, errs
+
+
+# ---------------------------------------------------------------- c_tilde scaling laws (Secs. 2, 3)
+
+def _run_ratio(ratio, nsteps=30):
+    w = make_workload(2, n=8, ppc=2, ratio=ratio)
+    p = oracle_params(w)
+    E, B = oracle_fields(w)
+    r = oracle.rollout(w.x, w.u, E, B, p, nsteps)
+    return w, p, r
+
+
+def test_step_space_invariance_under_ctilde():
+    """The RSOL is a rescaling of time only (Sec. 2 after Eq. (3); Sec. 3 closing paragraph):
+    with static fields and dt ~ 1/c_tilde the per-step maps depend on c_tilde dt alone, so
+    states, and the exchange times c_tilde/c, are the same for every c_tilde."""
+    base = None
+    for ratio in (1.0, 3.0, 10.0, 30.0, 100.0):
+        w, p, r = _run_ratio(ratio)
+        got = (r["x"], r["u"], r["dM"] * (p.c_tilde / p.c), r["dE"] * (p.c_tilde / p.c), p.c_tilde * p.dt)
+        if base is None:
+            base = got
+            continue
+        assert np.max(np.abs(got[0] - base[0])) < 1e-11
+        assert np.max(np.abs(got[1] - base[1]) / np.linalg.norm(base[1], axis=0)) < 1e-12
+        assert np.max(np.abs(got[2] - base[2])) < 1e-10 * np.max(np.abs(base[2]))
+        assert got[4] == pytest.approx(base[4], rel=1e-14)
+
+
+def test_exchange_pinned_by_action_reaction_and_rate_invariance():
+    """(a) At c_tilde = c the gas receives exactly minus the CR momentum change (textbook
+    action-reaction, Sec. 2 before Eq. (12)); (b) the exchange RATE dM/dt is independent of
+    c_tilde (Sec. 2: the force on the gas is the c_tilde = c one; Sec. 5, point (4)).
+    Together these fix the c/c_tilde factor of Eq. (12)."""
+    rates = []
+    for ratio in (1.0, 10.0, 100.0):
+        w = make_workload(2, n=8, ppc=2, ratio=ratio)
+        p = oracle_params(w)
+        E, B = oracle_fields(w)
+        x1, u1, dM, dE = oracle.step(w.x, w.u, E, B, p)
+        if ratio == 1.0:
+            gas = dM.sum(axis=1) * p.volume
+            cr = p.mass * p.c * (u1 - w.u).sum(axis=1)
+            scale = p.mass * p.c * np.abs(u1 - w.u).sum()
+            assert np.max(np.abs(gas + cr)) < 1e-13 * scale
+        rates.append(dM / p.dt)
+    for r in rates[1:]:
+        assert np.max(np.abs(r - rates[0])) < 1e-10 * np.max(np.abs(rates[0]))
+
+
+def test_conserved_momentum_and_energy_with_rsol():
+    """rho u + (c/c_tilde) P is conserved by the exchange (Sec. 2 closing discussion), and
+    likewise the energy with the packet energy M c^2 gamma (Eq. (9))."""
+    w = make_workload(2, n=8, ppc=4, ratio=30.0)
+    p = oracle_params(w)
+    E, B = oracle_fields(w)
+    x1, u1, dM, dE = oracle.step(w.x, w.u, E, B, p)
+    k = p.c / p.c_tilde
+    dP = p.mass * p.c * (u1 - w.u)
+    g0 = np.sqrt(1 + np.sum(w.u ** 2, axis=0))
+    g1 = np.sqrt(1 + np.sum(u1 ** 2, axis=0))
+    dEn = p.mass * p.c ** 2 * (g1 - g0)
+    # rounding bounds: the test differences the states itself, so each packet term carries
+    # an error of a few ulps of M c |u| (momentum) or M c^2 gamma (energy)
+    for comp in range(3):
+        res = math.fsum(dM[comp] * p.volume) + k * math.fsum(dP[comp])
+        assert abs(res) <= 40 * 2 ** -53 * k * p.mass * p.c * (np.abs(w.u[comp]).sum() + np.abs(u1[comp]).sum())
+    res = math.fsum(dE * p.volume) + k * math.fsum(dEn)
+    assert abs(res) <= 40 * 2 ** -53 * k * p.mass * p.c ** 2 * (g0.sum() + g1.sum())
+
+
+# ---------------------------------------------------------------- timestep (Sec. 4)
+
+def test_courant_dt_scaling_and_guarantees():
+    """Every CR timestep limit rescales by c/c_tilde (Secs. 2 and 4): dt(c_tilde) c_tilde is
+    constant; with that dt no packet moves more than C cells per step and no momentum
+    rotates by more than 2 atan(C/2) per step."""
+    prods = []
+    for ratio in (1.0, 10.0, 30.0):
+        w = make_workload(2, n=8, ppc=4, ratio=ratio)
+        p = oracle_params(w)
+        prods.append(p.dt * p.c_tilde)
+        E, B = oracle_fields(w)
+        x1, u1, _, _ = oracle.step(w.x, w.u, E, B, p)
+        d = np.abs(x1 - w.x)
+        d = np.minimum(d, 8.0 - d)
+        assert np.max(d) <= w.courant * w.dx * (1 + 1e-12)
+    assert max(prods) == pytest.approx(min(prods), rel=1e-14)
+    w = make_workload(1, n=8, ppc=4)
+    p = oracle_params(w)
+    E, B = oracle_fields(w)
+    _, u1, _, _ = oracle.step(w.x, w.u, E, B, p)
+    cosang = np.sum(u1[1:] * w.u[1:], axis=0) / (np.linalg.norm(u1[1:], axis=0) * np.linalg.norm(w.u[1:], axis=0))
+    assert np.max(np.arccos(np.clip(cosang, -1, 1))) <= 2 * math.atan(w.courant / 2) + 1e-9
+
+
+# ---------------------------------------------------------------- moments (Sec. 2 packet totals)
+
+@pytest.mark.parametrize("shape", ["cic", "tsc"])
+def test_moment_totals_and_single_packet(shape):
+    """Grid totals equal the packet totals N M, sum M c u, sum M c^2 gamma (partition of
+    unity), and one packet at a cell centre puts (3/4)^3 (TSC) or 1 (CIC) of its mass there."""
+    n = 8
+    rng = np.random.default_rng(5)
+    x = rng.uniform(0, n, (3, 300))
+    u = rng.standard_normal((3, 300)) * 5
+    p = _uniform_params(n, shape, 10.0, mass=0.37)
+    rho, P, e = oracle.moments(x, u, p)
+    g = np.sqrt(1 + np.sum(u * u, axis=0))
+    assert rho.sum() == pytest.approx(300 * 0.37, rel=1e-13)
+    assert np.allclose(P.sum(axis=1), 0.37 * 1000.0 * u.sum(axis=1), rtol=1e-12, atol=1e-9)
+    assert e.sum() == pytest.approx(0.37 * 1e6 * g.sum(), rel=1e-13)
+    rho1, _, _ = oracle.moments(np.array([[3.5], [4.5], [5.5]]), np.zeros((3, 1)), p)
+    home = 3 + n * (4 + n * 5)
+    assert rho1[home] == pytest.approx(0.37 * (0.75 ** 3 if shape == "tsc" else 1.0), rel=1e-15)
+
+
+# ---------------------------------------------------------------- reference gradients
+
+def test_complex_step_gradient_matches_central_difference_and_full_rerun():
+    """The structured complex-step gradient agrees with (a) an unstructured complex step of the
+    whole rollout and (b) the exact-summation central difference, on a small case."""
+    w = make_workload(5, n=4, ppc=2, nsteps=6)
+    p = oracle_params(w)
+    E, B = oracle_fields(w)
+    coords = [("E", 1, 5), ("B", 2, 17), ("u", 0, 3), ("u", 2, 60), ("B", 1, 40)]
+    cells = [c for k, _, c in coords if k != "u"]
+    touch = adjoint.packets_touching(w.x, w.u, E, B, p, 6, cells)
+    g_cs, L0 = adjoint.complex_step_grad(w.x, w.u, E, B, p, 6, w.target.reshape(3, -1), coords, touch)
+    g_fd = adjoint.central_fd_grad(w.x, w.u, E, B, p, 6, w.target.reshape(3, -1), coords, touch)
+    h = 1e-30
+    for (kind, comp, where), gc, gf in zip(coords, g_cs, g_fd):
+        Ec, Bc, uc = E.astype(complex), B.astype(complex), w.u.astype(complex)
+        {"E": Ec, "B": Bc, "u": uc}[kind][comp, where] += 1j * h
+        P = adjoint.final_momentum_density(w.x.astype(complex), uc, Ec, Bc, p, 6)
+        full = np.imag(adjoint.momentum_loss(P, w.target.reshape(3, -1))) / h
+        assert gc == pytest.approx(full, rel=1e-9, abs=1e-14 * abs(L0))
+        assert gf == pytest.approx(gc, rel=1e-5, abs=1e-9 * abs(L0))
