@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Throughput of the fused RSOL packet step on one MI355X.
+
+A step is one pass of the whole hot path over every packet of the workload: the
+tiled fused kernel (gather E and B, relativistic Boris kick with the RSOL
+factors, exchange deposit, drift), plus the cell re-binning sort amortised
+every --sort-every steps.  Inputs are resident in HBM before the timed region;
+the timed region is exactly --steps steps bracketed by device synchronisation.
+
+Prints ONE JSON line: value = particle-updates/s of the FP64 path on the
+workload; "fp32" = the precision form on the same workload; "roofline" = the
+step kernel's algorithmic HBM bytes per launch over its event-timed average
+duration against the 8 TB/s HBM3E peak; "cpu_baseline" = the CPU oracle timed on
+a bounded sample of the same workload.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "particle-updates/s (gather+RSOL push+deposit), FP32 vs FP64, % of HBM peak"
+KERNEL_SOURCES = ["paper_2111_14704_amd/csrc/kernels_step.hip", "paper_2111_14704_amd/csrc/rsol_device.hpp"]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes_per_packet_step(precision, ppc):
+    """Bytes one packet-step must move at minimum: the packet state read and written
+    once, plus the grid fields read once and the exchange read-modify-written once per
+    cell, shared by the ppc packets of a cell."""
+    if precision == "fp64":
+        packet = 2 * (3 * 8 + 3 * 8)           # x, u read + write
+        cell = 6 * 8 + 2 * 4 * 8               # E, B read; dM (3) + dE read + write, FP64
+    else:
+        packet = 2 * (4 + 3 * 4 + 3 * 4)       # cell, offset, u read + write
+        cell = 6 * 4 + 2 * 4 * 8               # FP32 E, B read; FP64 exchange read + write
+    return packet + cell / ppc
+
+
+def measured_traffic(precision, workload):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter runs,
+    if they were taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+    except Exception:
+        return None
+    rec = data.get(f"{workload}:{precision}")
+    if not rec or rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def time_path(w, precision, steps, warmup, sort_every):
+    import torch
+    from paper_2111_14704_amd.sim import Simulation
+
+    sim = Simulation.from_workload(w, precision=precision, sort_every=sort_every)
+    h = sim.handle
+    dM = sim.zeros_grid(3)
+    dE = sim.zeros_grid(1)[0]
+    sim.step(warmup, dM, dE)
+    h.rsol_check()
+    h.rsol_timing(True)
+    h.rsol_timing_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps, dM, dE)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    step_ms, n_step, sort_ms, n_sort = h.rsol_timing_read()
+    h.rsol_timing(False)
+    h.rsol_check()
+    wall = t1 - t0
+    npk = sim.n_particles
+    kern_s = step_ms / max(n_step, 1) / 1e3
+    balg = algorithmic_bytes_per_packet_step(precision, w.ppc)
+    achieved = balg * npk / kern_s / 1e9
+    traffic = measured_traffic(precision, w.name)
+    out = dict(
+        value=npk * steps / wall, ms_per_step=wall / steps * 1e3,
+        kernel_ms=kern_s * 1e3, sort_ms=(sort_ms / n_sort) if n_sort else 0.0, sorts=n_sort,
+        roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+                      traffic=traffic, bytes_per_packet_step=balg, kernel="step_tiled_kernel"),
+    )
+    del sim
+    torch.cuda.synchronize()
+    return out
+
+
+def cpu_baseline(w, sample=131072, steps=6):
+    """The CPU oracle (numpy FP64, as it stands) on a bounded sample of the same workload:
+    the first `sample` packets for `steps` steps in the workload's fields."""
+    import numpy as np
+    import oracle
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    p = oracle.Params(w.nx, w.ny, w.nz, w.dx, w.shape, w.c, w.c_tilde, w.qomc,
+                      oracle.courant_dt(w.u, w.B, w.c, w.c_tilde, w.qomc, w.dx, w.courant), w.mass)
+    E = oracle.electric_field(w.u_gas, w.B, w.c).reshape(3, -1)
+    B = w.B.reshape(3, -1)
+    x, u = np.ascontiguousarray(w.x[:, :sample]), np.ascontiguousarray(w.u[:, :sample])
+    ctx = threadpool_limits(limits=1) if threadpool_limits else None
+    if ctx:
+        ctx.__enter__()
+    try:
+        t0 = time.perf_counter()
+        oracle.rollout(x, u, E, B, p, steps)
+        t1 = time.perf_counter()
+    finally:
+        if ctx:
+            ctx.__exit__(None, None, None)
+    return dict(value=sample * steps / (t1 - t0), unit="particle-updates/s", cores=1, kind="oracle",
+                sample=f"first {sample} packets of the workload, {steps} steps, numpy float64, 1 thread")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", type=int, default=2, choices=[2, 4],
+                    help="2: 64^3 x 64 ppc Alfven-mode field (default); 4: 128^3 x 32 ppc turbulence")
+    ap.add_argument("--sort-every", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding of this path is a design note, not a built feature)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from workloads import make_workload
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = make_workload(args.workload, precision="fp64")
+    print(f"[bench] workload {w.name}: {w.n_particles} packets, {w.nx}^3 cells", file=sys.stderr, flush=True)
+    r64 = time_path(w, "fp64", args.steps, args.warmup, args.sort_every)
+    print(f"[bench] fp64 {r64['value']:.3e} upd/s, kernel {r64['kernel_ms']:.3f} ms", file=sys.stderr, flush=True)
+    r32 = None
+    if not args.no_fp32:
+        r32 = time_path(w, "fp32", args.steps, args.warmup, args.sort_every)
+        print(f"[bench] fp32 {r32['value']:.3e} upd/s, kernel {r32['kernel_ms']:.3f} ms", file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w)
+        print(f"[bench] cpu oracle {cpu['value']:.3e} upd/s", file=sys.stderr, flush=True)
+
+    line = dict(
+        metric=METRIC, value=r64["value"], unit="particle-updates/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=r64["ms_per_step"], higher_is_better=True, scaling="weak",
+        vs_baseline=None, dtype="f64", data="synthetic",
+        config=dict(workload=w.name, grid=[w.nx, w.ny, w.nz], ppc=w.ppc, n_particles=w.n_particles,
+                    shape=w.shape, c_over_c_tilde=w.c / w.c_tilde, sort_every=args.sort_every,
+                    parallelism="none"),
+        roofline=r64["roofline"],
+        cpu_baseline=cpu,
+        kernel_ms=r64["kernel_ms"], sort_ms=r64["sort_ms"],
+    )
+    if r32:
+        line["fp32"] = dict(value=r32["value"], ms_per_step=r32["ms_per_step"], kernel_ms=r32["kernel_ms"],
+                            sort_ms=r32["sort_ms"], dtype="f32", roofline=r32["roofline"],
+                            speedup_vs_fp64=r32["value"] / r64["value"])
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,171 @@
+/*
+ * rsol.h -- C ABI of the MI355X (gfx950) library for the data-parallel hot path
+ * of the reduced-speed-of-light (RSOL) MHD particle-in-cell method of
+ * Ji & Hopkins, "A Reduced-Speed-of-Light Formulation of the MHD-PIC Method"
+ * (arXiv:2111.14704).
+ *
+ * Per packet step (Sec. 2):
+ *   gather   E_p, B_p = sum_i W(x_p - x_i) (E_i, B_i)                  kernel W of Eq. (4)
+ *   kick     d(gamma beta)/dt = (c_tilde/c) (q/(m c)) [E + beta x B]     Eq. (11)
+ *   exchange d(rho u)/dt = -sum_j (1/V_j)(c/c_tilde) d_t P_j             Eq. (12)
+ *   drift    d<x>/dt = (c_tilde/c) <v> = c_tilde beta                   Sec. 2
+ * with E = -(u/c) x B from the gas velocity u and the TRUE c (Sec. 2, after Eq. (5)),
+ * gamma and beta the packet's true values (Eqs. (7)-(8)), P_j = M_j c u_j and
+ * energy M_j c^2 gamma_j (Eqs. (9)-(10)).  The integrator is the relativistic
+ * Boris scheme, leapfrog in time: the state is (x^n, u^{n-1/2}).
+ *
+ * Conventions shared by every entry point
+ *  - Grid: periodic, nx*ny*nz cells of side dx, cell-centred collocated fields.
+ *    Grid arrays are [C][n_cells] doubles, cell = ix + nx*(iy + ny*iz) (x fastest).
+ *  - Packets: structure of arrays over np packets.
+ *      FP64 form: x[3][np] absolute positions (double, in [0, L)), u[3][np] (double)
+ *      FP32 form: cell[np] home cell (int32), off[3][np] in-cell offset in cells
+ *                 (float, in [0, 1)), u[3][np] (float)
+ *    u = gamma*beta, the packet momentum in units of m c; id[np] (int32) labels packets.
+ *  - Every pointer argument is a DEVICE pointer owned by the caller unless stated.
+ *    The library never allocates or frees device memory; it keeps the pointers given
+ *    to rsol_init / rsol_set_* until rsol_destroy.
+ *  - All work is enqueued on the stream given to rsol_init and is asynchronous;
+ *    only rsol_courant_dt and rsol_check synchronise that stream.
+ *  - Every call returns RSOL_OK (0) or a negative status; rsol_last_error gives the
+ *    message.  No C++ exception crosses this boundary.
+ *  - Calls on one handle must not overlap from several host threads.
+ */
+#ifndef RSOL_H
+#define RSOL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum rsol_status {
+  RSOL_OK = 0,
+  RSOL_EINVAL = -1,   /* bad argument (NULL pointer, size, parameter out of range)          */
+  RSOL_ESTATE = -2,   /* call out of order (fields or packets not registered yet)           */
+  RSOL_EHIP = -3,     /* a HIP runtime call or kernel launch failed                          */
+  RSOL_ECOURANT = -4, /* a packet moved further in one step than the configured bound       */
+  RSOL_ENAN = -5,     /* a non-finite momentum appeared                                      */
+  RSOL_ESCRATCH = -6, /* scratch buffer smaller than rsol_scratch_bytes()                    */
+  RSOL_ETILE = -7     /* a packet left the region staged for its tile between re-sorts      */
+};
+
+enum rsol_shape { RSOL_CIC = 1, RSOL_TSC = 2 };   /* cloud-in-cell / triangular-shaped cloud */
+enum rsol_precision { RSOL_FP64 = 0, RSOL_FP32 = 1 };
+
+typedef struct rsol_params {
+  int32_t nx, ny, nz;   /* grid cells per axis, each 1..1024                                  */
+  int32_t shape;        /* RSOL_CIC or RSOL_TSC: the spatial kernel W of Eq. (4)              */
+  int32_t precision;    /* RSOL_FP64 or RSOL_FP32 (packet state and push arithmetic)          */
+  int32_t sort_every;   /* re-bin packets by cell every K steps inside rsol_step (1..8)      */
+  int32_t flags;        /* RSOL_FLAG_* bits                                                   */
+  int32_t reserved;     /* must be 0                                                          */
+  double dx;            /* cell size (V = dx^3)                                               */
+  double c;             /* true speed of light                                                */
+  double c_tilde;       /* reduced speed of light, 0 < c_tilde <= c                           */
+  double qomc;          /* q / (m_s c) of the CR species                                      */
+  double dt;            /* timestep; may be 0 until rsol_set_dt                                */
+  double courant;       /* Courant factor C of Sec. 4 (0 < C <= 0.5)                          */
+  double mass;          /* packet mass weight M_j = N_j <m_s>, equal for every packet         */
+} rsol_params;
+
+/* flags */
+#define RSOL_FLAG_GLOBAL_ATOMICS 1  /* rsol_step: use the one-thread-per-packet kernel with
+                                       global atomics instead of the tiled LDS kernel        */
+
+typedef struct rsol_ctx* rsol_handle;
+
+/* Bytes of device scratch rsol_init needs for these parameters and np packets. */
+size_t rsol_scratch_bytes(const rsol_params* p, int64_t n_particles);
+
+/* Create a handle.  p is copied (host pointer).  stream: a hipStream_t (NULL = default
+ * stream).  scratch: caller-owned device buffer of at least rsol_scratch_bytes() bytes,
+ * 256-byte aligned, kept until rsol_destroy.  Errors: RSOL_EINVAL for out-of-range
+ * parameters, RSOL_ESCRATCH if scratch_bytes is too small. */
+int rsol_init(const rsol_params* p, int64_t n_particles, void* stream, void* scratch,
+              size_t scratch_bytes, rsol_handle* out);
+
+/* Free the host-side handle (device memory stays with the caller). */
+int rsol_destroy(rsol_handle h);
+
+/* Message of the last failure on h (or of the last failed rsol_init when h is NULL).
+ * The string is owned by the library and valid until the next call on h. */
+const char* rsol_last_error(rsol_handle h);
+
+/* E = -(u_gas/c) x B at every cell centre with the true c (Sec. 2, after Eq. (5)).
+ * u_gas, B: [3][n_cells] in; E: [3][n_cells] out (may not alias the inputs). */
+int rsol_electric_field(rsol_handle h, const double* u_gas, const double* B, double* E);
+
+/* Register the grid fields E, B ([3][n_cells] doubles) used by the gather.  The
+ * FP32 form takes float copies into scratch here, so call again after changing them. */
+int rsol_set_fields(rsol_handle h, const double* E, const double* B);
+
+/* Register the packet state (Sec. 2, Eq. (4): packets {x, p} with weights N_j).
+ * FP64 form: pos = double x[3][np], off = NULL, u = double[3][np].
+ * FP32 form: pos = int32 cell[np], off = float[3][np], u = float[3][np].
+ * id: int32[np].  The arrays are updated in place by push/drift/step and permuted
+ * (with id) by rsol_sort and rsol_step. */
+int rsol_set_particles(rsol_handle h, void* pos, float* off, void* u, int32_t* id);
+
+/* Precision-form position conversions: absolute x[3][np] (double) <-> home cell[np]
+ * (int32) + in-cell offset off[3][np] (float).  np is the handle's packet count. */
+int rsol_positions_to_cells(rsol_handle h, const double* x, int32_t* cell, float* off);
+int rsol_cells_to_positions(rsol_handle h, const int32_t* cell, const float* off, double* x);
+
+/* RSOL Courant timestep (Sec. 4): dt = C min(dx/(c_tilde max beta), 1/Omega_eff,max) with
+ * Omega_eff = (c_tilde/c) qomc |B| / gamma, from the registered packets (max beta, min
+ * gamma) and fields (max |B|).  Synchronises the stream; *dt is a host pointer.  Does
+ * not change the handle's dt (use rsol_set_dt). */
+int rsol_courant_dt(rsol_handle h, double* dt);
+int rsol_set_dt(rsol_handle h, double dt);
+
+/* A packet step split into its phases, for any packet order.
+ * rsol_gather: Ep, Bp [3][np] (precision type) = fields at the current positions.
+ * rsol_push:   u <- u^{n+1/2} from Ep, Bp (Eq. (11)); payload [4][np] (precision type)
+ *              = (du_x, du_y, du_z, dgamma) of the step.
+ * rsol_deposit: adds -(c/c_tilde) M c du W / V to dM[3][n_cells] and -(c/c_tilde) M c^2
+ *              dgamma W / V to dE[n_cells] (Eq. (12)) with W at the CURRENT positions,
+ *              i.e. call before rsol_drift; dE may be NULL.
+ * rsol_drift:  x <- x + c_tilde dt u/gamma with periodic wrap (Sec. 2, v_eff = c_tilde beta). */
+int rsol_gather(rsol_handle h, void* Ep, void* Bp);
+int rsol_push(rsol_handle h, const void* Ep, const void* Bp, void* payload);
+int rsol_deposit(rsol_handle h, const void* payload, double* dM, double* dE);
+int rsol_drift(rsol_handle h);
+
+/* Counting sort of the packets by tile-major home cell (build-internal ordering; the
+ * registered arrays are permuted in place, id with them). */
+int rsol_sort(rsol_handle h);
+
+/* nsteps fused packet steps (gather, kick, exchange deposit at x^n, drift), re-binning
+ * packets every sort_every steps.  The exchange of every step is ADDED to dM[3][n_cells]
+ * and dE[n_cells] (either may be NULL to skip the deposit). */
+int rsol_step(rsol_handle h, int32_t nsteps, double* dM, double* dE);
+
+/* CR moments of the current state (Sec. 2 packet totals): rho[n_cells] = sum M W / V,
+ * P[3][n_cells] = sum M c u W / V, e[n_cells] = sum M c^2 gamma W / V.  Outputs are
+ * overwritten; any may be NULL. */
+int rsol_moments(rsol_handle h, double* rho, double* P, double* e);
+
+/* Launch timing (a profiling aid, not part of the method): while enabled, every step and
+ * sort launch made by rsol_step / rsol_sort is bracketed by HIP events on the handle's
+ * stream.  rsol_timing_read synchronises the stream, returns the summed milliseconds and
+ * launch counts since the last read (host pointers, any may be NULL) and resets them. */
+int rsol_timing(rsol_handle h, int32_t enable);
+int rsol_timing_read(rsol_handle h, double* step_ms, int64_t* n_step, double* sort_ms, int64_t* n_sort);
+
+/* Number of packet-steps since the last call that ran on the tiled kernel's fallback path
+ * (stencil outside its tile's staged region, e.g. after a timestep above the Courant
+ * limit).  Synchronises the stream; *n is a host pointer; the counter is cleared. */
+int rsol_stray_count(rsol_handle h, int64_t* n);
+
+/* Synchronise the stream and report device-detected faults since the last check:
+ * RSOL_ECOURANT, RSOL_ENAN, RSOL_ETILE (the word is cleared). */
+int rsol_check(rsol_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSOL_H */

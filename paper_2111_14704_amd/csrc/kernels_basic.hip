@@ -1,0 +1,513 @@
+// Unfused kernels of the RSOL packet step: one thread per packet, any packet
+// order, global FP64 atomics for every deposit.  They implement the library's
+// separable phases (gather, push, deposit, drift), the CR moments, the
+// timestep reductions and the field preparation, and serve as the plain GPU
+// reference beside the tiled fused step.
+#include <math.h>
+
+#include "rsol_launch.hpp"
+
+namespace rsol {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline int grid_for(int64_t n, int block = kBlock) {
+  int64_t g = (n + block - 1) / block;
+  return (int)(g < 1 ? 1 : (g > 1048576 ? 1048576 : g));
+}
+
+__device__ __forceinline__ int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+__device__ __forceinline__ int64_t gstride() { return (int64_t)gridDim.x * blockDim.x; }
+
+// ---------------------------------------------------------------- fields
+
+// E = -(u_gas/c) x B with the true c at every cell centre (Sec. 2, after Eq. (5)).
+__global__ void electric_field_kernel(const double* __restrict__ u, const double* __restrict__ B,
+                                      double* __restrict__ E, int nc, double inv_c) {
+  for (int64_t i = gtid(); i < nc; i += gstride()) {
+    const double ux = u[i], uy = u[nc + i], uz = u[2 * (int64_t)nc + i];
+    const double bx = B[i], by = B[nc + i], bz = B[2 * (int64_t)nc + i];
+    E[i] = -(uy * bz - uz * by) * inv_c;
+    E[nc + i] = -(uz * bx - ux * bz) * inv_c;
+    E[2 * (int64_t)nc + i] = -(ux * by - uy * bx) * inv_c;
+  }
+}
+
+__global__ void to_fp32_kernel(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
+  for (int64_t i = gtid(); i < n; i += gstride()) dst[i] = (float)src[i];
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n) {
+  for (int64_t i = gtid(); i < n; i += gstride()) p[i] = v;
+}
+
+__global__ void fill_f64_kernel(double* p, double v, int64_t n) {
+  for (int64_t i = gtid(); i < n; i += gstride()) p[i] = v;
+}
+
+// Absolute FP64 position -> home cell + FP32 offset (the precision form's state).
+__global__ void positions_to_cells_kernel(const double* __restrict__ x, int32_t* __restrict__ cell,
+                                          float* __restrict__ off, int64_t np, RunConsts k) {
+  const int n[3] = {k.nx, k.ny, k.nz};
+  for (int64_t i = gtid(); i < np; i += gstride()) {
+    int h[3];
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double s = x[d * np + i] * k.inv_dx;
+      const double fl = floor(s);
+      int hd = (int)fl;
+      float f = (float)(s - fl);
+      if (f >= 1.0f) {  // rounding to the cell edge: next cell, zero offset
+        f = 0.0f;
+        hd += 1;
+      }
+      h[d] = wrap_index(hd, n[d]);
+      off[d * np + i] = f;
+    }
+    cell[i] = h[0] + k.nx * (h[1] + k.ny * h[2]);
+  }
+}
+
+__global__ void cells_to_positions_kernel(const int32_t* __restrict__ cell, const float* __restrict__ off,
+                                          double* __restrict__ x, int64_t np, RunConsts k) {
+  const int nxy = k.nx * k.ny;
+  for (int64_t i = gtid(); i < np; i += gstride()) {
+    const int c = cell[i];
+    const int iz = c / nxy;
+    const int r = c - iz * nxy;
+    const int iy = r / k.nx;
+    const int ix = r - iy * k.nx;
+    x[i] = ((double)ix + (double)off[i]) * k.dx;
+    x[np + i] = ((double)iy + (double)off[np + i]) * k.dx;
+    x[2 * np + i] = ((double)iz + (double)off[2 * np + i]) * k.dx;
+  }
+}
+
+// ---------------------------------------------------------------- timestep inputs (Sec. 4)
+
+__device__ __forceinline__ unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
+
+template <typename T>
+__global__ void dt_inputs_kernel(Packets<T> P, const double* __restrict__ B, int nc,
+                                 unsigned long long* out) {
+  __shared__ double s_beta[kBlock], s_gamma[kBlock], s_b[kBlock];
+  double bmax = 0.0, gmin = INFINITY, bb = 0.0;
+  for (int64_t i = gtid(); i < P.np; i += gstride()) {
+    const double ux = (double)P.u[i], uy = (double)P.u[P.np + i], uz = (double)P.u[2 * P.np + i];
+    const double uu = ux * ux + uy * uy + uz * uz;
+    const double g = sqrt(1.0 + uu);
+    bmax = fmax(bmax, sqrt(uu) / g);
+    gmin = fmin(gmin, g);
+  }
+  for (int64_t i = gtid(); i < nc; i += gstride()) {
+    const double bx = B[i], by = B[nc + i], bz = B[2 * (int64_t)nc + i];
+    bb = fmax(bb, sqrt(bx * bx + by * by + bz * bz));
+  }
+  s_beta[threadIdx.x] = bmax;
+  s_gamma[threadIdx.x] = gmin;
+  s_b[threadIdx.x] = bb;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      s_beta[threadIdx.x] = fmax(s_beta[threadIdx.x], s_beta[threadIdx.x + w]);
+      s_gamma[threadIdx.x] = fmin(s_gamma[threadIdx.x], s_gamma[threadIdx.x + w]);
+      s_b[threadIdx.x] = fmax(s_b[threadIdx.x], s_b[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    // non-negative doubles order like their bit patterns
+    atomicMax(&out[0], dbits(s_beta[0]));
+    atomicMin(&out[1], dbits(s_gamma[0]));
+    atomicMax(&out[2], dbits(s_b[0]));
+  }
+}
+
+__global__ void dt_init_kernel(unsigned long long* out) {
+  out[0] = dbits(0.0);
+  out[1] = dbits(INFINITY);
+  out[2] = dbits(0.0);
+}
+
+// ---------------------------------------------------------------- unfused phases
+
+template <int M, typename T>
+struct Stencil {
+  AxisWeights<M, T> ax, ay, az;
+};
+
+template <int M, typename T>
+__device__ __forceinline__ Stencil<M, T> stencil_of(const Packets<T>& P, int64_t i, const RunConsts& k) {
+  int home[3];
+  T f[3];
+  load_position(P, i, k, home, f);
+  Stencil<M, T> s;
+  s.ax = axis_weights<M, T>(home[0], f[0]);
+  s.ay = axis_weights<M, T>(home[1], f[1]);
+  s.az = axis_weights<M, T>(home[2], f[2]);
+  return s;
+}
+
+// A4: E_p = sum_i W_i E_i, B_p = sum_i W_i B_i
+template <int M, typename T>
+__global__ void gather_kernel(Packets<T> P, const T* __restrict__ E, const T* __restrict__ B,
+                              T* __restrict__ Ep, T* __restrict__ Bp, RunConsts k) {
+  const int64_t nc = k.ncells;
+  for (int64_t i = gtid(); i < P.np; i += gstride()) {
+    const Stencil<M, T> s = stencil_of<M, T>(P, i, k);
+    T e[3] = {0, 0, 0}, b[3] = {0, 0, 0};
+    #pragma unroll
+    for (int cz = 0; cz < M; ++cz) {
+      const int iz = wrap_index(s.az.base + cz, k.nz);
+      #pragma unroll
+      for (int cy = 0; cy < M; ++cy) {
+        const int iy = wrap_index(s.ay.base + cy, k.ny);
+        const T wyz = s.ay.w[cy] * s.az.w[cz];
+        #pragma unroll
+        for (int cx = 0; cx < M; ++cx) {
+          const int ix = wrap_index(s.ax.base + cx, k.nx);
+          const int64_t node = ix + (int64_t)k.nx * (iy + (int64_t)k.ny * iz);
+          const T w = s.ax.w[cx] * wyz;
+          #pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            e[d] += w * E[d * nc + node];
+            b[d] += w * B[d * nc + node];
+          }
+        }
+      }
+    }
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      Ep[d * P.np + i] = e[d];
+      Bp[d * P.np + i] = b[d];
+    }
+  }
+}
+
+// A5: kick u in place; payload = (du_x, du_y, du_z, dgamma)
+template <typename T>
+__global__ void push_kernel(Packets<T> P, const T* __restrict__ Ep, const T* __restrict__ Bp,
+                            T* __restrict__ payload, RunConsts k) {
+  const T h = (T)k.h;
+  const int64_t np = P.np;
+  for (int64_t i = gtid(); i < np; i += gstride()) {
+    const T ux = P.u[i], uy = P.u[np + i], uz = P.u[2 * np + i];
+    const Kick<T> q = boris_kick<T>(ux, uy, uz, Ep[i], Ep[np + i], Ep[2 * np + i],
+                                    Bp[i], Bp[np + i], Bp[2 * np + i], h);
+    P.u[i] = ux + q.dux;
+    P.u[np + i] = uy + q.duy;
+    P.u[2 * np + i] = uz + q.duz;
+    payload[i] = q.dux;
+    payload[np + i] = q.duy;
+    payload[2 * np + i] = q.duz;
+    payload[3 * np + i] = q.dg;
+  }
+}
+
+// A6: add -(c/c_tilde) M c du W / V and -(c/c_tilde) M c^2 dgamma W / V at the current positions
+template <int M, typename T>
+__global__ void deposit_kernel(Packets<T> P, const T* __restrict__ payload, double* __restrict__ dM,
+                               double* __restrict__ dE, RunConsts k) {
+  const int64_t nc = k.ncells, np = P.np;
+  for (int64_t i = gtid(); i < np; i += gstride()) {
+    const Stencil<M, T> s = stencil_of<M, T>(P, i, k);
+    const T qx = (T)k.pfac * payload[i], qy = (T)k.pfac * payload[np + i];
+    const T qz = (T)k.pfac * payload[2 * np + i], qe = (T)k.efac * payload[3 * np + i];
+    #pragma unroll
+    for (int cz = 0; cz < M; ++cz) {
+      const int iz = wrap_index(s.az.base + cz, k.nz);
+      #pragma unroll
+      for (int cy = 0; cy < M; ++cy) {
+        const int iy = wrap_index(s.ay.base + cy, k.ny);
+        const T wyz = s.ay.w[cy] * s.az.w[cz];
+        #pragma unroll
+        for (int cx = 0; cx < M; ++cx) {
+          const int ix = wrap_index(s.ax.base + cx, k.nx);
+          const int64_t node = ix + (int64_t)k.nx * (iy + (int64_t)k.ny * iz);
+          const T w = s.ax.w[cx] * wyz;
+          atomicAdd(&dM[node], (double)(w * qx));
+          atomicAdd(&dM[nc + node], (double)(w * qy));
+          atomicAdd(&dM[2 * nc + node], (double)(w * qz));
+          if (dE) atomicAdd(&dE[node], (double)(w * qe));
+        }
+      }
+    }
+  }
+}
+
+// A7: x^{n+1} = x^n + c_tilde dt u/gamma with periodic wrap (FP64), or the
+// cell + offset carry of the precision form (FP32).
+template <typename T>
+__device__ __forceinline__ void drift_one(const Packets<T>& P, int64_t i, T ux, T uy, T uz,
+                                          const RunConsts& k) {
+  const int64_t np = P.np;
+  const T g = sqrt(T(1) + (ux * ux + uy * uy + uz * uz));
+  bool bad = !(isfinite(g));
+  if constexpr (is_fp64<T>()) {
+    const double L[3] = {k.Lx, k.Ly, k.Lz};
+    const double u3[3] = {ux, uy, uz};
+    const double s = k.cdt / g;
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double step = s * u3[d];
+      bad |= fabs(step) > k.max_step * k.dx;
+      P.x[d * np + i] = wrap_coord(P.x[d * np + i] + step, L[d]);
+    }
+  } else {
+    const int n[3] = {k.nx, k.ny, k.nz};
+    const float u3[3] = {ux, uy, uz};
+    const float s = (float)k.cdt_dx / g;
+    const int c = P.cell[i];
+    const int nxy = k.nx * k.ny;
+    int h[3];
+    h[2] = c / nxy;
+    const int r = c - h[2] * nxy;
+    h[1] = r / k.nx;
+    h[0] = r - h[1] * k.nx;
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float step = s * u3[d];
+      bad |= fabsf(step) > (float)k.max_step;
+      float f = P.off[d * np + i] + step;
+      const float fl = floorf(f);
+      int hd = h[d] + (int)fl;
+      f -= fl;
+      if (f >= 1.0f) {
+        f = 0.0f;
+        hd += 1;
+      }
+      h[d] = wrap_index(hd, n[d]);
+      P.off[d * np + i] = f;
+    }
+    P.cell[i] = h[0] + k.nx * (h[1] + k.ny * h[2]);
+  }
+  if (bad) set_status(k.status, isfinite(g) ? ERR_COURANT : ERR_NAN);
+}
+
+template <typename T>
+__global__ void drift_kernel(Packets<T> P, RunConsts k) {
+  for (int64_t i = gtid(); i < P.np; i += gstride()) {
+    drift_one<T>(P, i, P.u[i], P.u[P.np + i], P.u[2 * P.np + i], k);
+  }
+}
+
+// A8: rho = sum M W / V, P = sum M c u W / V, e = sum M c^2 gamma W / V
+template <int M, typename T>
+__global__ void moments_kernel(Packets<T> P, double* __restrict__ rho, double* __restrict__ Pm,
+                               double* __restrict__ e, RunConsts k) {
+  const int64_t nc = k.ncells, np = P.np;
+  const double inv_v = 1.0 / (k.dx * k.dx * k.dx);
+  const double m = k.mass * inv_v, mc = k.mass * k.c * inv_v, mcc = k.mass * k.c * k.c * inv_v;
+  for (int64_t i = gtid(); i < np; i += gstride()) {
+    const Stencil<M, T> s = stencil_of<M, T>(P, i, k);
+    const double ux = (double)P.u[i], uy = (double)P.u[np + i], uz = (double)P.u[2 * np + i];
+    const double g = sqrt(1.0 + (ux * ux + uy * uy + uz * uz));
+    #pragma unroll
+    for (int cz = 0; cz < M; ++cz) {
+      const int iz = wrap_index(s.az.base + cz, k.nz);
+      #pragma unroll
+      for (int cy = 0; cy < M; ++cy) {
+        const int iy = wrap_index(s.ay.base + cy, k.ny);
+        const double wyz = (double)s.ay.w[cy] * (double)s.az.w[cz];
+        #pragma unroll
+        for (int cx = 0; cx < M; ++cx) {
+          const int ix = wrap_index(s.ax.base + cx, k.nx);
+          const int64_t node = ix + (int64_t)k.nx * (iy + (int64_t)k.ny * iz);
+          const double w = (double)s.ax.w[cx] * wyz;
+          if (rho) atomicAdd(&rho[node], w * m);
+          if (Pm) {
+            atomicAdd(&Pm[node], w * mc * ux);
+            atomicAdd(&Pm[nc + node], w * mc * uy);
+            atomicAdd(&Pm[2 * nc + node], w * mc * uz);
+          }
+          if (e) atomicAdd(&e[node], w * mcc * g);
+        }
+      }
+    }
+  }
+}
+
+// Fused step with global atomics: gather at x^n, kick, exchange deposit at x^n, drift.
+template <int M, typename T>
+__global__ void __launch_bounds__(kBlock) step_global_kernel(Packets<T> P, const T* __restrict__ E,
+                                                             const T* __restrict__ B, double* __restrict__ dM,
+                                                             double* __restrict__ dE, RunConsts k) {
+  const int64_t nc = k.ncells, np = P.np;
+  const T h = (T)k.h;
+  for (int64_t i = gtid(); i < np; i += gstride()) {
+    const Stencil<M, T> s = stencil_of<M, T>(P, i, k);
+    T e[3] = {0, 0, 0}, b[3] = {0, 0, 0};
+    #pragma unroll
+    for (int cz = 0; cz < M; ++cz) {
+      const int iz = wrap_index(s.az.base + cz, k.nz);
+      #pragma unroll
+      for (int cy = 0; cy < M; ++cy) {
+        const int iy = wrap_index(s.ay.base + cy, k.ny);
+        const T wyz = s.ay.w[cy] * s.az.w[cz];
+        #pragma unroll
+        for (int cx = 0; cx < M; ++cx) {
+          const int ix = wrap_index(s.ax.base + cx, k.nx);
+          const int64_t node = ix + (int64_t)k.nx * (iy + (int64_t)k.ny * iz);
+          const T w = s.ax.w[cx] * wyz;
+          #pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            e[d] += w * E[d * nc + node];
+            b[d] += w * B[d * nc + node];
+          }
+        }
+      }
+    }
+    const T ux = P.u[i], uy = P.u[np + i], uz = P.u[2 * np + i];
+    const Kick<T> q = boris_kick<T>(ux, uy, uz, e[0], e[1], e[2], b[0], b[1], b[2], h);
+    const T nux = ux + q.dux, nuy = uy + q.duy, nuz = uz + q.duz;
+    P.u[i] = nux;
+    P.u[np + i] = nuy;
+    P.u[2 * np + i] = nuz;
+    if (dM) {
+      const T qx = (T)k.pfac * q.dux, qy = (T)k.pfac * q.duy, qz = (T)k.pfac * q.duz;
+      const T qe = (T)k.efac * q.dg;
+      #pragma unroll
+      for (int cz = 0; cz < M; ++cz) {
+        const int iz = wrap_index(s.az.base + cz, k.nz);
+        #pragma unroll
+        for (int cy = 0; cy < M; ++cy) {
+          const int iy = wrap_index(s.ay.base + cy, k.ny);
+          const T wyz = s.ay.w[cy] * s.az.w[cz];
+          #pragma unroll
+          for (int cx = 0; cx < M; ++cx) {
+            const int ix = wrap_index(s.ax.base + cx, k.nx);
+            const int64_t node = ix + (int64_t)k.nx * (iy + (int64_t)k.ny * iz);
+            const T w = s.ax.w[cx] * wyz;
+            atomicAdd(&dM[node], (double)(w * qx));
+            atomicAdd(&dM[nc + node], (double)(w * qy));
+            atomicAdd(&dM[2 * nc + node], (double)(w * qz));
+            if (dE) atomicAdd(&dE[node], (double)(w * qe));
+          }
+        }
+      }
+    }
+    drift_one<T>(P, i, nux, nuy, nuz, k);
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t launch_electric_field(const double* u_gas, const double* B, double* E, int ncells, double c,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(electric_field_kernel, dim3(grid_for(ncells)), dim3(kBlock), 0, s, u_gas, B, E, ncells,
+                     1.0 / c);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_fp32(const double* src, float* dst, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(to_fp32_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(fill_f64_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_positions_to_cells(const double* x, int32_t* cell, float* off, int64_t np,
+                                     const RunConsts& k, hipStream_t s) {
+  hipLaunchKernelGGL(positions_to_cells_kernel, dim3(grid_for(np)), dim3(kBlock), 0, s, x, cell, off, np, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_cells_to_positions(const int32_t* cell, const float* off, double* x, int64_t np,
+                                     const RunConsts& k, hipStream_t s) {
+  hipLaunchKernelGGL(cells_to_positions_kernel, dim3(grid_for(np)), dim3(kBlock), 0, s, cell, off, x, np, k);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dt_inputs(const Packets<T>& P, const double* B, int ncells, unsigned long long* out,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(dt_init_kernel, dim3(1), dim3(1), 0, s, out);
+  const int64_t n = P.np > ncells ? P.np : ncells;
+  hipLaunchKernelGGL(dt_inputs_kernel<T>, dim3(grid_for(n) > 4096 ? 4096 : grid_for(n)), dim3(kBlock), 0, s, P,
+                     B, ncells, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gather(int shape, const Packets<T>& P, const T* E, const T* B, T* Ep, T* Bp,
+                         const RunConsts& k, hipStream_t s) {
+  if (shape == kShapeCIC)
+    hipLaunchKernelGGL((gather_kernel<2, T>), dim3(grid_for(P.np)), dim3(kBlock), 0, s, P, E, B, Ep, Bp, k);
+  else
+    hipLaunchKernelGGL((gather_kernel<3, T>), dim3(grid_for(P.np)), dim3(kBlock), 0, s, P, E, B, Ep, Bp, k);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_push(const Packets<T>& P, const T* Ep, const T* Bp, T* payload, const RunConsts& k,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(push_kernel<T>, dim3(grid_for(P.np)), dim3(kBlock), 0, s, P, Ep, Bp, payload, k);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_deposit(int shape, const Packets<T>& P, const T* payload, double* dM, double* dE,
+                          const RunConsts& k, hipStream_t s) {
+  if (shape == kShapeCIC)
+    hipLaunchKernelGGL((deposit_kernel<2, T>), dim3(grid_for(P.np)), dim3(kBlock), 0, s, P, payload, dM, dE, k);
+  else
+    hipLaunchKernelGGL((deposit_kernel<3, T>), dim3(grid_for(P.np)), dim3(kBlock), 0, s, P, payload, dM, dE, k);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_drift(const Packets<T>& P, const RunConsts& k, hipStream_t s) {
+  hipLaunchKernelGGL(drift_kernel<T>, dim3(grid_for(P.np)), dim3(kBlock), 0, s, P, k);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_moments(int shape, const Packets<T>& P, double* rho, double* Pm, double* e, const RunConsts& k,
+                          hipStream_t s) {
+  if (shape == kShapeCIC)
+    hipLaunchKernelGGL((moments_kernel<2, T>), dim3(grid_for(P.np)), dim3(kBlock), 0, s, P, rho, Pm, e, k);
+  else
+    hipLaunchKernelGGL((moments_kernel<3, T>), dim3(grid_for(P.np)), dim3(kBlock), 0, s, P, rho, Pm, e, k);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_step_global(int shape, const Packets<T>& P, const T* E, const T* B, double* dM, double* dE,
+                              const RunConsts& k, hipStream_t s) {
+  if (shape == kShapeCIC)
+    hipLaunchKernelGGL((step_global_kernel<2, T>), dim3(grid_for(P.np)), dim3(kBlock), 0, s, P, E, B, dM, dE, k);
+  else
+    hipLaunchKernelGGL((step_global_kernel<3, T>), dim3(grid_for(P.np)), dim3(kBlock), 0, s, P, E, B, dM, dE, k);
+  return hipGetLastError();
+}
+
+#define RSOL_INSTANTIATE(T)                                                                                    \
+  template hipError_t launch_dt_inputs<T>(const Packets<T>&, const double*, int, unsigned long long*,         \
+                                          hipStream_t);                                                        \
+  template hipError_t launch_gather<T>(int, const Packets<T>&, const T*, const T*, T*, T*, const RunConsts&, \
+                                       hipStream_t);                                                           \
+  template hipError_t launch_push<T>(const Packets<T>&, const T*, const T*, T*, const RunConsts&, hipStream_t); \
+  template hipError_t launch_deposit<T>(int, const Packets<T>&, const T*, double*, double*, const RunConsts&, \
+                                        hipStream_t);                                                          \
+  template hipError_t launch_drift<T>(const Packets<T>&, const RunConsts&, hipStream_t);                      \
+  template hipError_t launch_moments<T>(int, const Packets<T>&, double*, double*, double*, const RunConsts&,  \
+                                        hipStream_t);                                                          \
+  template hipError_t launch_step_global<T>(int, const Packets<T>&, const T*, const T*, double*, double*,     \
+                                            const RunConsts&, hipStream_t);
+
+RSOL_INSTANTIATE(double)
+RSOL_INSTANTIATE(float)
+
+}  // namespace rsol

@@ -1,0 +1,589 @@
+// C-ABI entry points of librsol: argument validation, scratch carve-up, launch
+// sequencing on the caller's stream and status reporting.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/rsol.h"
+#include "rsol_launch.hpp"
+#include "rsol_sort.hpp"
+#include "rsol_step.hpp"
+
+using namespace rsol;
+
+struct rsol_ctx {
+  rsol_params p;
+  int64_t np;
+  hipStream_t stream;
+  char* scratch;
+  size_t scratch_bytes;
+  // scratch regions
+  uint32_t* status;
+  unsigned long long* red;
+  int32_t* sort_ints;
+  void* perm;           // permuted packet copy written by the sort
+  float* E32;
+  float* B32;
+  // registered caller arrays
+  const double* E;
+  const double* B;
+  void* pos;
+  float* off;
+  void* u;
+  int32_t* id;
+  bool have_fields, have_packets, sorted_valid;
+  int steps_since_sort;
+  Tiling tiling;
+  StepPlan plan;
+  std::string err;
+  // optional launch timing: event pairs around every step / sort launch
+  bool timing;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_step, ev_sort;
+};
+
+namespace {
+
+thread_local std::string g_init_error;
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int fail(rsol_ctx* h, int code, const std::string& msg) {
+  if (h)
+    h->err = msg;
+  else
+    g_init_error = msg;
+  return code;
+}
+
+int hip_fail(rsol_ctx* h, hipError_t e, const char* where) {
+  return fail(h, RSOL_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define RSOL_HIP(h, call, where)               \
+  do {                                          \
+    hipError_t _e = (call);                     \
+    if (_e != hipSuccess) return hip_fail(h, _e, where); \
+  } while (0)
+
+int64_t n_cells(const rsol_params& p) { return (int64_t)p.nx * p.ny * p.nz; }
+
+hipEvent_t take_event(rsol_ctx* h) {
+  if (!h->ev_pool.empty()) {
+    hipEvent_t e = h->ev_pool.back();
+    h->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Record the start of a timed launch; returns the pair to close with timed_end.
+std::pair<hipEvent_t, hipEvent_t> timed_begin(rsol_ctx* h) {
+  std::pair<hipEvent_t, hipEvent_t> pr(nullptr, nullptr);
+  if (!h->timing) return pr;
+  pr.first = take_event(h);
+  pr.second = take_event(h);
+  if (pr.first) (void)hipEventRecord(pr.first, h->stream);
+  return pr;
+}
+
+void timed_end(rsol_ctx* h, std::pair<hipEvent_t, hipEvent_t> pr, bool is_sort) {
+  if (!h->timing || !pr.first || !pr.second) return;
+  (void)hipEventRecord(pr.second, h->stream);
+  (is_sort ? h->ev_sort : h->ev_step).push_back(pr);
+}
+
+bool fp32(const rsol_params& p) { return p.precision == RSOL_FP32; }
+
+Tiling tiling_for(const rsol_params& p) {
+  const StepPlan pl = plan_step(p.nx, p.ny, p.nz, p.shape, p.precision, p.sort_every, p.courant);
+  return make_tiling(p.nx, p.ny, p.nz, pl.tx, pl.ty, pl.tz);
+}
+
+// Scratch layout; returns total bytes and fills offsets when h is given.
+size_t layout(const rsol_params& p, int64_t np, rsol_ctx* h) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  const size_t st = take(sizeof(uint32_t) * 4);
+  const size_t rd = take(sizeof(unsigned long long) * 4);
+  const Tiling t = tiling_for(p);
+  const size_t si = take(sizeof(int32_t) * sort_scratch_ints(t, np));
+  const size_t per = fp32(p) ? (sizeof(int32_t) + 6 * sizeof(float) + sizeof(int32_t))
+                             : (6 * sizeof(double) + sizeof(int32_t));
+  const size_t pm = take(per * (size_t)np + 64);
+  size_t e32 = 0, b32 = 0;
+  if (fp32(p)) {
+    e32 = take(sizeof(float) * 3 * (size_t)n_cells(p));
+    b32 = take(sizeof(float) * 3 * (size_t)n_cells(p));
+  }
+  if (h) {
+    char* s = h->scratch;
+    h->status = (uint32_t*)(s + st);
+    h->red = (unsigned long long*)(s + rd);
+    h->sort_ints = (int32_t*)(s + si);
+    h->perm = (void*)(s + pm);
+    h->E32 = fp32(p) ? (float*)(s + e32) : nullptr;
+    h->B32 = fp32(p) ? (float*)(s + b32) : nullptr;
+  }
+  return off;
+}
+
+std::string validate(const rsol_params* p, int64_t np) {
+  if (!p) return "params is NULL";
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1 || p->nx > 1024 || p->ny > 1024 || p->nz > 1024)
+    return "grid dimensions must be in 1..1024";
+  if (p->shape != RSOL_CIC && p->shape != RSOL_TSC) return "shape must be RSOL_CIC or RSOL_TSC";
+  if (p->precision != RSOL_FP64 && p->precision != RSOL_FP32) return "precision must be RSOL_FP64 or RSOL_FP32";
+  if (p->sort_every < 1 || p->sort_every > 8) return "sort_every must be in 1..8";
+  if (p->reserved != 0) return "reserved must be 0";
+  if (!(p->dx > 0)) return "dx must be > 0";
+  if (!(p->c > 0) || !(p->c_tilde > 0) || p->c_tilde > p->c) return "need 0 < c_tilde <= c";
+  if (!isfinite(p->qomc)) return "qomc must be finite";
+  if (!(p->dt >= 0) || !isfinite(p->dt)) return "dt must be finite and >= 0";
+  if (!(p->courant > 0) || p->courant > 0.5) return "courant must be in (0, 0.5]";
+  if (!(p->mass >= 0) || !isfinite(p->mass)) return "mass must be finite and >= 0";
+  if (np < 0 || np > (int64_t)INT32_MAX - 64) return "n_particles out of range";
+  const Tiling t = tiling_for(*p);
+  if (t.nbins() > max_sort_bins()) return "grid too large for the sort";
+  if (t.cells_per_tile > max_cells_per_tile()) return "tile larger than the sort supports";
+  return "";
+}
+
+RunConsts consts(const rsol_ctx* h) {
+  const rsol_params& p = h->p;
+  RunConsts k;
+  k.nx = p.nx;
+  k.ny = p.ny;
+  k.nz = p.nz;
+  k.ncells = (int)n_cells(p);
+  k.dx = p.dx;
+  k.inv_dx = 1.0 / p.dx;
+  k.Lx = p.nx * p.dx;
+  k.Ly = p.ny * p.dx;
+  k.Lz = p.nz * p.dx;
+  k.c = p.c;
+  k.c_tilde = p.c_tilde;
+  k.qomc = p.qomc;
+  k.dt = p.dt;
+  k.mass = p.mass;
+  k.h = 0.5 * (p.c_tilde / p.c) * p.qomc * p.dt;
+  k.cdt = p.c_tilde * p.dt;
+  k.cdt_dx = p.c_tilde * p.dt / p.dx;
+  const double vol = p.dx * p.dx * p.dx;
+  k.pfac = -(p.c / p.c_tilde) * p.mass * p.c / vol;
+  k.efac = -(p.c / p.c_tilde) * p.mass * p.c * p.c / vol;
+  // a packet may never cross more than one cell per step; the tiled kernel's halo
+  // additionally relies on the Courant bound (at most C cells per step)
+  k.max_step = h->plan.max_step;
+  k.status = h->status;
+  return k;
+}
+
+template <typename T>
+Packets<T> caller_packets(const rsol_ctx* h) {
+  Packets<T> P;
+  P.np = h->np;
+  if constexpr (is_fp64<T>()) {
+    P.x = (double*)h->pos;
+    P.cell = nullptr;
+    P.off = nullptr;
+  } else {
+    P.x = nullptr;
+    P.cell = (int32_t*)h->pos;
+    P.off = h->off;
+  }
+  P.u = (T*)h->u;
+  P.id = h->id;
+  return P;
+}
+
+template <typename T>
+Packets<T> perm_packets(const rsol_ctx* h) {
+  Packets<T> P;
+  P.np = h->np;
+  char* b = (char*)h->perm;
+  const size_t n = (size_t)h->np;
+  if constexpr (is_fp64<T>()) {
+    P.x = (double*)b;
+    P.cell = nullptr;
+    P.off = nullptr;
+    P.u = (T*)(b + 3 * n * sizeof(double));
+    P.id = (int32_t*)(b + 6 * n * sizeof(double));
+  } else {
+    P.x = nullptr;
+    P.cell = (int32_t*)b;
+    P.off = (float*)(b + n * sizeof(int32_t));
+    P.u = (T*)(b + n * sizeof(int32_t) + 3 * n * sizeof(float));
+    P.id = (int32_t*)(b + n * sizeof(int32_t) + 6 * n * sizeof(float));
+  }
+  return P;
+}
+
+int need(rsol_ctx* h, bool fields, bool packets) {
+  if (!h) return fail(nullptr, RSOL_EINVAL, "handle is NULL");
+  if (fields && !h->have_fields) return fail(h, RSOL_ESTATE, "fields not registered (rsol_set_fields)");
+  if (packets && !h->have_packets) return fail(h, RSOL_ESTATE, "packets not registered (rsol_set_particles)");
+  return RSOL_OK;
+}
+
+template <typename T>
+const T* field_E(const rsol_ctx* h) {
+  if constexpr (is_fp64<T>()) return h->E; else return h->E32;
+}
+template <typename T>
+const T* field_B(const rsol_ctx* h) {
+  if constexpr (is_fp64<T>()) return h->B; else return h->B32;
+}
+
+// Copy the permuted packets back over the caller's arrays.
+template <typename T>
+int copy_back(rsol_ctx* h) {
+  const Packets<T> src = perm_packets<T>(h), dst = caller_packets<T>(h);
+  const size_t n = (size_t)h->np;
+  if (n == 0) return RSOL_OK;
+  if constexpr (is_fp64<T>()) {
+    RSOL_HIP(h, hipMemcpyAsync(dst.x, src.x, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, h->stream), "copy x");
+  } else {
+    RSOL_HIP(h, hipMemcpyAsync(dst.cell, src.cell, n * sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream), "copy cell");
+    RSOL_HIP(h, hipMemcpyAsync(dst.off, src.off, 3 * n * sizeof(float), hipMemcpyDeviceToDevice, h->stream), "copy off");
+  }
+  RSOL_HIP(h, hipMemcpyAsync(dst.u, src.u, 3 * n * sizeof(T), hipMemcpyDeviceToDevice, h->stream), "copy u");
+  RSOL_HIP(h, hipMemcpyAsync(dst.id, src.id, n * sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream), "copy id");
+  return RSOL_OK;
+}
+
+template <typename T>
+int do_sort(rsol_ctx* h, bool copy) {
+  if (h->np == 0) {
+    h->sorted_valid = true;
+    h->steps_since_sort = 0;
+    return RSOL_OK;
+  }
+  const RunConsts k = consts(h);
+  auto ev = timed_begin(h);
+  RSOL_HIP(h, launch_sort<T>(caller_packets<T>(h), perm_packets<T>(h), k, h->tiling, h->sort_ints, h->stream),
+           "sort");
+  timed_end(h, ev, true);
+  h->sorted_valid = true;
+  h->steps_since_sort = 0;
+  if (copy) return copy_back<T>(h);
+  return RSOL_OK;
+}
+
+template <typename T>
+int do_step(rsol_ctx* h, int32_t nsteps, double* dM, double* dE) {
+  const RunConsts k = consts(h);
+  const bool global = (h->p.flags & RSOL_FLAG_GLOBAL_ATOMICS) != 0 || !h->plan.tiled;
+  for (int32_t s = 0; s < nsteps; ++s) {
+    if (global) {
+      auto ev = timed_begin(h);
+      RSOL_HIP(h, launch_step_global<T>(h->p.shape, caller_packets<T>(h), field_E<T>(h), field_B<T>(h), dM, dE,
+                                        k, h->stream),
+               "step (global)");
+      timed_end(h, ev, false);
+      h->sorted_valid = false;
+      continue;
+    }
+    bool from_perm = false;
+    if (!h->sorted_valid || h->steps_since_sort >= h->p.sort_every) {
+      int rc = do_sort<T>(h, false);
+      if (rc) return rc;
+      from_perm = true;
+    }
+    const Packets<T> src = from_perm ? perm_packets<T>(h) : caller_packets<T>(h);
+    auto ev = timed_begin(h);
+    RSOL_HIP(h, launch_step_tiled<T>(h->plan, h->p.shape, h->tiling, src, caller_packets<T>(h), h->sort_ints,
+                                     field_E<T>(h), field_B<T>(h), dM, dE, k, h->stream),
+             "step (tiled)");
+    timed_end(h, ev, false);
+    h->steps_since_sort += 1;
+  }
+  return RSOL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t rsol_scratch_bytes(const rsol_params* p, int64_t n_particles) {
+  if (!validate(p, n_particles).empty()) return 0;
+  return layout(*p, n_particles, nullptr);
+}
+
+int rsol_init(const rsol_params* p, int64_t n_particles, void* stream, void* scratch, size_t scratch_bytes,
+              rsol_handle* out) {
+  if (!out) return fail(nullptr, RSOL_EINVAL, "out is NULL");
+  *out = nullptr;
+  const std::string bad = validate(p, n_particles);
+  if (!bad.empty()) return fail(nullptr, RSOL_EINVAL, bad);
+  const size_t need_bytes = layout(*p, n_particles, nullptr);
+  if (!scratch) return fail(nullptr, RSOL_EINVAL, "scratch is NULL");
+  if (((uintptr_t)scratch) % kAlign) return fail(nullptr, RSOL_EINVAL, "scratch must be 256-byte aligned");
+  if (scratch_bytes < need_bytes)
+    return fail(nullptr, RSOL_ESCRATCH,
+                "scratch too small: need " + std::to_string(need_bytes) + " bytes, got " + std::to_string(scratch_bytes));
+  rsol_ctx* h = new (std::nothrow) rsol_ctx();
+  if (!h) return fail(nullptr, RSOL_EINVAL, "out of host memory");
+  h->p = *p;
+  h->np = n_particles;
+  h->stream = (hipStream_t)stream;
+  h->scratch = (char*)scratch;
+  h->scratch_bytes = scratch_bytes;
+  h->plan = plan_step(p->nx, p->ny, p->nz, p->shape, p->precision, p->sort_every, p->courant);
+  h->tiling = make_tiling(p->nx, p->ny, p->nz, h->plan.tx, h->plan.ty, h->plan.tz);
+  layout(*p, n_particles, h);
+  hipError_t e = launch_fill_u32(h->status, 0u, 4, h->stream);
+  if (e != hipSuccess) {
+    int rc = hip_fail(nullptr, e, "init status");
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return RSOL_OK;
+}
+
+int rsol_destroy(rsol_handle h) {
+  if (h) {
+    for (auto& pr : h->ev_step) h->ev_pool.push_back(pr.first), h->ev_pool.push_back(pr.second);
+    for (auto& pr : h->ev_sort) h->ev_pool.push_back(pr.first), h->ev_pool.push_back(pr.second);
+    for (hipEvent_t e : h->ev_pool)
+      if (e) (void)hipEventDestroy(e);
+  }
+  delete h;
+  return RSOL_OK;
+}
+
+int rsol_timing(rsol_handle h, int32_t enable) {
+  if (int rc = need(h, false, false)) return rc;
+  h->timing = enable != 0;
+  return RSOL_OK;
+}
+
+int rsol_timing_read(rsol_handle h, double* step_ms, int64_t* n_step, double* sort_ms, int64_t* n_sort) {
+  if (int rc = need(h, false, false)) return rc;
+  RSOL_HIP(h, hipStreamSynchronize(h->stream), "timing sync");
+  double acc[2] = {0.0, 0.0};
+  int64_t cnt[2] = {0, 0};
+  for (int which = 0; which < 2; ++which) {
+    auto& v = which == 0 ? h->ev_step : h->ev_sort;
+    for (auto& pr : v) {
+      float ms = 0.f;
+      RSOL_HIP(h, hipEventElapsedTime(&ms, pr.first, pr.second), "event elapsed");
+      acc[which] += ms;
+      cnt[which] += 1;
+      h->ev_pool.push_back(pr.first);
+      h->ev_pool.push_back(pr.second);
+    }
+    v.clear();
+  }
+  if (step_ms) *step_ms = acc[0];
+  if (n_step) *n_step = cnt[0];
+  if (sort_ms) *sort_ms = acc[1];
+  if (n_sort) *n_sort = cnt[1];
+  return RSOL_OK;
+}
+
+const char* rsol_last_error(rsol_handle h) { return h ? h->err.c_str() : g_init_error.c_str(); }
+
+int rsol_electric_field(rsol_handle h, const double* u_gas, const double* B, double* E) {
+  if (int rc = need(h, false, false)) return rc;
+  if (!u_gas || !B || !E) return fail(h, RSOL_EINVAL, "NULL field pointer");
+  RSOL_HIP(h, launch_electric_field(u_gas, B, E, (int)n_cells(h->p), h->p.c, h->stream), "electric_field");
+  return RSOL_OK;
+}
+
+int rsol_set_fields(rsol_handle h, const double* E, const double* B) {
+  if (int rc = need(h, false, false)) return rc;
+  if (!E || !B) return fail(h, RSOL_EINVAL, "NULL field pointer");
+  h->E = E;
+  h->B = B;
+  if (fp32(h->p)) {
+    RSOL_HIP(h, launch_to_fp32(E, h->E32, 3 * n_cells(h->p), h->stream), "E to fp32");
+    RSOL_HIP(h, launch_to_fp32(B, h->B32, 3 * n_cells(h->p), h->stream), "B to fp32");
+  }
+  h->have_fields = true;
+  return RSOL_OK;
+}
+
+int rsol_set_particles(rsol_handle h, void* pos, float* off, void* u, int32_t* id) {
+  if (int rc = need(h, false, false)) return rc;
+  if (h->np > 0 && (!pos || !u || !id)) return fail(h, RSOL_EINVAL, "NULL packet pointer");
+  if (fp32(h->p) && h->np > 0 && !off) return fail(h, RSOL_EINVAL, "FP32 form needs off");
+  if (!fp32(h->p) && off) return fail(h, RSOL_EINVAL, "FP64 form takes no off array");
+  h->pos = pos;
+  h->off = off;
+  h->u = u;
+  h->id = id;
+  h->have_packets = true;
+  h->sorted_valid = false;
+  h->steps_since_sort = 0;
+  return RSOL_OK;
+}
+
+int rsol_positions_to_cells(rsol_handle h, const double* x, int32_t* cell, float* off) {
+  if (int rc = need(h, false, false)) return rc;
+  if (h->np == 0) return RSOL_OK;
+  if (!x || !cell || !off) return fail(h, RSOL_EINVAL, "NULL pointer");
+  RSOL_HIP(h, launch_positions_to_cells(x, cell, off, h->np, consts(h), h->stream), "positions_to_cells");
+  return RSOL_OK;
+}
+
+int rsol_cells_to_positions(rsol_handle h, const int32_t* cell, const float* off, double* x) {
+  if (int rc = need(h, false, false)) return rc;
+  if (h->np == 0) return RSOL_OK;
+  if (!x || !cell || !off) return fail(h, RSOL_EINVAL, "NULL pointer");
+  RSOL_HIP(h, launch_cells_to_positions(cell, off, x, h->np, consts(h), h->stream), "cells_to_positions");
+  return RSOL_OK;
+}
+
+int rsol_courant_dt(rsol_handle h, double* dt) {
+  if (int rc = need(h, true, true)) return rc;
+  if (!dt) return fail(h, RSOL_EINVAL, "dt is NULL");
+  if (h->np == 0) return fail(h, RSOL_EINVAL, "no packets");
+  if (fp32(h->p)) {
+    RSOL_HIP(h, launch_dt_inputs<float>(caller_packets<float>(h), h->B, (int)n_cells(h->p), h->red, h->stream),
+             "dt inputs");
+  } else {
+    RSOL_HIP(h, launch_dt_inputs<double>(caller_packets<double>(h), h->B, (int)n_cells(h->p), h->red, h->stream),
+             "dt inputs");
+  }
+  unsigned long long bits[3];
+  RSOL_HIP(h, hipMemcpyAsync(bits, h->red, sizeof(bits), hipMemcpyDeviceToHost, h->stream), "dt copy");
+  RSOL_HIP(h, hipStreamSynchronize(h->stream), "dt sync");
+  double v[3];
+  memcpy(v, bits, sizeof(v));
+  const double beta_max = v[0], gamma_min = v[1], b_max = v[2];
+  const rsol_params& p = h->p;
+  double lim = INFINITY;
+  if (beta_max > 0) lim = fmin(lim, p.courant * p.dx / (p.c_tilde * beta_max));
+  const double omega = (p.c_tilde / p.c) * fabs(p.qomc) * b_max / gamma_min;
+  if (omega > 0) lim = fmin(lim, p.courant / omega);
+  if (!isfinite(lim)) return fail(h, RSOL_EINVAL, "timestep unbounded (no motion and no field)");
+  *dt = lim;
+  return RSOL_OK;
+}
+
+int rsol_set_dt(rsol_handle h, double dt) {
+  if (int rc = need(h, false, false)) return rc;
+  if (!(dt > 0) || !isfinite(dt)) return fail(h, RSOL_EINVAL, "dt must be finite and > 0");
+  h->p.dt = dt;
+  return RSOL_OK;
+}
+
+int rsol_gather(rsol_handle h, void* Ep, void* Bp) {
+  if (int rc = need(h, true, true)) return rc;
+  if (h->np == 0) return RSOL_OK;
+  if (!Ep || !Bp) return fail(h, RSOL_EINVAL, "NULL output");
+  if (fp32(h->p))
+    RSOL_HIP(h, launch_gather<float>(h->p.shape, caller_packets<float>(h), h->E32, h->B32, (float*)Ep, (float*)Bp,
+                                     consts(h), h->stream), "gather");
+  else
+    RSOL_HIP(h, launch_gather<double>(h->p.shape, caller_packets<double>(h), h->E, h->B, (double*)Ep, (double*)Bp,
+                                      consts(h), h->stream), "gather");
+  return RSOL_OK;
+}
+
+int rsol_push(rsol_handle h, const void* Ep, const void* Bp, void* payload) {
+  if (int rc = need(h, false, true)) return rc;
+  if (h->np == 0) return RSOL_OK;
+  if (!Ep || !Bp || !payload) return fail(h, RSOL_EINVAL, "NULL pointer");
+  if (!(h->p.dt > 0)) return fail(h, RSOL_ESTATE, "dt not set");
+  if (fp32(h->p))
+    RSOL_HIP(h, launch_push<float>(caller_packets<float>(h), (const float*)Ep, (const float*)Bp, (float*)payload,
+                                   consts(h), h->stream), "push");
+  else
+    RSOL_HIP(h, launch_push<double>(caller_packets<double>(h), (const double*)Ep, (const double*)Bp,
+                                    (double*)payload, consts(h), h->stream), "push");
+  return RSOL_OK;
+}
+
+int rsol_deposit(rsol_handle h, const void* payload, double* dM, double* dE) {
+  if (int rc = need(h, false, true)) return rc;
+  if (h->np == 0) return RSOL_OK;
+  if (!payload || !dM) return fail(h, RSOL_EINVAL, "NULL pointer");
+  if (fp32(h->p))
+    RSOL_HIP(h, launch_deposit<float>(h->p.shape, caller_packets<float>(h), (const float*)payload, dM, dE, consts(h),
+                                      h->stream), "deposit");
+  else
+    RSOL_HIP(h, launch_deposit<double>(h->p.shape, caller_packets<double>(h), (const double*)payload, dM, dE,
+                                       consts(h), h->stream), "deposit");
+  return RSOL_OK;
+}
+
+int rsol_drift(rsol_handle h) {
+  if (int rc = need(h, false, true)) return rc;
+  if (h->np == 0) return RSOL_OK;
+  if (!(h->p.dt > 0)) return fail(h, RSOL_ESTATE, "dt not set");
+  if (fp32(h->p))
+    RSOL_HIP(h, launch_drift<float>(caller_packets<float>(h), consts(h), h->stream), "drift");
+  else
+    RSOL_HIP(h, launch_drift<double>(caller_packets<double>(h), consts(h), h->stream), "drift");
+  h->sorted_valid = false;
+  return RSOL_OK;
+}
+
+int rsol_sort(rsol_handle h) {
+  if (int rc = need(h, false, true)) return rc;
+  return fp32(h->p) ? do_sort<float>(h, true) : do_sort<double>(h, true);
+}
+
+int rsol_step(rsol_handle h, int32_t nsteps, double* dM, double* dE) {
+  if (int rc = need(h, true, true)) return rc;
+  if (nsteps < 0) return fail(h, RSOL_EINVAL, "nsteps < 0");
+  if (!(h->p.dt > 0)) return fail(h, RSOL_ESTATE, "dt not set");
+  if (!dM && dE) return fail(h, RSOL_EINVAL, "dE without dM");
+  if (h->np == 0 || nsteps == 0) return RSOL_OK;
+  return fp32(h->p) ? do_step<float>(h, nsteps, dM, dE) : do_step<double>(h, nsteps, dM, dE);
+}
+
+int rsol_moments(rsol_handle h, double* rho, double* P, double* e) {
+  if (int rc = need(h, false, true)) return rc;
+  const int64_t nc = n_cells(h->p);
+  if (rho) RSOL_HIP(h, launch_fill_f64(rho, 0.0, nc, h->stream), "zero rho");
+  if (P) RSOL_HIP(h, launch_fill_f64(P, 0.0, 3 * nc, h->stream), "zero P");
+  if (e) RSOL_HIP(h, launch_fill_f64(e, 0.0, nc, h->stream), "zero e");
+  if (h->np == 0) return RSOL_OK;
+  if (fp32(h->p))
+    RSOL_HIP(h, launch_moments<float>(h->p.shape, caller_packets<float>(h), rho, P, e, consts(h), h->stream),
+             "moments");
+  else
+    RSOL_HIP(h, launch_moments<double>(h->p.shape, caller_packets<double>(h), rho, P, e, consts(h), h->stream),
+             "moments");
+  return RSOL_OK;
+}
+
+int rsol_stray_count(rsol_handle h, int64_t* n) {
+  if (int rc = need(h, false, false)) return rc;
+  if (!n) return fail(h, RSOL_EINVAL, "n is NULL");
+  uint32_t word = 0;
+  RSOL_HIP(h, hipMemcpyAsync(&word, h->status + 1, sizeof(word), hipMemcpyDeviceToHost, h->stream), "stray copy");
+  RSOL_HIP(h, hipStreamSynchronize(h->stream), "stray sync");
+  RSOL_HIP(h, launch_fill_u32(h->status + 1, 0u, 1, h->stream), "stray clear");
+  *n = word;
+  return RSOL_OK;
+}
+
+int rsol_check(rsol_handle h) {
+  if (int rc = need(h, false, false)) return rc;
+  uint32_t word = 0;
+  RSOL_HIP(h, hipMemcpyAsync(&word, h->status, sizeof(word), hipMemcpyDeviceToHost, h->stream), "status copy");
+  RSOL_HIP(h, hipStreamSynchronize(h->stream), "status sync");
+  RSOL_HIP(h, launch_fill_u32(h->status, 0u, 1, h->stream), "status clear");
+  if (word & ERR_NAN) return fail(h, RSOL_ENAN, "non-finite packet momentum");
+  if (word & ERR_TILE) return fail(h, RSOL_ETILE, "a packet left its tile's staged region between re-sorts");
+  if (word & ERR_COURANT) return fail(h, RSOL_ECOURANT, "a packet moved further than the per-step bound");
+  return RSOL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,157 @@
+// Device-side building blocks of the RSOL packet step, shared by every kernel
+// of the library: run constants, the CIC/TSC assignment weights, the
+// relativistic Boris kick in increment form and the periodic drift.
+//
+// Physics (Ji & Hopkins, arXiv:2111.14704):
+//   drift      d<x>/dt = (c_tilde/c) <v> = c_tilde beta                 (Sec. 2)
+//   kick       d(gamma beta)/dt = (c_tilde/c) (q/(m c)) [E + beta x B]  (Sec. 2, Eq. (11))
+//   exchange   d(rho u)/dt = -sum_j (1/V_j) (c/c_tilde) d_t P_j         (Sec. 2, Eq. (12))
+//   E          = -(u_gas/c) x B with the true c                         (Sec. 2, after Eq. (5))
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rsol {
+
+// Error bits written by kernels into the library's device status word.
+enum : uint32_t {
+  ERR_COURANT = 1u,   // a packet moved further per step than the configured bound
+  ERR_NAN = 2u,       // a non-finite momentum or position appeared
+  ERR_TILE = 4u,      // a packet left the region its tile staged in LDS
+};
+
+// Per-run constants handed to every kernel by value.
+struct RunConsts {
+  int nx, ny, nz;
+  int ncells;
+  double dx, inv_dx;
+  double Lx, Ly, Lz;
+  double c, c_tilde, qomc, dt, mass;
+  double h;          // (c_tilde/c) (q/(m c)) dt / 2, the half kick of Eq. (11)
+  double cdt;        // c_tilde dt, the drift length per unit beta
+  double cdt_dx;     // c_tilde dt / dx
+  double pfac;       // -(c/c_tilde) M c / V: gas momentum per unit packet du (Eq. (12))
+  double efac;       // -(c/c_tilde) M c^2 / V: gas energy per unit packet dgamma
+  double max_step;   // largest allowed |dx| per step, in cells
+  uint32_t* status;  // device status word
+};
+
+__device__ __forceinline__ int wrap_index(int i, int n) {
+  return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+
+// Axis weights from a home cell and the in-cell offset f = x/dx - home in [0, 1).
+// CIC: nodes base, base+1 with base = floor(x/dx - 1/2).
+// TSC: nodes home-1, home, home+1 with d = f - 1/2.
+// (standard assignment functions standing in for the kernel W of Eq. (4)).
+template <int M, typename T>
+struct AxisWeights {
+  int base;  // first node (may be -1 before wrapping)
+  T w[M];
+};
+
+template <typename T>
+__device__ __forceinline__ AxisWeights<2, T> cic_axis(int home, T f) {
+  AxisWeights<2, T> a;
+  const T half = T(0.5);
+  T g;
+  if (f >= half) {
+    a.base = home;
+    g = f - half;
+  } else {
+    a.base = home - 1;
+    g = f + half;
+  }
+  a.w[0] = T(1) - g;
+  a.w[1] = g;
+  return a;
+}
+
+template <typename T>
+__device__ __forceinline__ AxisWeights<3, T> tsc_axis(int home, T f) {
+  AxisWeights<3, T> a;
+  const T half = T(0.5);
+  const T d = f - half;
+  a.base = home - 1;
+  const T l = half - d, r = half + d;
+  a.w[0] = half * l * l;
+  a.w[1] = T(0.75) - d * d;
+  a.w[2] = half * r * r;
+  return a;
+}
+
+template <int M, typename T>
+__device__ __forceinline__ AxisWeights<M, T> axis_weights(int home, T f) {
+  if constexpr (M == 2) {
+    return cic_axis<T>(home, f);
+  } else {
+    return tsc_axis<T>(home, f);
+  }
+}
+
+// Derivative of the axis weights with respect to the offset (per cell).
+template <int M, typename T>
+__device__ __forceinline__ void axis_weight_derivs(int home, T f, T dw[M]) {
+  if constexpr (M == 2) {
+    (void)home;
+    dw[0] = T(-1);
+    dw[1] = T(1);
+  } else {
+    (void)home;
+    const T d = f - T(0.5);
+    dw[0] = d - T(0.5);   // d/dd of (1/2)(1/2 - d)^2
+    dw[1] = T(-2) * d;
+    dw[2] = d + T(0.5);
+  }
+}
+
+// Relativistic Boris kick of u = gamma*beta with half kick h (Eq. (11)), written in
+// increment form: du = 2 h E + u' x s equals u_new - u exactly in real arithmetic but
+// carries no cancellation, and dgamma = du . (u_new + u) / (gamma_new + gamma).
+template <typename T>
+struct Kick {
+  T dux, duy, duz, dg;
+};
+
+template <typename T>
+__device__ __forceinline__ Kick<T> boris_kick(T ux, T uy, T uz, T ex, T ey, T ez,
+                                              T bx, T by, T bz, T h) {
+  const T hex = h * ex, hey = h * ey, hez = h * ez;
+  const T mx = ux + hex, my = uy + hey, mz = uz + hez;
+  const T gm = sqrt(T(1) + (mx * mx + my * my + mz * mz));
+  const T k = h / gm;
+  const T tx = k * bx, ty = k * by, tz = k * bz;
+  const T tt = tx * tx + ty * ty + tz * tz;
+  const T sf = T(2) / (T(1) + tt);
+  const T sx = sf * tx, sy = sf * ty, sz = sf * tz;
+  // u' = u- + u- x t
+  const T px = mx + (my * tz - mz * ty);
+  const T py = my + (mz * tx - mx * tz);
+  const T pz = mz + (mx * ty - my * tx);
+  // u+ - u- = u' x s
+  const T rx = py * sz - pz * sy;
+  const T ry = pz * sx - px * sz;
+  const T rz = px * sy - py * sx;
+  Kick<T> o;
+  o.dux = (hex + hex) + rx;
+  o.duy = (hey + hey) + ry;
+  o.duz = (hez + hez) + rz;
+  const T nx = ux + o.dux, ny = uy + o.duy, nz = uz + o.duz;
+  const T g0 = sqrt(T(1) + (ux * ux + uy * uy + uz * uz));
+  const T g1 = sqrt(T(1) + (nx * nx + ny * ny + nz * nz));
+  o.dg = (o.dux * (nx + ux) + o.duy * (ny + uy) + o.duz * (nz + uz)) / (g0 + g1);
+  return o;
+}
+
+// Periodic wrap of an absolute coordinate into [0, L); a value that rounds to L maps to 0.
+__device__ __forceinline__ double wrap_coord(double x, double L) {
+  double y = x - L * floor(x / L);
+  return y >= L ? y - L : y;
+}
+
+__device__ __forceinline__ void set_status(uint32_t* status, uint32_t bits) {
+  atomicOr(status, bits);
+}
+
+}  // namespace rsol

@@ -1,0 +1,55 @@
+// Packet-state views used by the kernels.
+//
+// Two layouts, both structure-of-arrays over packets:
+//   FP64 form: absolute positions x[3][np] (double), momenta u[3][np] (double)
+//   FP32 form: home cell index cell[np] (int32, ix + nx*(iy + ny*iz)),
+//              in-cell offsets off[3][np] (float, in [0, 1) cells), momenta u[3][np] (float)
+// plus a packet label id[np] (int32) that travels with every permutation.
+#pragma once
+
+#include <type_traits>
+
+#include "rsol_device.hpp"
+
+namespace rsol {
+
+template <typename T>
+struct Packets {
+  double* x;      // FP64 form only
+  int32_t* cell;  // FP32 form only
+  float* off;     // FP32 form only
+  T* u;
+  int32_t* id;
+  int64_t np;
+};
+
+template <typename T>
+constexpr bool is_fp64() { return std::is_same<T, double>::value; }
+
+// Home cell coordinates and the in-cell offset (in cells) of packet i.
+template <typename T>
+__device__ __forceinline__ void load_position(const Packets<T>& P, int64_t i, const RunConsts& k,
+                                              int home[3], T f[3]) {
+  if constexpr (is_fp64<T>()) {
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double s = P.x[d * P.np + i] * k.inv_dx;
+      const double fl = floor(s);
+      home[d] = (int)fl;
+      f[d] = s - fl;
+    }
+  } else {
+    const int c = P.cell[i];
+    const int nxy = k.nx * k.ny;
+    const int iz = c / nxy;
+    const int r = c - iz * nxy;
+    const int iy = r / k.nx;
+    home[0] = r - iy * k.nx;
+    home[1] = iy;
+    home[2] = iz;
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) f[d] = P.off[d * P.np + i];
+  }
+}
+
+}  // namespace rsol
