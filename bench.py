@@ -104,6 +104,41 @@ def time_path(w, precision, steps, warmup, sort_every):
     return out
 
 
+def time_backward(precision, nsteps=256, ckpt=16):
+    """Differentiation form on workload 5 (32^3 x 32 ppc, CIC): forward with checkpoints,
+    then the timed backward (moment adjoint + per segment: restore, recompute with stored
+    states, reverse sweep).  Rate = packets * steps / backward time."""
+    import torch
+    from paper_2111_14704_amd.autograd import RSOLRollout, spec_from_workload
+    from paper_2111_14704_amd.sim import Simulation
+    from workloads import make_workload
+
+    w = make_workload(5)
+    dev = "cuda"
+    # E = -(u/c) x B and the Courant timestep from the library
+    sim = Simulation.from_workload(w, precision="fp64")
+    dt = sim.dt
+    E = sim.E.clone().requires_grad_(True)
+    B = sim.B.clone().requires_grad_(True)
+    del sim
+    x0 = torch.tensor(w.x, device=dev)
+    u0 = torch.tensor(w.u, device=dev, requires_grad=True)
+    T = torch.tensor(w.target.reshape(3, -1), device=dev)
+    spec = spec_from_workload(w, dt, precision)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rho, P, e = RSOLRollout.apply(E, B, x0, u0, spec, nsteps, ckpt)
+    L = torch.sqrt(((P - T) ** 2).sum())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    npk = w.n_particles
+    return dict(workload=w.name, dtype="f64" if precision == "fp64" else "f32", value=npk * nsteps / (t2 - t1),
+                unit="particle-updates/s", backward_s=t2 - t1, forward_s=t1 - t0, steps=nsteps, ckpt=ckpt)
+
+
 def cpu_baseline(w, sample=131072, steps=6):
     """The CPU oracle (numpy FP64, as it stands) on a bounded sample of the same workload:
     the first `sample` packets for `steps` steps in the workload's fields."""
@@ -142,6 +177,9 @@ def main():
     ap.add_argument("--sort-every", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="first run one plain device copy of BYTES bytes (a known-size reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -152,6 +190,15 @@ def main():
     from workloads import make_workload
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:
+        n = args.calibrate_copy // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy of {n * 8} bytes done", file=sys.stderr, flush=True)
+        del src, dst
     w = make_workload(args.workload, precision="fp64")
     print(f"[bench] workload {w.name}: {w.n_particles} packets, {w.nx}^3 cells", file=sys.stderr, flush=True)
     r64 = time_path(w, "fp64", args.steps, args.warmup, args.sort_every)
@@ -160,6 +207,13 @@ def main():
     if not args.no_fp32:
         r32 = time_path(w, "fp32", args.steps, args.warmup, args.sort_every)
         print(f"[bench] fp32 {r32['value']:.3e} upd/s, kernel {r32['kernel_ms']:.3f} ms", file=sys.stderr, flush=True)
+    bwd = None
+    if not args.no_backward:
+        bwd = time_backward("fp64")
+        print(f"[bench] backward fp64 {bwd['value']:.3e} upd/s", file=sys.stderr, flush=True)
+        b32 = time_backward("fp32")
+        bwd["fp32"] = dict(value=b32["value"], backward_s=b32["backward_s"])
+        print(f"[bench] backward fp32 {b32['value']:.3e} upd/s", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w)
@@ -176,6 +230,8 @@ def main():
         cpu_baseline=cpu,
         kernel_ms=r64["kernel_ms"], sort_ms=r64["sort_ms"],
     )
+    if bwd:
+        line["backward"] = bwd
     if r32:
         line["fp32"] = dict(value=r32["value"], ms_per_step=r32["ms_per_step"], kernel_ms=r32["kernel_ms"],
                             sort_ms=r32["sort_ms"], dtype="f32", roofline=r32["roofline"],

@@ -72,8 +72,9 @@ typedef struct rsol_params {
 } rsol_params;
 
 /* flags */
-#define RSOL_FLAG_GLOBAL_ATOMICS 1  /* rsol_step: use the one-thread-per-packet kernel with
-                                       global atomics instead of the tiled LDS kernel        */
+#define RSOL_FLAG_KEEP_ORDER 1  /* rsol_step keeps the packet order (never re-bins) and runs the
+                                   one-thread-per-packet kernel with global atomics instead of
+                                   the tiled LDS kernel; the differentiation form runs so      */
 
 typedef struct rsol_ctx* rsol_handle;
 
@@ -147,6 +148,36 @@ int rsol_step(rsol_handle h, int32_t nsteps, double* dM, double* dE);
  * P[3][n_cells] = sum M c u W / V, e[n_cells] = sum M c^2 gamma W / V.  Outputs are
  * overwritten; any may be NULL. */
 int rsol_moments(rsol_handle h, double* rho, double* P, double* e);
+
+/* Set the RSOL_FLAG_* bits of the handle. */
+int rsol_set_flags(rsol_handle h, int32_t flags);
+
+/* ---- Differentiation form (reverse mode through gather -> push -> drift) ----
+ * The adjoint of the deposit is a gather and the adjoint of the gather is a scatter.
+ * Gradients flow to the grid fields E, B (as independent inputs) and to the initial
+ * packet state; dt is a fixed parameter.  Packet order must stay fixed between the
+ * recorded states and the adjoint arrays (rsol_record_states never re-bins). */
+
+/* Bytes of one stored packet state: np * 48 (FP64 form: x[3], u[3] doubles) or np * 28
+ * (FP32 form: cell, off[3], u[3] as 4-byte words). */
+size_t rsol_state_bytes(rsol_handle h);
+
+/* Advance nsteps steps without exchange deposit and without re-binning, writing the
+ * state BEFORE each step into states[n] (device buffer of nsteps * rsol_state_bytes). */
+int rsol_record_states(rsol_handle h, int32_t nsteps, void* states);
+
+/* Reverse of the nsteps steps recorded in states (from step nsteps-1 down to 0).
+ * lam_x, lam_u: [3][np] (precision type), on entry dL/d(x, u) after the last step, on
+ * exit dL/d(x, u) before the first.  lam_dM [3][n_cells], lam_dE [n_cells]: cotangent of
+ * the exchange summed over these steps (both may be NULL; lam_dE needs lam_dM).
+ * gE, gB: [3][n_cells] doubles, ACCUMULATED (+=).  Device pointers. */
+int rsol_step_backward(rsol_handle h, int32_t nsteps, const void* states, void* lam_x, void* lam_u,
+                       const double* lam_dM, const double* lam_dE, double* gE, double* gB);
+
+/* Adjoint of rsol_moments at the current state: adds to lam_x, lam_u ([3][np]) the
+ * gradient of sum(lam_rho*rho) + sum(lam_P*P) + sum(lam_e*e); any cotangent may be NULL. */
+int rsol_moments_backward(rsol_handle h, const double* lam_rho, const double* lam_P, const double* lam_e,
+                          void* lam_x, void* lam_u);
 
 /* Launch timing (a profiling aid, not part of the method): while enabled, every step and
  * sort launch made by rsol_step / rsol_sort is bracketed by HIP events on the handle's

@@ -7,5 +7,5 @@ this package only binds it (rsol.py) and wires device tensors to it (sim.py).
 """
 
 from .rsol import (  # noqa: F401
-    Handle, Params, RSOLError, RSOL_CIC, RSOL_TSC, RSOL_FP32, RSOL_FP64, RSOL_FLAG_GLOBAL_ATOMICS, lib,
+    Handle, Params, RSOLError, RSOL_CIC, RSOL_TSC, RSOL_FP32, RSOL_FP64, RSOL_FLAG_KEEP_ORDER, lib,
 )

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/rsol.h"
+#include "rsol_adjoint.hpp"
 #include "rsol_launch.hpp"
 #include "rsol_sort.hpp"
 #include "rsol_step.hpp"
@@ -284,7 +285,7 @@ int do_sort(rsol_ctx* h, bool copy) {
 template <typename T>
 int do_step(rsol_ctx* h, int32_t nsteps, double* dM, double* dE) {
   const RunConsts k = consts(h);
-  const bool global = (h->p.flags & RSOL_FLAG_GLOBAL_ATOMICS) != 0 || !h->plan.tiled;
+  const bool global = (h->p.flags & RSOL_FLAG_KEEP_ORDER) != 0 || !h->plan.tiled;
   for (int32_t s = 0; s < nsteps; ++s) {
     if (global) {
       auto ev = timed_begin(h);
@@ -560,6 +561,79 @@ int rsol_moments(rsol_handle h, double* rho, double* P, double* e) {
   else
     RSOL_HIP(h, launch_moments<double>(h->p.shape, caller_packets<double>(h), rho, P, e, consts(h), h->stream),
              "moments");
+  return RSOL_OK;
+}
+
+int rsol_set_flags(rsol_handle h, int32_t flags) {
+  if (int rc = need(h, false, false)) return rc;
+  if (flags & ~RSOL_FLAG_KEEP_ORDER) return fail(h, RSOL_EINVAL, "unknown flag bits");
+  h->p.flags = flags;
+  return RSOL_OK;
+}
+
+size_t rsol_state_bytes(rsol_handle h) {
+  if (!h) return 0;
+  return (size_t)h->np * (fp32(h->p) ? 7 * sizeof(float) : 6 * sizeof(double));
+}
+
+int rsol_record_states(rsol_handle h, int32_t nsteps, void* states) {
+  if (int rc = need(h, true, true)) return rc;
+  if (nsteps < 0) return fail(h, RSOL_EINVAL, "nsteps < 0");
+  if (!(h->p.dt > 0)) return fail(h, RSOL_ESTATE, "dt not set");
+  if (h->np == 0 || nsteps == 0) return RSOL_OK;
+  if (!states) return fail(h, RSOL_EINVAL, "states is NULL");
+  const RunConsts k = consts(h);
+  const size_t slab = rsol_state_bytes(h);
+  for (int32_t n = 0; n < nsteps; ++n) {
+    void* at = (char*)states + (size_t)n * slab;
+    if (fp32(h->p)) {
+      RSOL_HIP(h, launch_record<float>(caller_packets<float>(h), at, h->stream), "record");
+      RSOL_HIP(h, launch_step_global<float>(h->p.shape, caller_packets<float>(h), h->E32, h->B32, nullptr, nullptr, k,
+                                            h->stream), "record step");
+    } else {
+      RSOL_HIP(h, launch_record<double>(caller_packets<double>(h), at, h->stream), "record");
+      RSOL_HIP(h, launch_step_global<double>(h->p.shape, caller_packets<double>(h), h->E, h->B, nullptr, nullptr, k,
+                                             h->stream), "record step");
+    }
+  }
+  h->sorted_valid = false;
+  return RSOL_OK;
+}
+
+int rsol_step_backward(rsol_handle h, int32_t nsteps, const void* states, void* lam_x, void* lam_u,
+                       const double* lam_dM, const double* lam_dE, double* gE, double* gB) {
+  if (int rc = need(h, true, true)) return rc;
+  if (nsteps < 0) return fail(h, RSOL_EINVAL, "nsteps < 0");
+  if (!(h->p.dt > 0)) return fail(h, RSOL_ESTATE, "dt not set");
+  if (!lam_dM && lam_dE) return fail(h, RSOL_EINVAL, "lam_dE without lam_dM");
+  if (h->np == 0 || nsteps == 0) return RSOL_OK;
+  if (!states || !lam_x || !lam_u || !gE || !gB) return fail(h, RSOL_EINVAL, "NULL pointer");
+  const RunConsts k = consts(h);
+  const size_t slab = rsol_state_bytes(h);
+  for (int32_t n = nsteps - 1; n >= 0; --n) {
+    const void* at = (const char*)states + (size_t)n * slab;
+    if (fp32(h->p))
+      RSOL_HIP(h, launch_step_backward<float>(h->p.shape, at, h->np, (float*)lam_x, (float*)lam_u, h->E32, h->B32,
+                                              lam_dM, lam_dE, gE, gB, k, h->stream), "step backward");
+    else
+      RSOL_HIP(h, launch_step_backward<double>(h->p.shape, at, h->np, (double*)lam_x, (double*)lam_u, h->E, h->B,
+                                               lam_dM, lam_dE, gE, gB, k, h->stream), "step backward");
+  }
+  return RSOL_OK;
+}
+
+int rsol_moments_backward(rsol_handle h, const double* lam_rho, const double* lam_P, const double* lam_e,
+                          void* lam_x, void* lam_u) {
+  if (int rc = need(h, false, true)) return rc;
+  if (h->np == 0) return RSOL_OK;
+  if (!lam_x || !lam_u) return fail(h, RSOL_EINVAL, "NULL adjoint array");
+  if (fp32(h->p))
+    RSOL_HIP(h, launch_moments_backward<float>(h->p.shape, caller_packets<float>(h), lam_rho, lam_P, lam_e,
+                                               (float*)lam_x, (float*)lam_u, consts(h), h->stream), "moments backward");
+  else
+    RSOL_HIP(h, launch_moments_backward<double>(h->p.shape, caller_packets<double>(h), lam_rho, lam_P, lam_e,
+                                                (double*)lam_x, (double*)lam_u, consts(h), h->stream),
+             "moments backward");
   return RSOL_OK;
 }
 

@@ -24,7 +24,7 @@ STATUS = {
 }
 RSOL_CIC, RSOL_TSC = 1, 2
 RSOL_FP64, RSOL_FP32 = 0, 1
-RSOL_FLAG_GLOBAL_ATOMICS = 1
+RSOL_FLAG_KEEP_ORDER = 1
 
 
 class RSOLError(RuntimeError):
@@ -78,6 +78,11 @@ def lib():
             "rsol_check": (ctypes.c_int, [vp]),
             "rsol_timing": (ctypes.c_int, [vp, i32]),
             "rsol_stray_count": (ctypes.c_int, [vp, ctypes.POINTER(i64)]),
+            "rsol_set_flags": (ctypes.c_int, [vp, i32]),
+            "rsol_state_bytes": (ctypes.c_size_t, [vp]),
+            "rsol_record_states": (ctypes.c_int, [vp, i32, vp]),
+            "rsol_step_backward": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, vp]),
+            "rsol_moments_backward": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
             "rsol_timing_read": (ctypes.c_int, [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64),
                                                  ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
         }
@@ -95,7 +100,8 @@ def exported_symbols():
         "rsol_set_fields", "rsol_set_particles", "rsol_positions_to_cells", "rsol_cells_to_positions",
         "rsol_courant_dt", "rsol_set_dt", "rsol_gather", "rsol_push", "rsol_deposit", "rsol_drift",
         "rsol_sort", "rsol_step", "rsol_moments", "rsol_check", "rsol_timing", "rsol_timing_read",
-        "rsol_stray_count",
+        "rsol_stray_count", "rsol_set_flags", "rsol_state_bytes", "rsol_record_states", "rsol_step_backward",
+        "rsol_moments_backward",
     ]
 
 
@@ -227,6 +233,24 @@ class Handle:
 
     def rsol_check(self):
         _check(self.h, lib().rsol_check(self.h))
+
+    def rsol_set_flags(self, flags: int):
+        _check(self.h, lib().rsol_set_flags(self.h, int(flags)))
+        self.params.flags = int(flags)
+
+    def rsol_state_bytes(self) -> int:
+        return int(lib().rsol_state_bytes(self.h))
+
+    def rsol_record_states(self, nsteps: int, states):
+        _check(self.h, lib().rsol_record_states(self.h, int(nsteps), _ptr(states)))
+
+    def rsol_step_backward(self, nsteps: int, states, lam_x, lam_u, gE, gB, lam_dM=None, lam_dE=None):
+        _check(self.h, lib().rsol_step_backward(self.h, int(nsteps), _ptr(states), _ptr(lam_x), _ptr(lam_u),
+                                                _ptr(lam_dM), _ptr(lam_dE), _ptr(gE), _ptr(gB)))
+
+    def rsol_moments_backward(self, lam_x, lam_u, lam_rho=None, lam_P=None, lam_e=None):
+        _check(self.h, lib().rsol_moments_backward(self.h, _ptr(lam_rho), _ptr(lam_P), _ptr(lam_e), _ptr(lam_x),
+                                                   _ptr(lam_u)))
 
     def rsol_stray_count(self) -> int:
         n = ctypes.c_int64()

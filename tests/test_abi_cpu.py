@@ -25,7 +25,7 @@ def _lib():
 
 def test_header_declares_the_hot_path_entry_points():
     names = _declared()
-    for required in ("rsol_init", "rsol_gather", "rsol_push", "rsol_deposit", "rsol_step"):
+    for required in ("rsol_init", "rsol_gather", "rsol_push", "rsol_deposit", "rsol_step", "rsol_step_backward"):
         assert required in names, required
 
 
