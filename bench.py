@@ -27,7 +27,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "particle-updates/s (gather+RSOL push+deposit), FP32 vs FP64, % of HBM peak"
-KERNEL_SOURCES = ["paper_2111_14704_amd/csrc/kernels_step.hip", "paper_2111_14704_amd/csrc/rsol_device.hpp"]
+KERNEL_SOURCES = ["paper_2111_14704_amd/csrc/kernels_cells.hip", "paper_2111_14704_amd/csrc/rsol_cells.hpp",
+                  "paper_2111_14704_amd/csrc/rsol_device.hpp"]
 
 
 def kernel_hash():
@@ -97,7 +98,7 @@ def time_path(w, precision, steps, warmup, sort_every):
         value=npk * steps / wall, ms_per_step=wall / steps * 1e3,
         kernel_ms=kern_s * 1e3, sort_ms=(sort_ms / n_sort) if n_sort else 0.0, sorts=n_sort,
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                      traffic=traffic, bytes_per_packet_step=balg, kernel="step_tiled_kernel"),
+                      traffic=traffic, bytes_per_packet_step=balg, kernel="cells_step_kernel"),
     )
     del sim
     torch.cuda.synchronize()

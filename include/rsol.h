@@ -73,8 +73,11 @@ typedef struct rsol_params {
 
 /* flags */
 #define RSOL_FLAG_KEEP_ORDER 1  /* rsol_step keeps the packet order (never re-bins) and runs the
-                                   one-thread-per-packet kernel with global atomics instead of
-                                   the tiled LDS kernel; the differentiation form runs so      */
+                                   one-thread-per-packet kernel with global atomics; the
+                                   differentiation form runs so                               */
+#define RSOL_FLAG_TILED 2       /* rsol_step runs the tiled LDS kernel over packets re-sorted
+                                   every sort_every steps instead of the default cell-list
+                                   kernel (ignored under RSOL_FLAG_KEEP_ORDER)                */
 
 typedef struct rsol_ctx* rsol_handle;
 
@@ -139,9 +142,13 @@ int rsol_drift(rsol_handle h);
  * registered arrays are permuted in place, id with them). */
 int rsol_sort(rsol_handle h);
 
-/* nsteps fused packet steps (gather, kick, exchange deposit at x^n, drift), re-binning
- * packets every sort_every steps.  The exchange of every step is ADDED to dM[3][n_cells]
- * and dE[n_cells] (either may be NULL to skip the deposit). */
+/* nsteps fused packet steps (gather, kick, exchange deposit at x^n, drift).  The
+ * exchange of every step is ADDED to dM[3][n_cells] and dE[n_cells] (dM NULL skips the
+ * deposit; dE may be NULL).  Default path: the packets are filed into per-cell buckets
+ * in scratch, every step moves each packet into the bucket of its new cell, and on
+ * return the registered arrays hold the packets in cell-major order (id permuted with
+ * them).  RSOL_FLAG_TILED: re-sort every sort_every steps and run the tiled kernel.
+ * RSOL_FLAG_KEEP_ORDER: packet order unchanged. */
 int rsol_step(rsol_handle h, int32_t nsteps, double* dM, double* dE);
 
 /* CR moments of the current state (Sec. 2 packet totals): rho[n_cells] = sum M W / V,

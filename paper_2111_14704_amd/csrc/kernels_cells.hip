@@ -1,0 +1,1128 @@
+// Cell-list fused packet step.
+//
+// Packets live in per-cell buckets (two ping-pong buffers), plus per-tile inboxes
+// and one overflow list for the grid.  One 256-thread workgroup owns a 4x4x4 tile;
+// its 64 cells map one-to-one to 64 quads (groups of 4 lanes).  A quad keeps the
+// field stencil of its cell in registers: lane q < 3 holds component q of E and of
+// B on the 27 nodes around the cell.  It also keeps the cell's exchange deposit in
+// registers: lane q holds component q of (dM_x, dM_y, dM_z, dE) on the same 27
+// nodes.  The cell's packets are taken four at a time, one per lane; the weights,
+// exchange values and partial field sums of the four packets pass between the
+// quad's lanes through a per-wave LDS area, so the main loop neither reads the
+// field grid nor issues atomics to global memory.
+//
+// After its drift a packet is written straight into the bucket of its new cell
+// when that cell is in the same tile (slot from an LDS counter); otherwise into
+// the neighbouring tile's inbox part reserved for packets arriving from this tile
+// (slot from another LDS counter; the final count is stored once, by this
+// workgroup, without atomics).  The next step therefore reads every packet from
+// the store of the tile it is in.  Inbox packets take a per-packet path that
+// gathers from LDS-staged fields and deposits with LDS atomics; overflow packets
+// (full parts, never in practice) gather from global memory and deposit with
+// global atomics.  The workgroup's exchange accumulator (tile plus one-cell halo)
+// is stored without atomics to a per-tile buffer that a second kernel adds into
+// the grid.
+//
+// Physics per packet as in the other step kernels: gather at x^n, relativistic Boris
+// kick of Eq. (11), exchange of Eq. (12) at x^n, drift with c_tilde beta (Sec. 2).
+#include <math.h>
+
+#include "rsol_cells.hpp"
+#include "rsol_launch.hpp"
+#include "rsol_sort.hpp"
+
+namespace rsol {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kTrashSlots = 8 * kThreads;
+
+__device__ __host__ __forceinline__ int wrapm(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+// Per-lane strides (elements) of the quad loop's LDS exchange areas: 12 weights + 4
+// exchange values, and 4 x 2 partial sums, padded so that the 16 quads of a wave
+// (and the lanes of a wave) start on distinct 16-byte bank groups.
+template <typename T>
+constexpr int kPkStride = sizeof(T) == 8 ? 18 : 20;
+template <typename T>
+constexpr int kRsStride = 10;
+
+// Order the wave's own LDS writes before its following LDS reads (lanes of one wave
+// exchange data through LDS; no other wave touches the area).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Axis weights on the three nodes (home-1, home, home+1) for an in-cell offset f in
+// [0, 1); CIC puts its two nonzero weights on (home-1, home) or (home, home+1).
+template <int M, typename T>
+__device__ __forceinline__ void weights3(T f, T* w) {
+  const T half = T(0.5);
+  if constexpr (M == 3) {
+    const T d = f - half, l = half - d, r = half + d;
+    w[0] = half * l * l;
+    w[1] = T(0.75) - d * d;
+    w[2] = half * r * r;
+  } else {
+    if (f >= half) {
+      const T g = f - half;
+      w[0] = T(0);
+      w[1] = T(1) - g;
+      w[2] = g;
+    } else {
+      const T g = f + half;
+      w[0] = T(1) - g;
+      w[1] = g;
+      w[2] = T(0);
+    }
+  }
+}
+
+// Interpolate six field components at one packet from the 27 nodes around its home
+// cell, fetch(node, comp) giving the node values; the summation order (x first, then
+// y-z pairs) is the one the quad path uses, so a packet's arithmetic does not depend
+// on the store it was read from.
+template <typename T, typename F>
+__device__ __forceinline__ void gather27(const T* w, F fetch, T out[6]) {
+  #pragma unroll
+  for (int d = 0; d < 6; ++d) out[d] = T(0);
+  #pragma unroll
+  for (int c = 0; c < 3; ++c)
+    #pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const T wyz = w[3 + b] * w[6 + c];
+      #pragma unroll
+      for (int d = 0; d < 6; ++d) {
+        T t = T(0);
+        #pragma unroll
+        for (int a = 0; a < 3; ++a) t += w[a] * fetch(a + 3 * (b + 3 * c), d);
+        out[d] += wyz * t;
+      }
+    }
+}
+
+// Bucket slot s of the cell with grid coordinates h: buckets are laid out tile by
+// tile as [slot][cell in tile], so the 16 cells a wave works on keep each slot
+// row in whole cache lines.
+__device__ __forceinline__ int64_t bucket_index(const int h[3], int s, int ntx, int nty, int cap) {
+  const int tx = h[0] / kCellTile, ty = h[1] / kCellTile, tz = h[2] / kCellTile;
+  const int64_t t = tx + (int64_t)ntx * (ty + (int64_t)nty * tz);
+  const int lc = (h[0] - tx * kCellTile) + kCellTile * ((h[1] - ty * kCellTile) + kCellTile * (h[2] - tz * kCellTile));
+  return (t * cap + s) * kCellTileCells + lc;
+}
+
+__device__ __forceinline__ void cell_coords(int c, const RunConsts& k, int h[3]) {
+  const int nxy = k.nx * k.ny;
+  h[2] = c / nxy;
+  const int r = c - h[2] * nxy;
+  h[1] = r / k.nx;
+  h[0] = r - h[1] * k.nx;
+}
+
+// Buffers of one step, current (in) and next (out).
+struct StepView {
+  int ntx, nty, ntz;
+  int64_t ntiles;
+  int cap, per_tile;
+  int64_t ocap;
+  int dcap[kDirs];
+  int doff[kDirs + 1];
+  SlotArrays bin, iin, oin;
+  SlotArrays bout, iout, oout;
+  SlotArrays trash;
+  const int32_t* bcnt_in;
+  int32_t* bcnt_out;
+  int32_t* icnt_in;   // [ntiles*kDirs] then the overflow count
+  int32_t* icnt_out;
+  double* halo;
+};
+
+StepView step_view(const CellLists& L) {
+  StepView V;
+  const int a = L.cur, b = 1 - L.cur;
+  V.ntx = L.ntx;
+  V.nty = L.nty;
+  V.ntz = L.ntz;
+  V.ntiles = L.ntiles;
+  V.cap = L.cap;
+  V.per_tile = L.per_tile;
+  V.ocap = L.ocap;
+  for (int d = 0; d < kDirs; ++d) V.dcap[d] = L.dcap[d];
+  for (int d = 0; d <= kDirs; ++d) V.doff[d] = L.doff[d];
+  V.bin = L.bucket[a];
+  V.iin = L.inbox[a];
+  V.oin = L.ovf[a];
+  V.bout = L.bucket[b];
+  V.iout = L.inbox[b];
+  V.oout = L.ovf[b];
+  V.trash = L.trash;
+  V.bcnt_in = L.bcnt[a];
+  V.bcnt_out = L.bcnt[b];
+  V.icnt_in = L.icnt[a];
+  V.icnt_out = L.icnt[b];
+  V.halo = L.halo;
+  return V;
+}
+
+// Per-component pointers of one slot.
+template <typename T>
+struct Dst {
+  double* x;      // FP64
+  float* off;     // FP32
+  T* u;
+  int32_t* id;
+  int32_t* cell;  // FP32
+  int64_t stride;
+};
+
+template <typename T>
+__device__ __forceinline__ Dst<T> dst_of(const SlotArrays& S, int64_t j) {
+  Dst<T> d;
+  if constexpr (is_fp64<T>()) {
+    d.x = S.x + j;
+    d.off = nullptr;
+  } else {
+    d.x = nullptr;
+    d.off = S.off + j;
+  }
+  d.u = (T*)S.u + j;
+  d.id = S.id + j;
+  d.cell = S.cell ? S.cell + j : nullptr;
+  d.stride = S.stride;
+  return d;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_dst(const Dst<T>& d, const double x[3], const T f[3], const T u[3], int32_t id,
+                                          int32_t cell) {
+  #pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if constexpr (is_fp64<T>()) d.x[c * d.stride] = x[c];
+    else d.off[c * d.stride] = f[c];
+    d.u[c * d.stride] = u[c];
+  }
+  d.id[0] = id;
+  if constexpr (!is_fp64<T>()) d.cell[0] = cell;
+}
+
+// Load a packet from an inbox or the overflow list (home cell not implied by the slot).
+template <typename T>
+__device__ __forceinline__ void load_free(const SlotArrays& S, int64_t j, const RunConsts& k, int home[3], T f[3],
+                                          double xa[3], T u[3], int32_t& id) {
+  const T* su = (const T*)S.u;
+  if constexpr (is_fp64<T>()) {
+    const int n3[3] = {k.nx, k.ny, k.nz};
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      xa[d] = S.x[d * S.stride + j];
+      const double s = xa[d] * k.inv_dx;
+      const double fl = floor(s);
+      home[d] = wrapm((int)fl, n3[d]);
+      f[d] = s - fl;
+    }
+  } else {
+    cell_coords(S.cell[j], k, home);
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      f[d] = S.off[d * S.stride + j];
+      xa[d] = 0.0;
+    }
+  }
+  #pragma unroll
+  for (int d = 0; d < 3; ++d) u[d] = su[d * S.stride + j];
+  id = S.id[j];
+}
+
+// Tile offset from tile tt to tile t along an axis of n tiles: -1, 0 or 1 (through
+// the periodic wrap), or 2 when the tiles are not neighbours.
+__device__ __forceinline__ int tile_step(int t, int tt, int n) {
+  int d = t - tt;
+  if (n > 2) {
+    if (d == n - 1) d = -1;
+    else if (d == 1 - n) d = 1;
+  }
+  return (d < -1 || d > 1) ? 2 : d;
+}
+
+enum : int { kToTrash = 0, kToBucket = 1, kToInbox = 2, kToOverflow = 3 };
+
+// Slot for a packet of this workgroup's tile whose new (wrapped) home cell is h:
+// the bucket of h when h is in this tile and the bucket has room (kToBucket), else
+// the part of h's tile inbox reserved for packets from this tile (kToInbox).
+// kToOverflow when neither has room or h's tile is not a neighbour.
+__device__ __forceinline__ int place(const StepView& V, int ttx, int tty, int ttz, int* cntB, int* cntD,
+                                     const int* sDcap, const int* sDoff, const RunConsts& k, const int h[3],
+                                     int64_t& j) {
+  const int tx = h[0] / kCellTile, ty = h[1] / kCellTile, tz = h[2] / kCellTile;
+  const int sx = tile_step(tx, ttx, V.ntx), sy = tile_step(ty, tty, V.nty), sz = tile_step(tz, ttz, V.ntz);
+  if (sx > 1 || sy > 1 || sz > 1) return kToOverflow;
+  const int dir = (sx + 1) + 3 * ((sy + 1) + 3 * (sz + 1));
+  if (dir == kSelfDir) {
+    const int local =
+        (h[0] - tx * kCellTile) + kCellTile * ((h[1] - ty * kCellTile) + kCellTile * (h[2] - tz * kCellTile));
+    const int slot = atomicAdd(&cntB[local], 1);
+    if (slot < V.cap) {
+      j = bucket_index(h, slot, V.ntx, V.nty, V.cap);
+      return kToBucket;
+    }
+  }
+  const int s = atomicAdd(&cntD[dir], 1);
+  if (s < sDcap[dir]) {
+    const int64_t t = tx + (int64_t)V.ntx * (ty + (int64_t)V.nty * tz);
+    j = t * V.per_tile + sDoff[dir] + s;
+    return kToInbox;
+  }
+  return kToOverflow;
+}
+
+// Pointers of slot j of the store `kind` of the next buffer, chosen with selects on
+// the (uniform) store bases.
+template <typename T>
+__device__ __forceinline__ Dst<T> dst_select(const StepView& V, int kind, int64_t j) {
+  const SlotArrays& A = V.bout;
+  const SlotArrays& I = V.iout;
+  const SlotArrays& O = V.oout;
+  const SlotArrays& X = V.trash;
+  auto pick = [&](auto a, auto i, auto o, auto x) { return kind == kToBucket ? a : kind == kToInbox ? i : kind == kToOverflow ? o : x; };
+  Dst<T> d;
+  if constexpr (is_fp64<T>()) {
+    d.x = pick(A.x, I.x, O.x, X.x) + j;
+    d.off = nullptr;
+  } else {
+    d.x = nullptr;
+    d.off = pick(A.off, I.off, O.off, X.off) + j;
+  }
+  d.u = (T*)pick(A.u, I.u, O.u, X.u) + j;
+  d.id = pick(A.id, I.id, O.id, X.id) + j;
+  // buckets imply the cell; their cell store goes to the trash slot
+  d.cell = kind == kToBucket ? nullptr : pick(A.cell, I.cell, O.cell, X.cell) + j;
+  d.stride = pick(A.stride, I.stride, O.stride, X.stride);
+  return d;
+}
+
+// Slot in the next overflow list (global counter): kToOverflow, or kToTrash and
+// ERR_TILE when that is full too (unreachable: the list holds every packet).
+__device__ __forceinline__ int place_overflow(const StepView& V, int trash_slot, uint32_t& err, int64_t& j) {
+  const int s = atomicAdd(V.icnt_out + V.ntiles * kDirs, 1);
+  if ((int64_t)s < V.ocap) {
+    j = s;
+    return kToOverflow;
+  }
+  err |= ERR_TILE;
+  j = trash_slot;
+  return kToTrash;
+}
+
+// Drift (Sec. 2: dx/dt = c_tilde beta) of one packet with home cell `home`, offset f
+// (cells) and FP64 position xa; returns the new home h, position xn (FP64) and
+// offset fn (FP32), and error bits.
+template <typename T>
+__device__ __forceinline__ uint32_t drift3(const RunConsts& k, const int home[3], const T f[3], const double xa[3],
+                                           const T un[3], int h[3], double xn[3], T fn[3]) {
+  const T g = sqrt(T(1) + (un[0] * un[0] + un[1] * un[1] + un[2] * un[2]));
+  bool bad = !isfinite(g);
+  const int n3[3] = {k.nx, k.ny, k.nz};
+  if constexpr (is_fp64<T>()) {
+    const double L3[3] = {k.Lx, k.Ly, k.Lz};
+    const double s = k.cdt / g;
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double st = s * un[d];
+      bad |= fabs(st) > k.max_step * k.dx;
+      xn[d] = wrap_coord(xa[d] + st, L3[d]);
+      h[d] = wrapm((int)floor(xn[d] * k.inv_dx), n3[d]);
+      fn[d] = 0;
+    }
+  } else {
+    const float s = (float)k.cdt_dx / g;
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float st = s * un[d];
+      bad |= fabsf(st) > (float)k.max_step;
+      float fo = f[d] + st;
+      const float fl = floorf(fo);
+      int hd = home[d] + (int)fl;
+      fo -= fl;
+      if (fo >= 1.0f) {
+        fo = 0.0f;
+        hd += 1;
+      }
+      h[d] = wrapm(hd, n3[d]);
+      fn[d] = fo;
+      xn[d] = 0.0;
+    }
+  }
+  if (!bad) return 0u;
+  return isfinite(g) ? (uint32_t)ERR_COURANT : (uint32_t)ERR_NAN;
+}
+
+template <int M, typename T, bool DEP>
+__global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const T* __restrict__ E,
+                                                              const T* __restrict__ B, double* __restrict__ dM,
+                                                              double* __restrict__ dE, RunConsts k) {
+  __shared__ T Fs[6][kRegionCells];
+  __shared__ double Acc[4][kRegionCells];
+  __shared__ int cntB[kCellTileCells];
+  __shared__ int cntD[kDirs];
+  __shared__ int sDcap[kDirs];
+  __shared__ int sDoff[kDirs + 1];
+  __shared__ int sPre[kDirs + 1];   // prefix of this tile's inbox counts by direction
+  // per-wave exchange areas of the quad loop: per lane, the packet's weights and
+  // exchange values (Pk) and the lane's partial field sums (Rs)
+  __shared__ __attribute__((aligned(16))) T Pk[kThreads / 64][64 * kPkStride<T>];
+  __shared__ __attribute__((aligned(16))) T Rs[kThreads / 64][64 * kRsStride<T>];
+
+  constexpr bool deposit = DEP;
+  const int64_t ntiles = V.ntiles;
+  int64_t tile = blockIdx.x;
+  // consecutive workgroups go to different XCDs: give each XCD a contiguous range of
+  // tiles so neighbouring tiles share that XCD's L2
+  if ((ntiles & 7) == 0) tile = (int64_t)(blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
+  const int ttx = (int)(tile % V.ntx);
+  const int tty = (int)((tile / V.ntx) % V.nty);
+  const int ttz = (int)(tile / ((int64_t)V.ntx * V.nty));
+  const int ox = ttx * kCellTile - 1, oy = tty * kCellTile - 1, oz = ttz * kCellTile - 1;
+  const int64_t nc = k.ncells;
+  const int trash_slot = (int)(blockIdx.x & 7) * kThreads + threadIdx.x;
+  uint32_t err = 0;
+
+  for (int r = threadIdx.x; r < kRegionCells; r += kThreads) {
+    const int rx = r % kRegionEdge, ry = (r / kRegionEdge) % kRegionEdge, rz = r / (kRegionEdge * kRegionEdge);
+    const int64_t cell =
+        wrapm(ox + rx, k.nx) + (int64_t)k.nx * (wrapm(oy + ry, k.ny) + (int64_t)k.ny * wrapm(oz + rz, k.nz));
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      Fs[d][r] = E[d * nc + cell];
+      Fs[3 + d][r] = B[d * nc + cell];
+    }
+    if constexpr (deposit) {
+      #pragma unroll
+      for (int d = 0; d < 4; ++d) Acc[d][r] = 0.0;
+    }
+  }
+  if (threadIdx.x < kCellTileCells) cntB[threadIdx.x] = 0;
+  if (threadIdx.x < kDirs) {
+    cntD[threadIdx.x] = 0;
+    sDcap[threadIdx.x] = V.dcap[threadIdx.x];
+  }
+  if (threadIdx.x <= kDirs) sDoff[threadIdx.x] = V.doff[threadIdx.x];
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int d = 0; d < kDirs; ++d) {
+      sPre[d] = run;
+      const int c = V.icnt_in[tile * kDirs + d];
+      run += c < V.dcap[d] ? c : V.dcap[d];
+    }
+    sPre[kDirs] = run;
+  }
+  __syncthreads();
+
+  const T h = (T)k.h;
+  const T pf = (T)k.pfac, ef = (T)k.efac;
+
+  // ------------------------------------------------------------ quads: one cell each
+  {
+    const int q = threadIdx.x & 3;
+    const int quad = threadIdx.x >> 2;
+    const int lane = threadIdx.x & 63;
+    const int qbase = lane & ~3;  // first lane of this quad within the wave
+    T* pkw = &Pk[threadIdx.x >> 6][0];
+    T* rsw = &Rs[threadIdx.x >> 6][0];
+    const int lx = quad & 3, ly = (quad >> 2) & 3, lz = quad >> 4;
+    const int home[3] = {ttx * kCellTile + lx, tty * kCellTile + ly, ttz * kCellTile + lz};
+    const bool valid = home[0] < k.nx && home[1] < k.ny && home[2] < k.nz;
+    const int64_t cell = valid ? home[0] + (int64_t)k.nx * (home[1] + (int64_t)k.ny * home[2]) : 0;
+    int n = valid ? V.bcnt_in[cell] : 0;
+    n = n < V.cap ? n : V.cap;
+
+    // this lane's field components on the 27 nodes around the cell
+    T F0[27], F1[27], D[27];
+    #pragma unroll
+    for (int c = 0; c < 3; ++c)
+      #pragma unroll
+      for (int b = 0; b < 3; ++b)
+        #pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int node = a + 3 * (b + 3 * c);
+          const int r = (lx + a) + kRegionEdge * ((ly + b) + kRegionEdge * (lz + c));
+          F0[node] = q < 3 ? Fs[q][r] : T(0);
+          F1[node] = q < 3 ? Fs[3 + q][r] : T(0);
+          D[node] = T(0);
+        }
+
+    const SlotArrays& S = V.bin;
+    const T* su = (const T*)S.u;
+    const int rounds = (n + 3) >> 2;
+    // packet state of the coming round, loaded one round ahead; idle lanes load a
+    // valid slot of their cell and ignore it, so every round issues the same loads
+    T pu[3];
+    double px[3];
+    int32_t pid;
+    auto fetch = [&](int rd) {
+      int kk = 4 * rd + q;
+      kk = kk < n ? kk : (n > 0 ? n - 1 : 0);
+      const int64_t j = (tile * V.cap + kk) * kCellTileCells + quad;
+      #pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        if constexpr (is_fp64<T>()) px[d] = S.x[d * S.stride + j];
+        else px[d] = (double)S.off[d * S.stride + j];
+        pu[d] = su[d * S.stride + j];
+      }
+      pid = S.id[j];
+    };
+    // the previous round's packet, stored at the start of the next round (just before
+    // that round's prefetch) so that the loop never waits on its own fresh stores
+    int okind = kToTrash;
+    int64_t oj = trash_slot;
+    double oxn[3] = {0.0, 0.0, 0.0};
+    T ofn[3] = {T(0), T(0), T(0)}, oun[3] = {T(0), T(0), T(0)};
+    int32_t oid = 0, ocell = 0;
+    auto flush = [&]() {
+      Dst<T> dst = dst_select<T>(V, okind, oj);
+      if constexpr (!is_fp64<T>()) {
+        if (!dst.cell) dst.cell = V.trash.cell + trash_slot;
+      }
+      store_dst<T>(dst, oxn, ofn, oun, oid, ocell);
+    };
+    fetch(0);
+    for (int rd = 0; __ballot(rd < rounds) != 0; ++rd) {
+      const bool act = 4 * rd + q < n;
+      T f[3], u[3];
+      double xa[3] = {0.0, 0.0, 0.0};
+      const int32_t id = pid;
+      #pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        if constexpr (is_fp64<T>()) {
+          xa[d] = px[d];
+          const double s = xa[d] * k.inv_dx;
+          f[d] = act ? s - floor(s) : 0.5;
+        } else {
+          f[d] = act ? (T)px[d] : T(0.5);
+        }
+        u[d] = act ? pu[d] : T(0);
+      }
+      flush();
+      fetch(rd + 1);
+
+      // own weights -> LDS: x weights, then the nine y-z products
+      {
+        T wx[3], wy[3], wz[3];
+        weights3<M, T>(f[0], wx);
+        weights3<M, T>(f[1], wy);
+        weights3<M, T>(f[2], wz);
+        T* o = pkw + lane * kPkStride<T>;
+        o[0] = wx[0];
+        o[1] = wx[1];
+        o[2] = wx[2];
+        #pragma unroll
+        for (int c = 0; c < 3; ++c)
+          #pragma unroll
+          for (int b = 0; b < 3; ++b) o[3 + b + 3 * c] = wy[b] * wz[c];
+      }
+      wave_sync();
+
+      // gather: lane q sums its two components for each packet J of the quad and
+      // leaves the partial sums in LDS for the owner lane
+      #pragma unroll
+      for (int J = 0; J < 4; ++J) {
+        const T* wj = pkw + (qbase + J) * kPkStride<T>;
+        T w[12];
+        #pragma unroll
+        for (int i = 0; i < 12; ++i) w[i] = wj[i];
+        T s0 = T(0), s1 = T(0);
+        #pragma unroll
+        for (int c = 0; c < 3; ++c)
+          #pragma unroll
+          for (int b = 0; b < 3; ++b) {
+            T t0 = T(0), t1 = T(0);
+            #pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              const int node = a + 3 * (b + 3 * c);
+              t0 += w[a] * F0[node];
+              t1 += w[a] * F1[node];
+            }
+            s0 += w[3 + b + 3 * c] * t0;
+            s1 += w[3 + b + 3 * c] * t1;
+          }
+        rsw[lane * kRsStride<T> + 2 * J] = s0;
+        rsw[lane * kRsStride<T> + 2 * J + 1] = s1;
+      }
+      wave_sync();
+      T eb[6];
+      #pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        eb[c] = rsw[(qbase + c) * kRsStride<T> + 2 * q];
+        eb[3 + c] = rsw[(qbase + c) * kRsStride<T> + 2 * q + 1];
+      }
+
+      // kick (Eq. (11))
+      const Kick<T> kq = boris_kick<T>(u[0], u[1], u[2], eb[0], eb[1], eb[2], eb[3], eb[4], eb[5], h);
+      const T un[3] = {u[0] + kq.dux, u[1] + kq.duy, u[2] + kq.duz};
+
+      // exchange (Eq. (12)) into the quad's registers, lane q taking component q
+      if constexpr (deposit) {
+        T* o = pkw + lane * kPkStride<T>;
+        o[12] = act ? pf * kq.dux : T(0);
+        o[13] = act ? pf * kq.duy : T(0);
+        o[14] = act ? pf * kq.duz : T(0);
+        o[15] = act ? ef * kq.dg : T(0);
+        wave_sync();
+        #pragma unroll
+        for (int J = 0; J < 4; ++J) {
+          const T* wj = pkw + (qbase + J) * kPkStride<T>;
+          T w[12];
+          #pragma unroll
+          for (int i = 0; i < 12; ++i) w[i] = wj[i];
+          const T mine = wj[12 + q];
+          #pragma unroll
+          for (int c = 0; c < 3; ++c)
+            #pragma unroll
+            for (int b = 0; b < 3; ++b) {
+              const T wq = w[3 + b + 3 * c] * mine;
+              #pragma unroll
+              for (int a = 0; a < 3; ++a) D[a + 3 * (b + 3 * c)] += w[a] * wq;
+            }
+        }
+      }
+      wave_sync();
+
+      // drift, then take a slot in the next buffer; every lane stores (idle lanes into
+      // the trash slots) so that each round issues the same memory operations
+      int hn[3];
+      const uint32_t e1 = drift3<T>(k, home, f, xa, un, hn, oxn, ofn);
+      err |= act ? e1 : 0u;
+      oj = trash_slot;
+      okind = act ? place(V, ttx, tty, ttz, cntB, cntD, sDcap, sDoff, k, hn, oj) : kToTrash;
+      if (okind == kToOverflow) okind = place_overflow(V, trash_slot, err, oj);
+      #pragma unroll
+      for (int d = 0; d < 3; ++d) oun[d] = un[d];
+      oid = id;
+      ocell = hn[0] + k.nx * (hn[1] + k.ny * hn[2]);
+    }
+    flush();
+    if (deposit && n > 0) {
+      #pragma unroll
+      for (int c = 0; c < 3; ++c)
+        #pragma unroll
+        for (int b = 0; b < 3; ++b)
+          #pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const int r = (lx + a) + kRegionEdge * ((ly + b) + kRegionEdge * (lz + c));
+            atomicAdd(&Acc[q][r], (double)D[a + 3 * (b + 3 * c)]);
+          }
+    }
+  }
+
+  // ------------------------------------------------------------ inbox: one packet per thread
+  {
+    const int nin = sPre[kDirs];
+    for (int i = threadIdx.x; i < nin; i += kThreads) {
+      int dir = 0;
+      #pragma unroll
+      for (int d = 1; d < kDirs; ++d) dir += (i >= sPre[d]) ? 1 : 0;
+      const int64_t j = tile * V.per_tile + sDoff[dir] + (i - sPre[dir]);
+      int home[3];
+      T f[3], u[3];
+      double xa[3];
+      int32_t id;
+      load_free<T>(V.iin, j, k, home, f, xa, u, id);
+      // region coordinates of node home-1 (the inbox only holds packets of this tile)
+      const int bx = home[0] - ttx * kCellTile, by = home[1] - tty * kCellTile, bz = home[2] - ttz * kCellTile;
+      T w[9];
+      weights3<M, T>(f[0], w);
+      weights3<M, T>(f[1], w + 3);
+      weights3<M, T>(f[2], w + 6);
+      T eb[6];
+      gather27<T>(w, [&](int node, int d) {
+        const int a = node % 3, b = (node / 3) % 3, c = node / 9;
+        return Fs[d][(bx + a) + kRegionEdge * ((by + b) + kRegionEdge * (bz + c))];
+      }, eb);
+      const Kick<T> kq = boris_kick<T>(u[0], u[1], u[2], eb[0], eb[1], eb[2], eb[3], eb[4], eb[5], h);
+      const T un[3] = {u[0] + kq.dux, u[1] + kq.duy, u[2] + kq.duz};
+      if constexpr (deposit) {
+        const T qv[4] = {pf * kq.dux, pf * kq.duy, pf * kq.duz, ef * kq.dg};
+        #pragma unroll
+        for (int c = 0; c < 3; ++c)
+          #pragma unroll
+          for (int b = 0; b < 3; ++b) {
+            const T wyz = w[3 + b] * w[6 + c];
+            #pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              const int r = (bx + a) + kRegionEdge * ((by + b) + kRegionEdge * (bz + c));
+              const T W = w[a] * wyz;
+              if (W != T(0)) {
+                #pragma unroll
+                for (int d = 0; d < 4; ++d) atomicAdd(&Acc[d][r], (double)(W * qv[d]));
+              }
+            }
+          }
+      }
+      int hn[3];
+      double xn[3];
+      T fn[3];
+      err |= drift3<T>(k, home, f, xa, un, hn, xn, fn);
+      int64_t j2 = trash_slot;
+      int kind = place(V, ttx, tty, ttz, cntB, cntD, sDcap, sDoff, k, hn, j2);
+      if (kind == kToOverflow) kind = place_overflow(V, trash_slot, err, j2);
+      Dst<T> dst = dst_select<T>(V, kind, j2);
+      if constexpr (!is_fp64<T>()) {
+        if (!dst.cell) dst.cell = V.trash.cell + trash_slot;
+      }
+      store_dst<T>(dst, xn, fn, un, id, hn[0] + k.nx * (hn[1] + k.ny * hn[2]));
+    }
+  }
+
+  // ------------------------------------------------------------ overflow list, shared by all workgroups
+  {
+    int nov = V.icnt_in[ntiles * kDirs];
+    nov = (int64_t)nov < V.ocap ? nov : (int)V.ocap;
+    const int n3[3] = {k.nx, k.ny, k.nz};
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < nov; i += (int64_t)gridDim.x * kThreads) {
+      int home[3];
+      T f[3], u[3];
+      double xa[3];
+      int32_t id;
+      load_free<T>(V.oin, i, k, home, f, xa, u, id);
+      T w[9];
+      weights3<M, T>(f[0], w);
+      weights3<M, T>(f[1], w + 3);
+      weights3<M, T>(f[2], w + 6);
+      int64_t nodes[27];
+      #pragma unroll
+      for (int c = 0; c < 3; ++c)
+        #pragma unroll
+        for (int b = 0; b < 3; ++b)
+          #pragma unroll
+          for (int a = 0; a < 3; ++a)
+            nodes[a + 3 * (b + 3 * c)] = wrapm(home[0] - 1 + a, n3[0]) +
+                (int64_t)k.nx * (wrapm(home[1] - 1 + b, n3[1]) + (int64_t)k.ny * wrapm(home[2] - 1 + c, n3[2]));
+      T eb[6];
+      gather27<T>(w, [&](int node, int d) { return d < 3 ? E[d * nc + nodes[node]] : B[(d - 3) * nc + nodes[node]]; },
+                  eb);
+      const Kick<T> kq = boris_kick<T>(u[0], u[1], u[2], eb[0], eb[1], eb[2], eb[3], eb[4], eb[5], h);
+      const T un[3] = {u[0] + kq.dux, u[1] + kq.duy, u[2] + kq.duz};
+      if constexpr (deposit) {
+        const T qv[4] = {pf * kq.dux, pf * kq.duy, pf * kq.duz, ef * kq.dg};
+        #pragma unroll
+        for (int c = 0; c < 3; ++c)
+          #pragma unroll
+          for (int b = 0; b < 3; ++b)
+            #pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              const T W = w[a] * w[3 + b] * w[6 + c];
+              if (W != T(0)) {
+                const int64_t g = nodes[a + 3 * (b + 3 * c)];
+                #pragma unroll
+                for (int d = 0; d < 3; ++d) atomicAdd(&dM[d * nc + g], (double)(W * qv[d]));
+                if (dE) atomicAdd(&dE[g], (double)(W * qv[3]));
+              }
+            }
+      }
+      int hn[3];
+      double xn[3];
+      T fn[3];
+      err |= drift3<T>(k, home, f, xa, un, hn, xn, fn);
+      int64_t j2 = trash_slot;
+      const int kind = place_overflow(V, trash_slot, err, j2);
+      Dst<T> dst = dst_select<T>(V, kind, j2);
+      if constexpr (!is_fp64<T>()) {
+        if (!dst.cell) dst.cell = V.trash.cell + trash_slot;
+      }
+      store_dst<T>(dst, xn, fn, un, id, hn[0] + k.nx * (hn[1] + k.ny * hn[2]));
+    }
+  }
+  if (err) set_status(k.status, err);
+  __syncthreads();
+
+  // ------------------------------------------------------------ outputs
+  if constexpr (deposit) {
+    double* out = V.halo + tile * 4 * kRegionCells;
+    const double* acc = &Acc[0][0];
+    for (int r = threadIdx.x; r < 4 * kRegionCells; r += kThreads) out[r] = acc[r];
+  }
+  if (threadIdx.x < kCellTileCells) {
+    const int lx = threadIdx.x & 3, ly = (threadIdx.x >> 2) & 3, lz = threadIdx.x >> 4;
+    const int gx = ttx * kCellTile + lx, gy = tty * kCellTile + ly, gz = ttz * kCellTile + lz;
+    if (gx < k.nx && gy < k.ny && gz < k.nz) {
+      const int v = cntB[threadIdx.x];
+      V.bcnt_out[gx + (int64_t)k.nx * (gy + (int64_t)k.ny * gz)] = v < V.cap ? v : V.cap;
+    }
+  } else if (threadIdx.x >= 64 && threadIdx.x < 64 + kDirs) {
+    // count of part `dir` of the inbox of the tile at offset dir; this workgroup is
+    // that part's only writer
+    const int dir = threadIdx.x - 64;
+    const int sx = dir % 3 - 1, sy = (dir / 3) % 3 - 1, sz = dir / 9 - 1;
+    const int64_t t = wrapm(ttx + sx, V.ntx) +
+                      (int64_t)V.ntx * (wrapm(tty + sy, V.nty) + (int64_t)V.nty * wrapm(ttz + sz, V.ntz));
+    const int v = cntD[dir];
+    V.icnt_out[t * kDirs + dir] = v < sDcap[dir] ? v : sDcap[dir];
+  }
+}
+
+// After a step: add the per-tile exchange accumulators into the grid (a cell takes
+// every region slot, of its own tile and of neighbouring tiles' halos, that maps onto
+// it) and clear the overflow counter of the buffer the step consumed.
+__global__ void cells_post_kernel(StepView V, double* __restrict__ dM, double* __restrict__ dE, RunConsts k) {
+  const int64_t nc = k.ncells;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) V.icnt_in[V.ntiles * kDirs] = 0;
+  if (!dM) return;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += stride) {
+    const int g[3] = {(int)(c % k.nx), (int)((c / k.nx) % k.ny), (int)(c / ((int64_t)k.nx * k.ny))};
+    const int n3[3] = {k.nx, k.ny, k.nz};
+    const int nt[3] = {V.ntx, V.nty, V.ntz};
+    // per axis: (tile, region index) pairs whose region slot is this cell
+    int tl[3][8], rl[3][8], cnt[3] = {0, 0, 0};
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int t0 = g[d] / kCellTile;
+      for (int dt = -1; dt <= 1; ++dt) {
+        const int t = wrapm(t0 + dt, nt[d]);
+        bool dup = false;
+        for (int e = 0; e < cnt[d]; ++e) dup |= tl[d][e] == t;
+        if (dup) continue;
+        for (int r = 0; r < kRegionEdge; ++r)
+          if (wrapm(t * kCellTile - 1 + r, n3[d]) == g[d] && cnt[d] < 8) {
+            tl[d][cnt[d]] = t;
+            rl[d][cnt[d]] = r;
+            ++cnt[d];
+          }
+      }
+    }
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int a = 0; a < cnt[0]; ++a)
+      for (int b = 0; b < cnt[1]; ++b)
+        for (int e = 0; e < cnt[2]; ++e) {
+          const int64_t t = tl[0][a] + (int64_t)V.ntx * (tl[1][b] + (int64_t)V.nty * tl[2][e]);
+          const int r = rl[0][a] + kRegionEdge * (rl[1][b] + kRegionEdge * rl[2][e]);
+          const double* src = V.halo + t * 4 * kRegionCells + r;
+          #pragma unroll
+          for (int d = 0; d < 4; ++d) s[d] += src[d * kRegionCells];
+        }
+    dM[c] += s[0];
+    dM[nc + c] += s[1];
+    dM[2 * nc + c] += s[2];
+    if (dE) dE[c] += s[3];
+  }
+}
+
+// Slot of this lane in a per-key counter, one atomic per run of equal keys among
+// consecutive lanes (keys < 0 take no slot).
+__device__ __forceinline__ int run_slot(int32_t* counters, int key) {
+  const int lane = __lane_id();
+  const int prev = __shfl_up(key, 1);
+  const bool head = (lane == 0) || (prev != key);
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+  const int start = 63 - __clzll(heads & upto);
+  const unsigned long long after = heads & ~upto;
+  const int end = after ? (__ffsll((long long)after) - 1) : 64;
+  int base = 0;
+  if (lane == start && key >= 0) base = atomicAdd(&counters[key], end - start);
+  base = __shfl(base, start);
+  return key >= 0 ? base + (lane - start) : -1;
+}
+
+// Caller packets -> buffer 0: bucket slot from a per-cell counter, else the self part
+// of the tile's inbox, else the overflow list.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) cells_build_kernel(Packets<T> P, CellLists L, RunConsts k) {
+  const int n3[3] = {k.nx, k.ny, k.nz};
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < P.np; base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = base + threadIdx.x;
+    int key = -1;
+    int h[3] = {0, 0, 0};
+    T f[3] = {T(0), T(0), T(0)}, u[3] = {T(0), T(0), T(0)};
+    double x[3] = {0.0, 0.0, 0.0};
+    if (i < P.np) {
+      if constexpr (is_fp64<T>()) {
+        #pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          x[d] = P.x[d * P.np + i];
+          h[d] = wrapm((int)floor(x[d] * k.inv_dx), n3[d]);
+        }
+      } else {
+        int c = P.cell[i];
+        c = c < 0 ? 0 : (c >= k.ncells ? k.ncells - 1 : c);
+        cell_coords(c, k, h);
+        #pragma unroll
+        for (int d = 0; d < 3; ++d) f[d] = P.off[d * P.np + i];
+      }
+      #pragma unroll
+      for (int d = 0; d < 3; ++d) u[d] = P.u[d * P.np + i];
+      key = h[0] + k.nx * (h[1] + k.ny * h[2]);
+    }
+    const int slot = run_slot(L.bcnt[0], key);
+    if (i >= P.np) continue;
+    const int32_t id = P.id[i];
+    Dst<T> dst;
+    if (slot < L.cap) {
+      dst = dst_of<T>(L.bucket[0], bucket_index(h, slot, L.ntx, L.nty, L.cap));
+    } else {
+      const int64_t t = h[0] / kCellTile + (int64_t)L.ntx * (h[1] / kCellTile + (int64_t)L.nty * (h[2] / kCellTile));
+      const int is = atomicAdd(&L.icnt[0][t * kDirs + kSelfDir], 1);
+      if (is < L.dcap[kSelfDir]) {
+        dst = dst_of<T>(L.inbox[0], t * L.per_tile + L.doff[kSelfDir] + is);
+      } else {
+        const int os = atomicAdd(&L.icnt[0][L.ntiles * kDirs], 1);
+        if ((int64_t)os < L.ocap) {
+          dst = dst_of<T>(L.ovf[0], os);
+        } else {
+          set_status(k.status, ERR_TILE);
+          continue;
+        }
+      }
+    }
+    if constexpr (!is_fp64<T>()) {
+      if (!dst.cell) dst.cell = L.trash.cell + (blockIdx.x & 7) * kThreads + threadIdx.x;
+    }
+    store_dst<T>(dst, x, f, u, id, key);
+  }
+}
+
+// Clamped occupancy of every store, in compaction order: cells, tile directions, overflow.
+__global__ void cells_counts_kernel(CellLists L, int64_t nc, int32_t* __restrict__ out) {
+  const int cur = L.cur;
+  const int64_t ni = L.ntiles * kDirs;
+  const int64_t n = nc + ni + 1;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    int v, cap;
+    if (i < nc) {
+      v = L.bcnt[cur][i];
+      cap = L.cap;
+    } else if (i < nc + ni) {
+      v = L.icnt[cur][i - nc];
+      const int dir = (int)((i - nc) % kDirs);
+      cap = 0;
+      #pragma unroll
+      for (int d = 0; d < kDirs; ++d) cap = (dir == d) ? L.dcap[d] : cap;
+    } else {
+      v = L.icnt[cur][ni];
+      cap = (int)L.ocap;
+    }
+    out[i] = v < cap ? v : cap;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void copy_out(const Packets<T>& P, const SlotArrays& S, int64_t j, int64_t o,
+                                         int32_t cell) {
+  const T* su = (const T*)S.u;
+  #pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if constexpr (is_fp64<T>()) P.x[d * P.np + o] = S.x[d * S.stride + j];
+    else P.off[d * P.np + o] = S.off[d * S.stride + j];
+    P.u[d * P.np + o] = su[d * S.stride + j];
+  }
+  if constexpr (!is_fp64<T>()) P.cell[o] = cell;
+  P.id[o] = S.id[j];
+}
+
+// Every occupied slot of buffer cur -> caller arrays at its prefix-sum offset.
+template <typename T>
+__global__ void cells_compact_kernel(Packets<T> P, CellLists L, const int32_t* __restrict__ offs, RunConsts k) {
+  const int cur = L.cur;
+  const int64_t nc = k.ncells;
+  const int64_t nslot = L.ntiles * L.cap * kCellTileCells, islots = L.ntiles * L.per_tile;
+  const int64_t total = nslot + islots + L.ocap;
+  const int64_t obase = nc + L.ntiles * kDirs;
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < total; s += (int64_t)gridDim.x * blockDim.x) {
+    if (s < nslot) {
+      const int lc = (int)(s % kCellTileCells);
+      const int64_t ts = s / kCellTileCells;
+      const int sl = (int)(ts % L.cap);
+      const int64_t t = ts / L.cap;
+      const int gx = (int)(t % L.ntx) * kCellTile + (lc & 3), gy = (int)((t / L.ntx) % L.nty) * kCellTile + ((lc >> 2) & 3),
+                gz = (int)(t / ((int64_t)L.ntx * L.nty)) * kCellTile + (lc >> 4);
+      if (gx >= k.nx || gy >= k.ny || gz >= k.nz) continue;
+      const int64_t c = gx + (int64_t)k.nx * (gy + (int64_t)k.ny * gz);
+      if (sl >= offs[c + 1] - offs[c]) continue;
+      copy_out<T>(P, L.bucket[cur], s, offs[c] + sl, (int32_t)c);
+    } else if (s < nslot + islots) {
+      const int64_t si = s - nslot;
+      const int64_t t = si / L.per_tile;
+      const int r = (int)(si - t * L.per_tile);
+      int dir = 0, start = 0;
+      #pragma unroll
+      for (int d = 1; d < kDirs; ++d)
+        if (r >= L.doff[d]) {
+          dir = d;
+          start = L.doff[d];
+        }
+      const int sl = r - start;
+      const int64_t e = nc + t * kDirs + dir;
+      if (sl >= offs[e + 1] - offs[e]) continue;
+      const int32_t cell = is_fp64<T>() ? 0 : L.inbox[cur].cell[si];
+      copy_out<T>(P, L.inbox[cur], si, offs[e] + sl, cell);
+    } else {
+      const int64_t so = s - nslot - islots;
+      if (so >= offs[obase + 1] - offs[obase]) continue;
+      const int32_t cell = is_fp64<T>() ? 0 : L.ovf[cur].cell[so];
+      copy_out<T>(P, L.ovf[cur], so, offs[obase] + so, cell);
+    }
+  }
+}
+
+// offs[n] = offs[n-1] + counts[n-1] (total of an exclusive scan of n counts)
+__global__ void scan_total_kernel(int32_t* offs, const int32_t* counts, int64_t n) {
+  offs[n] = offs[n - 1] + counts[n - 1];
+}
+
+__global__ void zero_i32(int32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+inline int grid_for(int64_t n) {
+  int64_t g = (n + kThreads - 1) / kThreads;
+  return (int)(g < 1 ? 1 : (g > 65536 ? 65536 : g));
+}
+
+// Bump allocator over a (possibly notional) base address; every piece 256-aligned.
+struct Carver {
+  uintptr_t p;
+  char* take(size_t n) {
+    char* at = (char*)p;
+    p += (n + 255) / 256 * 256;
+    return at;
+  }
+};
+
+SlotArrays carve_slots(Carver& cv, int64_t nslots, bool f32, bool with_cell) {
+  SlotArrays S;
+  S.stride = nslots;
+  const size_t n = (size_t)nslots;
+  S.x = f32 ? nullptr : (double*)cv.take(3 * n * sizeof(double));
+  S.off = f32 ? (float*)cv.take(3 * n * sizeof(float)) : nullptr;
+  S.cell = (f32 && with_cell) ? (int32_t*)cv.take(n * sizeof(int32_t)) : nullptr;
+  S.u = (void*)cv.take(3 * n * (f32 ? sizeof(float) : sizeof(double)));
+  S.id = (int32_t*)cv.take(n * sizeof(int32_t));
+  return S;
+}
+
+CellLists carve(int nx, int ny, int nz, int64_t np, int precision, uintptr_t base, size_t* bytes) {
+  CellLists L;
+  const int64_t ncells = (int64_t)nx * ny * nz;
+  L.ntx = (nx + kCellTile - 1) / kCellTile;
+  L.nty = (ny + kCellTile - 1) / kCellTile;
+  L.ntz = (nz + kCellTile - 1) / kCellTile;
+  L.ntiles = (int64_t)L.ntx * L.nty * L.ntz;
+  // a cell holds Poisson-like counts around the mean: twice the mean plus a margin
+  // keeps bucket overflow rare.  Inbox parts by the number of tile faces crossed:
+  // self (full buckets) and faces take four buckets' worth, edges one, corners a
+  // quarter.
+  const int64_t mean = (np + ncells - 1) / ncells;
+  L.cap = (int)(2 * mean + 16);
+  int off = 0;
+  for (int d = 0; d < kDirs; ++d) {
+    const int axes = (d % 3 != 1) + ((d / 3) % 3 != 1) + (d / 9 != 1);
+    const int c = axes <= 1 ? 4 * L.cap : axes == 2 ? L.cap : L.cap / 4 + 8;
+    L.dcap[d] = c;
+    L.doff[d] = off;
+    off += c;
+  }
+  L.doff[kDirs] = off;
+  L.per_tile = off;
+  L.ocap = np > 0 ? np : 1;
+  const bool f32 = precision == 1;
+  Carver cv{(base + 255) / 256 * 256};
+  const uintptr_t start = cv.p;
+  for (int b = 0; b < 2; ++b) {
+    L.bucket[b] = carve_slots(cv, L.ntiles * L.cap * kCellTileCells, f32, false);
+    L.inbox[b] = carve_slots(cv, L.ntiles * L.per_tile, f32, true);
+    L.ovf[b] = carve_slots(cv, L.ocap, f32, true);
+    L.bcnt[b] = (int32_t*)cv.take((size_t)ncells * sizeof(int32_t));
+    L.icnt[b] = (int32_t*)cv.take((size_t)(L.ntiles * kDirs + 1) * sizeof(int32_t));
+  }
+  L.trash = carve_slots(cv, kTrashSlots, f32, true);
+  L.halo = (double*)cv.take((size_t)L.ntiles * 4 * kRegionCells * sizeof(double));
+  const int64_t nscan = ncells + L.ntiles * kDirs + 1;
+  // counts (nscan), offsets (nscan + 1), scan temporaries
+  L.scan = (int32_t*)cv.take((size_t)(2 * nscan + 1 + (int64_t)exclusive_scan_tmp_ints(nscan)) * sizeof(int32_t));
+  L.cur = 0;
+  if (bytes) *bytes = (size_t)(cv.p - start) + 256;
+  return L;
+}
+
+}  // namespace
+
+size_t cell_list_bytes(int nx, int ny, int nz, int64_t np, int precision) {
+  size_t bytes = 0;
+  (void)carve(nx, ny, nz, np, precision, 0, &bytes);
+  return bytes;
+}
+
+CellLists cell_list_carve(int nx, int ny, int nz, int64_t np, int precision, char* base) {
+  return carve(nx, ny, nz, np, precision, (uintptr_t)base, nullptr);
+}
+
+int64_t cell_list_scan_entries(int nx, int ny, int nz) {
+  const int64_t nt = (int64_t)((nx + kCellTile - 1) / kCellTile) * ((ny + kCellTile - 1) / kCellTile) *
+                     ((nz + kCellTile - 1) / kCellTile);
+  return (int64_t)nx * ny * nz + nt * kDirs + 1;
+}
+
+template <typename T>
+hipError_t launch_cells_build(const Packets<T>& P, CellLists& L, const RunConsts& k, hipStream_t s) {
+  L.cur = 0;
+  const int64_t ni = L.ntiles * kDirs + 1;
+  hipLaunchKernelGGL(zero_i32, dim3(grid_for(k.ncells)), dim3(kThreads), 0, s, L.bcnt[0], (int64_t)k.ncells);
+  hipLaunchKernelGGL(zero_i32, dim3(grid_for(ni)), dim3(kThreads), 0, s, L.icnt[0], ni);
+  hipLaunchKernelGGL(zero_i32, dim3(grid_for(ni)), dim3(kThreads), 0, s, L.icnt[1], ni);
+  if (P.np > 0) hipLaunchKernelGGL(cells_build_kernel<T>, dim3(grid_for(P.np)), dim3(kThreads), 0, s, P, L, k);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cells_step(int shape, CellLists& L, const T* E, const T* B, double* dM, double* dE,
+                             const RunConsts& k, hipStream_t s, hipEvent_t before, hipEvent_t after) {
+  const StepView V = step_view(L);
+  if (before) (void)hipEventRecord(before, s);
+  const dim3 grid((unsigned)L.ntiles), block(kThreads);
+  if (shape == kShapeCIC) {
+    if (dM) hipLaunchKernelGGL((cells_step_kernel<2, T, true>), grid, block, 0, s, V, E, B, dM, dE, k);
+    else hipLaunchKernelGGL((cells_step_kernel<2, T, false>), grid, block, 0, s, V, E, B, dM, dE, k);
+  } else {
+    if (dM) hipLaunchKernelGGL((cells_step_kernel<3, T, true>), grid, block, 0, s, V, E, B, dM, dE, k);
+    else hipLaunchKernelGGL((cells_step_kernel<3, T, false>), grid, block, 0, s, V, E, B, dM, dE, k);
+  }
+  if (after) (void)hipEventRecord(after, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t work = dM ? (int64_t)k.ncells : 1;
+  hipLaunchKernelGGL(cells_post_kernel, dim3(grid_for(work)), dim3(kThreads), 0, s, V, dM, dE, k);
+  L.cur = 1 - L.cur;
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cells_compact(const Packets<T>& P, CellLists& L, const RunConsts& k, hipStream_t s) {
+  const int64_t nc = k.ncells;
+  const int64_t nscan = nc + L.ntiles * kDirs + 1;
+  int32_t* counts = L.scan;
+  int32_t* offs = counts + nscan;
+  int32_t* tmp = offs + nscan + 1;
+  hipLaunchKernelGGL(cells_counts_kernel, dim3(grid_for(nscan)), dim3(kThreads), 0, s, L, nc, counts);
+  hipError_t e = launch_exclusive_scan(counts, offs, nscan, tmp, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(scan_total_kernel, dim3(1), dim3(1), 0, s, offs, counts, nscan);
+  const int64_t total = L.ntiles * L.cap * kCellTileCells + L.ntiles * L.per_tile + L.ocap;
+  hipLaunchKernelGGL(cells_compact_kernel<T>, dim3(grid_for(total)), dim3(kThreads), 0, s, P, L, offs, k);
+  return hipGetLastError();
+}
+
+#define RSOL_CELLS_INSTANTIATE(T)                                                                                  \
+  template hipError_t launch_cells_build<T>(const Packets<T>&, CellLists&, const RunConsts&, hipStream_t);         \
+  template hipError_t launch_cells_step<T>(int, CellLists&, const T*, const T*, double*, double*, const RunConsts&, \
+                                           hipStream_t, hipEvent_t, hipEvent_t);                                   \
+  template hipError_t launch_cells_compact<T>(const Packets<T>&, CellLists&, const RunConsts&, hipStream_t);
+
+RSOL_CELLS_INSTANTIATE(double)
+RSOL_CELLS_INSTANTIATE(float)
+
+}  // namespace rsol

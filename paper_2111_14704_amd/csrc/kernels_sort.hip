@@ -288,6 +288,20 @@ hipError_t launch_sort(const Packets<T>& src, const Packets<T>& dst, const RunCo
   return hipGetLastError();
 }
 
+size_t exclusive_scan_tmp_ints(int64_t n) { return (size_t)((n + kScanChunk - 1) / kScanChunk) + 16; }
+
+hipError_t launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nblk = (n + kScanChunk - 1) / kScanChunk;
+  if (nblk > kScanChunk) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(scan_chunk_kernel, dim3((unsigned)nblk), dim3(kScanThreads), 0, s, in, out, n, tmp);
+  if (nblk > 1) {
+    hipLaunchKernelGGL(scan_chunk_kernel, dim3(1), dim3(kScanThreads), 0, s, tmp, tmp, nblk, (int32_t*)nullptr);
+    hipLaunchKernelGGL(add_block_offsets_kernel, dim3((unsigned)nblk), dim3(256), 0, s, out, n, tmp);
+  }
+  return hipGetLastError();
+}
+
 template hipError_t launch_sort<double>(const Packets<double>&, const Packets<double>&, const RunConsts&,
                                         const Tiling&, int32_t*, hipStream_t);
 template hipError_t launch_sort<float>(const Packets<float>&, const Packets<float>&, const RunConsts&,

@@ -9,6 +9,7 @@
 
 #include "../../include/rsol.h"
 #include "rsol_adjoint.hpp"
+#include "rsol_cells.hpp"
 #include "rsol_launch.hpp"
 #include "rsol_sort.hpp"
 #include "rsol_step.hpp"
@@ -28,6 +29,7 @@ struct rsol_ctx {
   void* perm;           // permuted packet copy written by the sort
   float* E32;
   float* B32;
+  char* cells_base;     // cell-list buffers of the default step path
   // registered caller arrays
   const double* E;
   const double* B;
@@ -39,6 +41,7 @@ struct rsol_ctx {
   int steps_since_sort;
   Tiling tiling;
   StepPlan plan;
+  CellLists cells;
   std::string err;
   // optional launch timing: event pairs around every step / sort launch
   bool timing;
@@ -128,6 +131,7 @@ size_t layout(const rsol_params& p, int64_t np, rsol_ctx* h) {
     e32 = take(sizeof(float) * 3 * (size_t)n_cells(p));
     b32 = take(sizeof(float) * 3 * (size_t)n_cells(p));
   }
+  const size_t cl = take(cell_list_bytes(p.nx, p.ny, p.nz, np, p.precision));
   if (h) {
     char* s = h->scratch;
     h->status = (uint32_t*)(s + st);
@@ -136,6 +140,7 @@ size_t layout(const rsol_params& p, int64_t np, rsol_ctx* h) {
     h->perm = (void*)(s + pm);
     h->E32 = fp32(p) ? (float*)(s + e32) : nullptr;
     h->B32 = fp32(p) ? (float*)(s + b32) : nullptr;
+    h->cells_base = s + cl;
   }
   return off;
 }
@@ -148,6 +153,7 @@ std::string validate(const rsol_params* p, int64_t np) {
   if (p->precision != RSOL_FP64 && p->precision != RSOL_FP32) return "precision must be RSOL_FP64 or RSOL_FP32";
   if (p->sort_every < 1 || p->sort_every > 8) return "sort_every must be in 1..8";
   if (p->reserved != 0) return "reserved must be 0";
+  if (p->flags & ~(RSOL_FLAG_KEEP_ORDER | RSOL_FLAG_TILED)) return "unknown flag bits";
   if (!(p->dx > 0)) return "dx must be > 0";
   if (!(p->c > 0) || !(p->c_tilde > 0) || p->c_tilde > p->c) return "need 0 < c_tilde <= c";
   if (!isfinite(p->qomc)) return "qomc must be finite";
@@ -158,6 +164,8 @@ std::string validate(const rsol_params* p, int64_t np) {
   const Tiling t = tiling_for(*p);
   if (t.nbins() > max_sort_bins()) return "grid too large for the sort";
   if (t.cells_per_tile > max_cells_per_tile()) return "tile larger than the sort supports";
+  const int64_t ntiles4 = (int64_t)((p->nx + 3) / 4) * ((p->ny + 3) / 4) * ((p->nz + 3) / 4);
+  if (n_cells(*p) + ntiles4 + 1 > max_sort_bins()) return "grid too large for the cell lists";
   return "";
 }
 
@@ -282,8 +290,36 @@ int do_sort(rsol_ctx* h, bool copy) {
   return RSOL_OK;
 }
 
+// Default path: caller arrays -> cell buckets, nsteps cell-list steps, buckets ->
+// caller arrays (cell-major).
+template <typename T>
+int do_step_cells(rsol_ctx* h, int32_t nsteps, double* dM, double* dE) {
+  const RunConsts k = consts(h);
+  const Packets<T> P = caller_packets<T>(h);
+  auto ev = timed_begin(h);
+  RSOL_HIP(h, launch_cells_build<T>(P, h->cells, k, h->stream), "cell lists (build)");
+  timed_end(h, ev, true);
+  for (int32_t s = 0; s < nsteps; ++s) {
+    std::pair<hipEvent_t, hipEvent_t> pr(nullptr, nullptr);
+    if (h->timing) {
+      pr.first = take_event(h);
+      pr.second = take_event(h);
+    }
+    RSOL_HIP(h, launch_cells_step<T>(h->p.shape, h->cells, field_E<T>(h), field_B<T>(h), dM, dE, k, h->stream,
+                                     pr.first, pr.second),
+             "step (cells)");
+    if (pr.first && pr.second) h->ev_step.push_back(pr);
+  }
+  ev = timed_begin(h);
+  RSOL_HIP(h, launch_cells_compact<T>(P, h->cells, k, h->stream), "cell lists (compact)");
+  timed_end(h, ev, true);
+  h->sorted_valid = false;
+  return RSOL_OK;
+}
+
 template <typename T>
 int do_step(rsol_ctx* h, int32_t nsteps, double* dM, double* dE) {
+  if ((h->p.flags & (RSOL_FLAG_KEEP_ORDER | RSOL_FLAG_TILED)) == 0) return do_step_cells<T>(h, nsteps, dM, dE);
   const RunConsts k = consts(h);
   const bool global = (h->p.flags & RSOL_FLAG_KEEP_ORDER) != 0 || !h->plan.tiled;
   for (int32_t s = 0; s < nsteps; ++s) {
@@ -344,6 +380,7 @@ int rsol_init(const rsol_params* p, int64_t n_particles, void* stream, void* scr
   h->plan = plan_step(p->nx, p->ny, p->nz, p->shape, p->precision, p->sort_every, p->courant);
   h->tiling = make_tiling(p->nx, p->ny, p->nz, h->plan.tx, h->plan.ty, h->plan.tz);
   layout(*p, n_particles, h);
+  h->cells = cell_list_carve(p->nx, p->ny, p->nz, n_particles, p->precision, h->cells_base);
   hipError_t e = launch_fill_u32(h->status, 0u, 4, h->stream);
   if (e != hipSuccess) {
     int rc = hip_fail(nullptr, e, "init status");
@@ -566,7 +603,7 @@ int rsol_moments(rsol_handle h, double* rho, double* P, double* e) {
 
 int rsol_set_flags(rsol_handle h, int32_t flags) {
   if (int rc = need(h, false, false)) return rc;
-  if (flags & ~RSOL_FLAG_KEEP_ORDER) return fail(h, RSOL_EINVAL, "unknown flag bits");
+  if (flags & ~(RSOL_FLAG_KEEP_ORDER | RSOL_FLAG_TILED)) return fail(h, RSOL_EINVAL, "unknown flag bits");
   h->p.flags = flags;
   return RSOL_OK;
 }
@@ -655,7 +692,7 @@ int rsol_check(rsol_handle h) {
   RSOL_HIP(h, hipStreamSynchronize(h->stream), "status sync");
   RSOL_HIP(h, launch_fill_u32(h->status, 0u, 1, h->stream), "status clear");
   if (word & ERR_NAN) return fail(h, RSOL_ENAN, "non-finite packet momentum");
-  if (word & ERR_TILE) return fail(h, RSOL_ETILE, "a packet left its tile's staged region between re-sorts");
+  if (word & ERR_TILE) return fail(h, RSOL_ETILE, "a packet left its tile's staged region between re-sorts (tiled path) or the cell lists overflowed");
   if (word & ERR_COURANT) return fail(h, RSOL_ECOURANT, "a packet moved further than the per-step bound");
   return RSOL_OK;
 }

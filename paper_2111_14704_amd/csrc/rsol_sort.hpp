@@ -36,6 +36,11 @@ size_t sort_scratch_ints(const Tiling& t, int64_t np);
 int64_t max_sort_bins();
 int max_cells_per_tile();
 
+// Exclusive prefix sum of n int32 values (in == out allowed); tmp holds
+// exclusive_scan_tmp_ints(n) words.  n is at most max_sort_bins().
+size_t exclusive_scan_tmp_ints(int64_t n);
+hipError_t launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, hipStream_t s);
+
 // Sort src into dst by tile, rank-major inside each tile.  ints = scratch of
 // sort_scratch_ints words; on return ints[0..nbins] holds the exclusive bin offsets
 // (ints[nbins] = np), so tile t occupies [ints[t*cells_per_tile], ints[(t+1)*cells_per_tile]).

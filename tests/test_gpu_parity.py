@@ -88,7 +88,10 @@ def _compare(w, got, ref, tol, label):
     return errs
 
 
-@pytest.mark.parametrize("flags", [0, 1], ids=["tiled", "global"])
+PATHS = dict(cells=0, tiled=2, globl=1)
+
+
+@pytest.mark.parametrize("flags", [0, 2, 1], ids=["cells", "tiled", "global"])
 def test_config1_fp64_100_steps(flags):
     """Workload 1 (16^3, 8 ppc, CIC, c/c_tilde = 10, 100 steps) on the FP64 path vs the oracle."""
     w = make_workload(1)
@@ -99,26 +102,59 @@ def test_config1_fp64_100_steps(flags):
     _compare(w, got, ref, 1e-10, f"config1 fp64 flags={flags}")
 
 
-def test_config3_fp32_100_steps():
+@pytest.mark.parametrize("flags", [0, 2], ids=["cells", "tiled"])
+def test_config3_fp32_100_steps(flags):
     """Workload 3 (precision form of workload 1: int32 cell + FP32 offset, FP32 push,
-    FP32 per-workgroup deposit, FP64 global accumulation) vs the FP64 oracle."""
+    FP32 per-cell / per-workgroup deposit, FP64 global accumulation) vs the FP64 oracle."""
     w = make_workload(3)
-    _say("config3 fp32")
-    got, _ = _gpu_rollout(w, w.nsteps)
+    _say(f"config3 fp32 flags={flags}")
+    got, _ = _gpu_rollout(w, w.nsteps, flags=flags)
     ref = _oracle_rollout(w, w.nsteps, got["dt"])
-    _compare(w, got, ref, 1e-5, "config3 fp32")
+    _compare(w, got, ref, 1e-5, f"config3 fp32 flags={flags}")
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
-@pytest.mark.parametrize("sort_every", [1, 4, 8])
-def test_alfven_tsc_small(precision, tol, sort_every):
+@pytest.mark.parametrize("path,sort_every", [("cells", 4), ("tiled", 1), ("tiled", 4), ("tiled", 8)])
+def test_alfven_tsc_small(precision, tol, path, sort_every):
     """Workload-2 recipe at 16^3 x 8 ppc (TSC, E != 0, boosted power-law momenta): several
-    tiles, full oracle comparison, for several re-sort intervals (halo 1, 2, 4)."""
+    tiles, full oracle comparison; cell-list path, and the tiled path for several re-sort
+    intervals (halo 1, 2, 4)."""
     w = make_workload(2, n=16, ppc=8, nsteps=60, precision=precision)
-    _say(f"alfven16 {precision} sort_every={sort_every}")
-    got, _ = _gpu_rollout(w, 60, sort_every=sort_every)
+    _say(f"alfven16 {precision} {path} sort_every={sort_every}")
+    got, _ = _gpu_rollout(w, 60, sort_every=sort_every, flags=PATHS[path])
     ref = _oracle_rollout(w, 60, got["dt"])
-    _compare(w, got, ref, tol, f"alfven16 {precision} K={sort_every}")
+    _compare(w, got, ref, tol, f"alfven16 {precision} {path} K={sort_every}")
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_cells_overflow_stores(precision, tol):
+    """Cell-list path with a clustered start: 1500 of 2012 packets in one cell of an 8^3
+    grid overfill that cell's bucket (capacity 2*ceil(np/cells)+16 = 24) and its tile's
+    inbox (16*24+256 = 640), so packets also take the grid-wide overflow list; all three
+    stores must give the oracle's result, several steps in a row, in one rsol_step call
+    and one step per call.  A packet's arithmetic does not depend on the store it is read
+    from, so the two runs agree bit for bit on the packets; only the deposit sums run in
+    another order."""
+    w = make_workload(2, n=8, ppc=1, nsteps=12, precision=precision)
+    rng = np.random.default_rng(5)
+    cluster = 2.0 + rng.random((3, 1500))      # all in cell (2, 2, 2)
+    w.x = np.concatenate([w.x, cluster], axis=1)
+    w.u = np.concatenate([w.u, rng.standard_normal((3, 1500)) * 30.0], axis=1)
+    w.ids = np.arange(w.x.shape[1], dtype=np.int32)
+    _say(f"cells overflow {precision} np={w.x.shape[1]}")
+    got, _ = _gpu_rollout(w, 12)
+    ref = _oracle_rollout(w, 12, got["dt"])
+    _compare(w, got, ref, tol, f"cells overflow {precision}")
+    from paper_2111_14704_amd.sim import Simulation
+    sim = Simulation.from_workload(w, dt=got["dt"])
+    dM = sim.zeros_grid(3)
+    dE = sim.zeros_grid(1)[0]
+    sim.step(12, dM, dE)
+    sim.handle.rsol_check()
+    x, u = sim.state_by_id()
+    assert np.array_equal(x, got["x"]) and np.array_equal(u, got["u"])
+    # deposit sums run in a different order (bucket slots come from atomics)
+    assert rel_l2(dM.cpu().numpy(), got["dM_sum"]) <= (1e-12 if precision == "fp64" else 1e-6)
 
 
 @pytest.mark.parametrize("n", [(10, 6, 7), (4, 4, 4), (3, 5, 2)])
@@ -142,10 +178,11 @@ def test_ragged_and_tiny_grids(n, shape):
     w.B[1] = 0.05 * np.sin(2 * np.pi * np.arange(nx) / nx)[None, None, :]
     w.u_gas = np.zeros((3, nz, ny, nx))
     w.u_gas[2] = 0.3 * np.cos(2 * np.pi * np.arange(ny) / ny)[None, :, None]
-    _say(f"ragged {n} {shape}")
-    got, _ = _gpu_rollout(w, 20, sort_every=4)
-    ref = _oracle_rollout(w, 20, got["dt"])
-    _compare(w, got, ref, 1e-10, f"ragged {n} {shape}")
+    for path in ("cells", "tiled"):
+        _say(f"ragged {n} {shape} {path}")
+        got, _ = _gpu_rollout(w, 20, sort_every=4, flags=PATHS[path])
+        ref = _oracle_rollout(w, 20, got["dt"])
+        _compare(w, got, ref, 1e-10, f"ragged {n} {shape} {path}")
 
 
 def test_unfused_phases_match_oracle():
@@ -226,7 +263,7 @@ def test_sort_is_a_permutation_into_tile_segments(precision):
 
 
 def test_exchange_conservation_at_full_size_config2():
-    """Workload 2 at full size (64^3 x 64 ppc, 16.8M packets, TSC): one tiled FP64 step;
+    """Workload 2 at full size (64^3 x 64 ppc, 16.8M packets, TSC): one cell-list FP64 step;
     sum over the grid of the deposited momentum equals -(c/c_tilde) M c sum du over the
     packets (Sec. 2: rho u + (c/c_tilde) P conserved), computed from the GPU's own states."""
     torch = _torch()
@@ -256,7 +293,7 @@ def test_exchange_conservation_at_full_size_config2():
                                                     (4, "fp64", 100, 1e-10)])
 def test_full_size_sampled_trajectories(k, precision, nsteps, tol):
     """Full-size workloads 2 and 4 in the launch configuration the benchmark times
-    (tiled step, re-sort every 4 steps): after all steps, 2048 packets sampled by id are
+    (cell-list step): after all steps, 2048 packets sampled by id are
     re-run one by one in the oracle (static fields make packets independent)."""
     w = make_workload(k, precision=precision)
     _say(f"full-size workload {k} {precision} {nsteps} steps, {w.n_particles} packets")
