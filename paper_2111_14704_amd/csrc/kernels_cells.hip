@@ -131,11 +131,10 @@ struct StepView {
   int64_t ntiles;
   int cap, per_tile;
   int64_t ocap;
+  int64_t ib0, ov0, tr0;
   int dcap[kDirs];
   int doff[kDirs + 1];
-  SlotArrays bin, iin, oin;
-  SlotArrays bout, iout, oout;
-  SlotArrays trash;
+  SlotArrays in, out;
   const int32_t* bcnt_in;
   int32_t* bcnt_out;
   int32_t* icnt_in;   // [ntiles*kDirs] then the overflow count
@@ -153,15 +152,13 @@ StepView step_view(const CellLists& L) {
   V.cap = L.cap;
   V.per_tile = L.per_tile;
   V.ocap = L.ocap;
+  V.ib0 = L.ib0;
+  V.ov0 = L.ov0;
+  V.tr0 = L.tr0;
   for (int d = 0; d < kDirs; ++d) V.dcap[d] = L.dcap[d];
   for (int d = 0; d <= kDirs; ++d) V.doff[d] = L.doff[d];
-  V.bin = L.bucket[a];
-  V.iin = L.inbox[a];
-  V.oin = L.ovf[a];
-  V.bout = L.bucket[b];
-  V.iout = L.inbox[b];
-  V.oout = L.ovf[b];
-  V.trash = L.trash;
+  V.in = L.buf[a];
+  V.out = L.buf[b];
   V.bcnt_in = L.bcnt[a];
   V.bcnt_out = L.bcnt[b];
   V.icnt_in = L.icnt[a];
@@ -170,45 +167,20 @@ StepView step_view(const CellLists& L) {
   return V;
 }
 
-// Per-component pointers of one slot.
+// Store a packet into slot j of S (FP32: its home cell into slot jc, which is a trash
+// slot for buckets, where the slot implies the cell).
 template <typename T>
-struct Dst {
-  double* x;      // FP64
-  float* off;     // FP32
-  T* u;
-  int32_t* id;
-  int32_t* cell;  // FP32
-  int64_t stride;
-};
-
-template <typename T>
-__device__ __forceinline__ Dst<T> dst_of(const SlotArrays& S, int64_t j) {
-  Dst<T> d;
-  if constexpr (is_fp64<T>()) {
-    d.x = S.x + j;
-    d.off = nullptr;
-  } else {
-    d.x = nullptr;
-    d.off = S.off + j;
-  }
-  d.u = (T*)S.u + j;
-  d.id = S.id + j;
-  d.cell = S.cell ? S.cell + j : nullptr;
-  d.stride = S.stride;
-  return d;
-}
-
-template <typename T>
-__device__ __forceinline__ void store_dst(const Dst<T>& d, const double x[3], const T f[3], const T u[3], int32_t id,
-                                          int32_t cell) {
+__device__ __forceinline__ void store_slot(const SlotArrays& S, int64_t j, int64_t jc, const double x[3],
+                                           const T f[3], const T u[3], int32_t id, int32_t cell) {
+  T* su = (T*)S.u;
   #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    if constexpr (is_fp64<T>()) d.x[c * d.stride] = x[c];
-    else d.off[c * d.stride] = f[c];
-    d.u[c * d.stride] = u[c];
+    if constexpr (is_fp64<T>()) S.x[c * S.stride + j] = x[c];
+    else S.off[c * S.stride + j] = f[c];
+    su[c * S.stride + j] = u[c];
   }
-  d.id[0] = id;
-  if constexpr (!is_fp64<T>()) d.cell[0] = cell;
+  S.id[j] = id;
+  if constexpr (!is_fp64<T>()) S.cell[jc] = cell;
 }
 
 // Load a packet from an inbox or the overflow list (home cell not implied by the slot).
@@ -250,73 +222,43 @@ __device__ __forceinline__ int tile_step(int t, int tt, int n) {
   return (d < -1 || d > 1) ? 2 : d;
 }
 
-enum : int { kToTrash = 0, kToBucket = 1, kToInbox = 2, kToOverflow = 3 };
-
-// Slot for a packet of this workgroup's tile whose new (wrapped) home cell is h:
-// the bucket of h when h is in this tile and the bucket has room (kToBucket), else
-// the part of h's tile inbox reserved for packets from this tile (kToInbox).
-// kToOverflow when neither has room or h's tile is not a neighbour.
-__device__ __forceinline__ int place(const StepView& V, int ttx, int tty, int ttz, int* cntB, int* cntD,
-                                     const int* sDcap, const int* sDoff, const RunConsts& k, const int h[3],
-                                     int64_t& j) {
+// Slot (in the next buffer) for a packet of this workgroup's tile whose new (wrapped)
+// home cell is h: the bucket of h when h is in this tile and the bucket has room,
+// else the part of h's tile inbox reserved for packets from this tile.  Returns -1
+// when neither has room or h's tile is not a neighbour (the packet then needs an
+// overflow slot).  *bucket tells whether the slot is a bucket slot.
+__device__ __forceinline__ int64_t place(const StepView& V, int ttx, int tty, int ttz, int* cntB, int* cntD,
+                                         const int* sDcap, const int* sDoff, const int h[3], bool* bucket) {
   const int tx = h[0] / kCellTile, ty = h[1] / kCellTile, tz = h[2] / kCellTile;
   const int sx = tile_step(tx, ttx, V.ntx), sy = tile_step(ty, tty, V.nty), sz = tile_step(tz, ttz, V.ntz);
-  if (sx > 1 || sy > 1 || sz > 1) return kToOverflow;
+  *bucket = false;
+  if (sx > 1 || sy > 1 || sz > 1) return -1;
   const int dir = (sx + 1) + 3 * ((sy + 1) + 3 * (sz + 1));
   if (dir == kSelfDir) {
     const int local =
         (h[0] - tx * kCellTile) + kCellTile * ((h[1] - ty * kCellTile) + kCellTile * (h[2] - tz * kCellTile));
     const int slot = atomicAdd(&cntB[local], 1);
     if (slot < V.cap) {
-      j = bucket_index(h, slot, V.ntx, V.nty, V.cap);
-      return kToBucket;
+      *bucket = true;
+      const int64_t t = tx + (int64_t)V.ntx * (ty + (int64_t)V.nty * tz);
+      return (t * V.cap + slot) * kCellTileCells + local;
     }
   }
   const int s = atomicAdd(&cntD[dir], 1);
   if (s < sDcap[dir]) {
     const int64_t t = tx + (int64_t)V.ntx * (ty + (int64_t)V.nty * tz);
-    j = t * V.per_tile + sDoff[dir] + s;
-    return kToInbox;
+    return V.ib0 + t * V.per_tile + sDoff[dir] + s;
   }
-  return kToOverflow;
+  return -1;
 }
 
-// Pointers of slot j of the store `kind` of the next buffer, chosen with selects on
-// the (uniform) store bases.
-template <typename T>
-__device__ __forceinline__ Dst<T> dst_select(const StepView& V, int kind, int64_t j) {
-  const SlotArrays& A = V.bout;
-  const SlotArrays& I = V.iout;
-  const SlotArrays& O = V.oout;
-  const SlotArrays& X = V.trash;
-  auto pick = [&](auto a, auto i, auto o, auto x) { return kind == kToBucket ? a : kind == kToInbox ? i : kind == kToOverflow ? o : x; };
-  Dst<T> d;
-  if constexpr (is_fp64<T>()) {
-    d.x = pick(A.x, I.x, O.x, X.x) + j;
-    d.off = nullptr;
-  } else {
-    d.x = nullptr;
-    d.off = pick(A.off, I.off, O.off, X.off) + j;
-  }
-  d.u = (T*)pick(A.u, I.u, O.u, X.u) + j;
-  d.id = pick(A.id, I.id, O.id, X.id) + j;
-  // buckets imply the cell; their cell store goes to the trash slot
-  d.cell = kind == kToBucket ? nullptr : pick(A.cell, I.cell, O.cell, X.cell) + j;
-  d.stride = pick(A.stride, I.stride, O.stride, X.stride);
-  return d;
-}
-
-// Slot in the next overflow list (global counter): kToOverflow, or kToTrash and
-// ERR_TILE when that is full too (unreachable: the list holds every packet).
-__device__ __forceinline__ int place_overflow(const StepView& V, int trash_slot, uint32_t& err, int64_t& j) {
+// Slot in the next overflow list (global counter), or the trash slot and ERR_TILE
+// when that is full too (unreachable: the list holds every packet).
+__device__ __forceinline__ int64_t place_overflow(const StepView& V, int64_t trash, uint32_t& err) {
   const int s = atomicAdd(V.icnt_out + V.ntiles * kDirs, 1);
-  if ((int64_t)s < V.ocap) {
-    j = s;
-    return kToOverflow;
-  }
+  if ((int64_t)s < V.ocap) return V.ov0 + s;
   err |= ERR_TILE;
-  j = trash_slot;
-  return kToTrash;
+  return trash;
 }
 
 // Drift (Sec. 2: dx/dt = c_tilde beta) of one packet with home cell `home`, offset f
@@ -380,26 +322,62 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
 
   constexpr bool deposit = DEP;
   const int64_t ntiles = V.ntiles;
-  int64_t tile = blockIdx.x;
+  int tile = blockIdx.x;
   // consecutive workgroups go to different XCDs: give each XCD a contiguous range of
   // tiles so neighbouring tiles share that XCD's L2
-  if ((ntiles & 7) == 0) tile = (int64_t)(blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
-  const int ttx = (int)(tile % V.ntx);
-  const int tty = (int)((tile / V.ntx) % V.nty);
-  const int ttz = (int)(tile / ((int64_t)V.ntx * V.nty));
+  if ((ntiles & 7) == 0) tile = (int)(blockIdx.x & 7) * (int)(ntiles >> 3) + (int)(blockIdx.x >> 3);
+  const int ttx = tile % V.ntx;
+  const int tty = (tile / V.ntx) % V.nty;
+  const int ttz = tile / (V.ntx * V.nty);
   const int ox = ttx * kCellTile - 1, oy = tty * kCellTile - 1, oz = ttz * kCellTile - 1;
   const int64_t nc = k.ncells;
-  const int trash_slot = (int)(blockIdx.x & 7) * kThreads + threadIdx.x;
+  const int64_t trash = V.tr0 + (int)(blockIdx.x & 7) * kThreads + threadIdx.x;
   uint32_t err = 0;
+
+  // this thread's quad, cell and first packets: every load of the prologue is issued
+  // before the first wait, so a workgroup pays one memory latency before its loop
+  const int q = threadIdx.x & 3;
+  const int quad = threadIdx.x >> 2;
+  const int lane = threadIdx.x & 63;
+  const int lx = quad & 3, ly = (quad >> 2) & 3, lz = quad >> 4;
+  const int home[3] = {ttx * kCellTile + lx, tty * kCellTile + ly, ttz * kCellTile + lz};
+  const bool valid = home[0] < k.nx && home[1] < k.ny && home[2] < k.nz;
+  const int64_t cell = valid ? home[0] + (int64_t)k.nx * (home[1] + (int64_t)k.ny * home[2]) : 0;
+  const int n_raw = V.bcnt_in[cell];
+
+  const SlotArrays& S = V.in;
+  const T* su = (const T*)S.u;
+  // packet state of the next two rounds (two register sets used alternately, so a
+  // load has two rounds to arrive); slots past the cell's count hold stale data that
+  // the lane ignores, so every round issues the same loads
+  T pua[3], pub[3];
+  double pxa[3], pxb[3];
+  int32_t pida, pidb;
+  auto fetch = [&](int rd, double (&px)[3], T (&pu)[3], int32_t& pid) {
+    int kk = 4 * rd + q;
+    kk = kk < V.cap ? kk : V.cap - 1;
+    const int64_t j = ((int64_t)tile * V.cap + kk) * kCellTileCells + quad;
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if constexpr (is_fp64<T>()) px[d] = S.x[d * S.stride + j];
+      else px[d] = (double)S.off[d * S.stride + j];
+      pu[d] = su[d * S.stride + j];
+    }
+    pid = S.id[j];
+  };
+  fetch(0, pxa, pua, pida);
+  fetch(1, pxb, pub, pidb);
+  // this tile's inbox counts by direction, one per lane of the first wave
+  const int cin = threadIdx.x < kDirs ? V.icnt_in[(int64_t)tile * kDirs + threadIdx.x] : 0;
 
   for (int r = threadIdx.x; r < kRegionCells; r += kThreads) {
     const int rx = r % kRegionEdge, ry = (r / kRegionEdge) % kRegionEdge, rz = r / (kRegionEdge * kRegionEdge);
-    const int64_t cell =
+    const int64_t rc =
         wrapm(ox + rx, k.nx) + (int64_t)k.nx * (wrapm(oy + ry, k.ny) + (int64_t)k.ny * wrapm(oz + rz, k.nz));
     #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      Fs[d][r] = E[d * nc + cell];
-      Fs[3 + d][r] = B[d * nc + cell];
+      Fs[d][r] = E[d * nc + rc];
+      Fs[3 + d][r] = B[d * nc + rc];
     }
     if constexpr (deposit) {
       #pragma unroll
@@ -407,19 +385,28 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
     }
   }
   if (threadIdx.x < kCellTileCells) cntB[threadIdx.x] = 0;
-  if (threadIdx.x < kDirs) {
-    cntD[threadIdx.x] = 0;
-    sDcap[threadIdx.x] = V.dcap[threadIdx.x];
-  }
-  if (threadIdx.x <= kDirs) sDoff[threadIdx.x] = V.doff[threadIdx.x];
-  if (threadIdx.x == 0) {
-    int run = 0;
+  if (threadIdx.x < 64) {
+    // part capacities and offsets by lane (uniform kernel-argument reads), then the
+    // prefix of the clamped counts across the first wave
+    int dcap = 0, doff = V.doff[kDirs];
+    #pragma unroll
     for (int d = 0; d < kDirs; ++d) {
-      sPre[d] = run;
-      const int c = V.icnt_in[tile * kDirs + d];
-      run += c < V.dcap[d] ? c : V.dcap[d];
+      dcap = threadIdx.x == d ? V.dcap[d] : dcap;
+      doff = threadIdx.x == d ? V.doff[d] : doff;
     }
-    sPre[kDirs] = run;
+    if (threadIdx.x < kDirs) {
+      cntD[threadIdx.x] = 0;
+      sDcap[threadIdx.x] = dcap;
+    }
+    if (threadIdx.x <= kDirs) sDoff[threadIdx.x] = doff;
+    const int c = cin < dcap ? cin : dcap;
+    int incl = c;
+    #pragma unroll
+    for (int o = 1; o < 32; o <<= 1) {
+      const int y = __shfl_up(incl, o);
+      if (lane >= o) incl += y;
+    }
+    if (threadIdx.x <= kDirs) sPre[threadIdx.x] = incl - c;
   }
   __syncthreads();
 
@@ -428,17 +415,10 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
 
   // ------------------------------------------------------------ quads: one cell each
   {
-    const int q = threadIdx.x & 3;
-    const int quad = threadIdx.x >> 2;
-    const int lane = threadIdx.x & 63;
     const int qbase = lane & ~3;  // first lane of this quad within the wave
     T* pkw = &Pk[threadIdx.x >> 6][0];
     T* rsw = &Rs[threadIdx.x >> 6][0];
-    const int lx = quad & 3, ly = (quad >> 2) & 3, lz = quad >> 4;
-    const int home[3] = {ttx * kCellTile + lx, tty * kCellTile + ly, ttz * kCellTile + lz};
-    const bool valid = home[0] < k.nx && home[1] < k.ny && home[2] < k.nz;
-    const int64_t cell = valid ? home[0] + (int64_t)k.nx * (home[1] + (int64_t)k.ny * home[2]) : 0;
-    int n = valid ? V.bcnt_in[cell] : 0;
+    int n = valid ? n_raw : 0;
     n = n < V.cap ? n : V.cap;
 
     // this lane's field components on the 27 nodes around the cell
@@ -456,42 +436,17 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
           D[node] = T(0);
         }
 
-    const SlotArrays& S = V.bin;
-    const T* su = (const T*)S.u;
     const int rounds = (n + 3) >> 2;
-    // packet state of the coming round, loaded one round ahead; idle lanes load a
-    // valid slot of their cell and ignore it, so every round issues the same loads
-    T pu[3];
-    double px[3];
-    int32_t pid;
-    auto fetch = [&](int rd) {
-      int kk = 4 * rd + q;
-      kk = kk < n ? kk : (n > 0 ? n - 1 : 0);
-      const int64_t j = (tile * V.cap + kk) * kCellTileCells + quad;
-      #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        if constexpr (is_fp64<T>()) px[d] = S.x[d * S.stride + j];
-        else px[d] = (double)S.off[d * S.stride + j];
-        pu[d] = su[d * S.stride + j];
-      }
-      pid = S.id[j];
-    };
     // the previous round's packet, stored at the start of the next round (just before
     // that round's prefetch) so that the loop never waits on its own fresh stores
-    int okind = kToTrash;
-    int64_t oj = trash_slot;
+    int64_t oj = trash, ojc = trash;
     double oxn[3] = {0.0, 0.0, 0.0};
     T ofn[3] = {T(0), T(0), T(0)}, oun[3] = {T(0), T(0), T(0)};
     int32_t oid = 0, ocell = 0;
     auto flush = [&]() {
-      Dst<T> dst = dst_select<T>(V, okind, oj);
-      if constexpr (!is_fp64<T>()) {
-        if (!dst.cell) dst.cell = V.trash.cell + trash_slot;
-      }
-      store_dst<T>(dst, oxn, ofn, oun, oid, ocell);
+      store_slot<T>(V.out, oj, ojc, oxn, ofn, oun, oid, ocell);
     };
-    fetch(0);
-    for (int rd = 0; __ballot(rd < rounds) != 0; ++rd) {
+    auto round = [&](const int rd, double (&px)[3], T (&pu)[3], int32_t& pid) {
       const bool act = 4 * rd + q < n;
       T f[3], u[3];
       double xa[3] = {0.0, 0.0, 0.0};
@@ -508,7 +463,7 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
         u[d] = act ? pu[d] : T(0);
       }
       flush();
-      fetch(rd + 1);
+      fetch(rd + 2, px, pu, pid);
 
       // own weights -> LDS: x weights, then the nine y-z products
       {
@@ -597,13 +552,19 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
       int hn[3];
       const uint32_t e1 = drift3<T>(k, home, f, xa, un, hn, oxn, ofn);
       err |= act ? e1 : 0u;
-      oj = trash_slot;
-      okind = act ? place(V, ttx, tty, ttz, cntB, cntD, sDcap, sDoff, k, hn, oj) : kToTrash;
-      if (okind == kToOverflow) okind = place_overflow(V, trash_slot, err, oj);
+      bool to_bucket = false;
+      oj = act ? place(V, ttx, tty, ttz, cntB, cntD, sDcap, sDoff, hn, &to_bucket) : trash;
+      if (oj < 0) oj = place_overflow(V, trash, err);
+      ojc = to_bucket ? trash : oj;
       #pragma unroll
       for (int d = 0; d < 3; ++d) oun[d] = un[d];
       oid = id;
       ocell = hn[0] + k.nx * (hn[1] + k.ny * hn[2]);
+    };
+    for (int rd = 0; __ballot(rd < rounds) != 0; rd += 2) {
+      round(rd, pxa, pua, pida);
+      if (__ballot(rd + 1 < rounds) == 0) break;
+      round(rd + 1, pxb, pub, pidb);
     }
     flush();
     if (deposit && n > 0) {
@@ -626,12 +587,12 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
       int dir = 0;
       #pragma unroll
       for (int d = 1; d < kDirs; ++d) dir += (i >= sPre[d]) ? 1 : 0;
-      const int64_t j = tile * V.per_tile + sDoff[dir] + (i - sPre[dir]);
+      const int64_t j = (int64_t)tile * V.per_tile + sDoff[dir] + (i - sPre[dir]);
       int home[3];
       T f[3], u[3];
       double xa[3];
       int32_t id;
-      load_free<T>(V.iin, j, k, home, f, xa, u, id);
+      load_free<T>(V.in, V.ib0 + j, k, home, f, xa, u, id);
       // region coordinates of node home-1 (the inbox only holds packets of this tile)
       const int bx = home[0] - ttx * kCellTile, by = home[1] - tty * kCellTile, bz = home[2] - ttz * kCellTile;
       T w[9];
@@ -667,14 +628,10 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
       double xn[3];
       T fn[3];
       err |= drift3<T>(k, home, f, xa, un, hn, xn, fn);
-      int64_t j2 = trash_slot;
-      int kind = place(V, ttx, tty, ttz, cntB, cntD, sDcap, sDoff, k, hn, j2);
-      if (kind == kToOverflow) kind = place_overflow(V, trash_slot, err, j2);
-      Dst<T> dst = dst_select<T>(V, kind, j2);
-      if constexpr (!is_fp64<T>()) {
-        if (!dst.cell) dst.cell = V.trash.cell + trash_slot;
-      }
-      store_dst<T>(dst, xn, fn, un, id, hn[0] + k.nx * (hn[1] + k.ny * hn[2]));
+      bool to_bucket = false;
+      int64_t j2 = place(V, ttx, tty, ttz, cntB, cntD, sDcap, sDoff, hn, &to_bucket);
+      if (j2 < 0) j2 = place_overflow(V, trash, err);
+      store_slot<T>(V.out, j2, to_bucket ? trash : j2, xn, fn, un, id, hn[0] + k.nx * (hn[1] + k.ny * hn[2]));
     }
   }
 
@@ -688,7 +645,7 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
       T f[3], u[3];
       double xa[3];
       int32_t id;
-      load_free<T>(V.oin, i, k, home, f, xa, u, id);
+      load_free<T>(V.in, V.ov0 + i, k, home, f, xa, u, id);
       T w[9];
       weights3<M, T>(f[0], w);
       weights3<M, T>(f[1], w + 3);
@@ -728,13 +685,8 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
       double xn[3];
       T fn[3];
       err |= drift3<T>(k, home, f, xa, un, hn, xn, fn);
-      int64_t j2 = trash_slot;
-      const int kind = place_overflow(V, trash_slot, err, j2);
-      Dst<T> dst = dst_select<T>(V, kind, j2);
-      if constexpr (!is_fp64<T>()) {
-        if (!dst.cell) dst.cell = V.trash.cell + trash_slot;
-      }
-      store_dst<T>(dst, xn, fn, un, id, hn[0] + k.nx * (hn[1] + k.ny * hn[2]));
+      const int64_t j2 = place_overflow(V, trash, err);
+      store_slot<T>(V.out, j2, j2, xn, fn, un, id, hn[0] + k.nx * (hn[1] + k.ny * hn[2]));
     }
   }
   if (err) set_status(k.status, err);
@@ -742,7 +694,7 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
 
   // ------------------------------------------------------------ outputs
   if constexpr (deposit) {
-    double* out = V.halo + tile * 4 * kRegionCells;
+    double* out = V.halo + (int64_t)tile * 4 * kRegionCells;
     const double* acc = &Acc[0][0];
     for (int r = threadIdx.x; r < 4 * kRegionCells; r += kThreads) out[r] = acc[r];
   }
@@ -861,28 +813,27 @@ __global__ void __launch_bounds__(kThreads) cells_build_kernel(Packets<T> P, Cel
     const int slot = run_slot(L.bcnt[0], key);
     if (i >= P.np) continue;
     const int32_t id = P.id[i];
-    Dst<T> dst;
+    const int64_t trash = L.tr0 + (blockIdx.x & 7) * kThreads + threadIdx.x;
+    int64_t j, jc;
     if (slot < L.cap) {
-      dst = dst_of<T>(L.bucket[0], bucket_index(h, slot, L.ntx, L.nty, L.cap));
+      j = bucket_index(h, slot, L.ntx, L.nty, L.cap);
+      jc = trash;
     } else {
       const int64_t t = h[0] / kCellTile + (int64_t)L.ntx * (h[1] / kCellTile + (int64_t)L.nty * (h[2] / kCellTile));
       const int is = atomicAdd(&L.icnt[0][t * kDirs + kSelfDir], 1);
       if (is < L.dcap[kSelfDir]) {
-        dst = dst_of<T>(L.inbox[0], t * L.per_tile + L.doff[kSelfDir] + is);
+        j = L.ib0 + t * L.per_tile + L.doff[kSelfDir] + is;
       } else {
         const int os = atomicAdd(&L.icnt[0][L.ntiles * kDirs], 1);
-        if ((int64_t)os < L.ocap) {
-          dst = dst_of<T>(L.ovf[0], os);
-        } else {
+        if ((int64_t)os >= L.ocap) {
           set_status(k.status, ERR_TILE);
           continue;
         }
+        j = L.ov0 + os;
       }
+      jc = j;
     }
-    if constexpr (!is_fp64<T>()) {
-      if (!dst.cell) dst.cell = L.trash.cell + (blockIdx.x & 7) * kThreads + threadIdx.x;
-    }
-    store_dst<T>(dst, x, f, u, id, key);
+    store_slot<T>(L.buf[0], j, jc, x, f, u, id, key);
   }
 }
 
@@ -927,10 +878,10 @@ __device__ __forceinline__ void copy_out(const Packets<T>& P, const SlotArrays& 
 // Every occupied slot of buffer cur -> caller arrays at its prefix-sum offset.
 template <typename T>
 __global__ void cells_compact_kernel(Packets<T> P, CellLists L, const int32_t* __restrict__ offs, RunConsts k) {
-  const int cur = L.cur;
+  const SlotArrays& S = L.buf[L.cur];
   const int64_t nc = k.ncells;
-  const int64_t nslot = L.ntiles * L.cap * kCellTileCells, islots = L.ntiles * L.per_tile;
-  const int64_t total = nslot + islots + L.ocap;
+  const int64_t nslot = L.ib0, islots = L.ov0 - L.ib0;
+  const int64_t total = L.ov0 + L.ocap;
   const int64_t obase = nc + L.ntiles * kDirs;
   for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < total; s += (int64_t)gridDim.x * blockDim.x) {
     if (s < nslot) {
@@ -943,7 +894,7 @@ __global__ void cells_compact_kernel(Packets<T> P, CellLists L, const int32_t* _
       if (gx >= k.nx || gy >= k.ny || gz >= k.nz) continue;
       const int64_t c = gx + (int64_t)k.nx * (gy + (int64_t)k.ny * gz);
       if (sl >= offs[c + 1] - offs[c]) continue;
-      copy_out<T>(P, L.bucket[cur], s, offs[c] + sl, (int32_t)c);
+      copy_out<T>(P, S, s, offs[c] + sl, (int32_t)c);
     } else if (s < nslot + islots) {
       const int64_t si = s - nslot;
       const int64_t t = si / L.per_tile;
@@ -958,13 +909,13 @@ __global__ void cells_compact_kernel(Packets<T> P, CellLists L, const int32_t* _
       const int sl = r - start;
       const int64_t e = nc + t * kDirs + dir;
       if (sl >= offs[e + 1] - offs[e]) continue;
-      const int32_t cell = is_fp64<T>() ? 0 : L.inbox[cur].cell[si];
-      copy_out<T>(P, L.inbox[cur], si, offs[e] + sl, cell);
+      const int32_t cell = is_fp64<T>() ? 0 : S.cell[s];
+      copy_out<T>(P, S, s, offs[e] + sl, cell);
     } else {
       const int64_t so = s - nslot - islots;
       if (so >= offs[obase + 1] - offs[obase]) continue;
-      const int32_t cell = is_fp64<T>() ? 0 : L.ovf[cur].cell[so];
-      copy_out<T>(P, L.ovf[cur], so, offs[obase] + so, cell);
+      const int32_t cell = is_fp64<T>() ? 0 : S.cell[s];
+      copy_out<T>(P, S, s, offs[obase] + so, cell);
     }
   }
 }
@@ -1032,14 +983,15 @@ CellLists carve(int nx, int ny, int nz, int64_t np, int precision, uintptr_t bas
   const bool f32 = precision == 1;
   Carver cv{(base + 255) / 256 * 256};
   const uintptr_t start = cv.p;
+  L.ib0 = L.ntiles * L.cap * kCellTileCells;
+  L.ov0 = L.ib0 + L.ntiles * L.per_tile;
+  L.tr0 = L.ov0 + L.ocap;
+  const int64_t slots = L.tr0 + kTrashSlots;
   for (int b = 0; b < 2; ++b) {
-    L.bucket[b] = carve_slots(cv, L.ntiles * L.cap * kCellTileCells, f32, false);
-    L.inbox[b] = carve_slots(cv, L.ntiles * L.per_tile, f32, true);
-    L.ovf[b] = carve_slots(cv, L.ocap, f32, true);
+    L.buf[b] = carve_slots(cv, slots, f32, true);
     L.bcnt[b] = (int32_t*)cv.take((size_t)ncells * sizeof(int32_t));
     L.icnt[b] = (int32_t*)cv.take((size_t)(L.ntiles * kDirs + 1) * sizeof(int32_t));
   }
-  L.trash = carve_slots(cv, kTrashSlots, f32, true);
   L.halo = (double*)cv.take((size_t)L.ntiles * 4 * kRegionCells * sizeof(double));
   const int64_t nscan = ncells + L.ntiles * kDirs + 1;
   // counts (nscan), offsets (nscan + 1), scan temporaries
@@ -1111,7 +1063,7 @@ hipError_t launch_cells_compact(const Packets<T>& P, CellLists& L, const RunCons
   hipError_t e = launch_exclusive_scan(counts, offs, nscan, tmp, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(scan_total_kernel, dim3(1), dim3(1), 0, s, offs, counts, nscan);
-  const int64_t total = L.ntiles * L.cap * kCellTileCells + L.ntiles * L.per_tile + L.ocap;
+  const int64_t total = L.ov0 + L.ocap;
   hipLaunchKernelGGL(cells_compact_kernel<T>, dim3(grid_for(total)), dim3(kThreads), 0, s, P, L, offs, k);
   return hipGetLastError();
 }

@@ -18,11 +18,11 @@ constexpr int kDirs = 27;                            // 3x3x3 tile offsets, inde
 constexpr int kSelfDir = 13;                         // offset (0, 0, 0)
 
 // One structure-of-arrays packet store: component d of slot j at [d * stride + j].
-// FP64 keeps absolute positions x; FP32 keeps the in-cell offset (and, where the
-// slot does not imply it, the home cell).
+// FP64 keeps absolute positions x; FP32 keeps the in-cell offset and the home cell
+// (read only where the slot does not imply it).
 struct SlotArrays {
   double* x;        // FP64 only
-  int32_t* cell;    // FP32 inbox/overflow/trash only
+  int32_t* cell;    // FP32 only
   float* off;       // FP32 only
   void* u;          // momentum, precision type
   int32_t* id;
@@ -31,13 +31,19 @@ struct SlotArrays {
 
 // Sizes and buffers of the cell-list layout (all in the library's scratch).
 //
-// Every tile has an inbox split by the direction the packets came from: the part
-// for direction dir holds packets that moved into the tile from the tile at offset
-// -dir... written by exactly one source tile (the one at tile - dir), which takes
-// slots from an LDS counter and stores the final count with a plain store.  The
-// self part (kSelfDir) takes a tile's own packets whose bucket is full.  Packets
-// that find their part full (or moved further than one tile) go to one overflow
-// list for the grid.
+// Each of the two buffers is ONE slot store (a SlotArrays whose stride is the total
+// slot count), cut into ranges: the buckets first, then the tile inboxes, the
+// overflow list and a few trash slots that idle lanes write to.  A packet's place
+// is therefore a single slot index.
+//
+// Buckets are laid out tile by tile as [slot][cell in tile]: slot s of local cell lc
+// of tile t is (t*cap + s)*64 + lc, so the 16 cells a wave works on keep each slot
+// row in whole cache lines.  Every tile has an inbox split into 27 parts by the tile
+// offset a packet moved by: part dir of tile t holds packets that came from the tile
+// at t - dir, which is that part's only writer (slots from an LDS counter, the final
+// count stored with a plain store).  The self part (kSelfDir) takes a tile's own
+// packets whose bucket is full.  Packets that find their part full, or that moved
+// further than one tile, go to the overflow list, which holds every packet.
 struct CellLists {
   int ntx, nty, ntz;      // tiles per axis (the last tile along an axis may be partial)
   int64_t ntiles;
@@ -45,11 +51,9 @@ struct CellLists {
   int per_tile;           // inbox slots per tile (sum of dcap)
   int dcap[kDirs];        // inbox slots per direction
   int doff[kDirs + 1];    // first slot of each direction in a tile's inbox
-  int64_t ocap;           // overflow slots (one list for the whole grid)
-  SlotArrays bucket[2];   // tile by tile, [slot][cell in tile]: slot s of local cell lc of tile t at (t*cap + s)*64 + lc
-  SlotArrays inbox[2];    // slot s of direction d of tile t at t*per_tile + doff[d] + s
-  SlotArrays ovf[2];      // overflow list
-  SlotArrays trash;       // write target of idle lanes: [8][256] slots
+  int64_t ocap;           // overflow slots
+  int64_t ib0, ov0, tr0;  // first slot of the inboxes, the overflow list, the trash
+  SlotArrays buf[2];      // the two slot stores (FP32: with a cell array over all slots)
   int32_t* bcnt[2];       // packets per cell
   int32_t* icnt[2];       // packets per (tile, direction) [ntiles*kDirs], then the overflow count
   double* halo;           // [ntiles][4][kRegionCells] per-tile exchange accumulators
