@@ -243,12 +243,12 @@ template <typename T>
 __device__ __forceinline__ void drift_one(const Packets<T>& P, int64_t i, T ux, T uy, T uz,
                                           const RunConsts& k) {
   const int64_t np = P.np;
-  const T g = sqrt(T(1) + (ux * ux + uy * uy + uz * uz));
-  bool bad = !(isfinite(g));
+  bool fin;
+  const T s = drift_scale<T>(ux, uy, uz, is_fp64<T>() ? (T)k.cdt : (T)k.cdt_dx, &fin);
+  bool bad = !fin;
   if constexpr (is_fp64<T>()) {
     const double L[3] = {k.Lx, k.Ly, k.Lz};
     const double u3[3] = {ux, uy, uz};
-    const double s = k.cdt / g;
     #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const double step = s * u3[d];
@@ -258,7 +258,6 @@ __device__ __forceinline__ void drift_one(const Packets<T>& P, int64_t i, T ux, 
   } else {
     const int n[3] = {k.nx, k.ny, k.nz};
     const float u3[3] = {ux, uy, uz};
-    const float s = (float)k.cdt_dx / g;
     const int c = P.cell[i];
     const int nxy = k.nx * k.ny;
     int h[3];
@@ -283,7 +282,7 @@ __device__ __forceinline__ void drift_one(const Packets<T>& P, int64_t i, T ux, 
     }
     P.cell[i] = h[0] + k.nx * (h[1] + k.ny * h[2]);
   }
-  if (bad) set_status(k.status, isfinite(g) ? ERR_COURANT : ERR_NAN);
+  if (bad) set_status(k.status, fin ? ERR_COURANT : ERR_NAN);
 }
 
 template <typename T>

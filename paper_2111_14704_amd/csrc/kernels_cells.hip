@@ -267,12 +267,12 @@ __device__ __forceinline__ int64_t place_overflow(const StepView& V, int64_t tra
 template <typename T>
 __device__ __forceinline__ uint32_t drift3(const RunConsts& k, const int home[3], const T f[3], const double xa[3],
                                            const T un[3], int h[3], double xn[3], T fn[3]) {
-  const T g = sqrt(T(1) + (un[0] * un[0] + un[1] * un[1] + un[2] * un[2]));
-  bool bad = !isfinite(g);
+  bool fin;
+  const T s = drift_scale<T>(un[0], un[1], un[2], is_fp64<T>() ? (T)k.cdt : (T)k.cdt_dx, &fin);
+  bool bad = !fin;
   const int n3[3] = {k.nx, k.ny, k.nz};
   if constexpr (is_fp64<T>()) {
     const double L3[3] = {k.Lx, k.Ly, k.Lz};
-    const double s = k.cdt / g;
     #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const double st = s * un[d];
@@ -282,7 +282,6 @@ __device__ __forceinline__ uint32_t drift3(const RunConsts& k, const int home[3]
       fn[d] = 0;
     }
   } else {
-    const float s = (float)k.cdt_dx / g;
     #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const float st = s * un[d];
@@ -301,7 +300,7 @@ __device__ __forceinline__ uint32_t drift3(const RunConsts& k, const int home[3]
     }
   }
   if (!bad) return 0u;
-  return isfinite(g) ? (uint32_t)ERR_COURANT : (uint32_t)ERR_NAN;
+  return fin ? (uint32_t)ERR_COURANT : (uint32_t)ERR_NAN;
 }
 
 template <int M, typename T, bool DEP>

@@ -229,10 +229,10 @@ __global__ void __launch_bounds__(256) step_tiled_kernel(Packets<T> src, Packets
     }
 
     // ---- drift (Sec. 2: dx/dt = c_tilde beta) and store
-    const T g = sqrt(T(1) + (nux * nux + nuy * nuy + nuz * nuz));
-    bool bad = !isfinite(g);
+    bool fin;
+    const T s = drift_scale<T>(nux, nuy, nuz, is_fp64<T>() ? (T)k.cdt : (T)k.cdt_dx, &fin);
+    bool bad = !fin;
     if constexpr (is_fp64<T>()) {
-      const double s = k.cdt / g;
       const double L[3] = {k.Lx, k.Ly, k.Lz};
       const double un[3] = {nux, nuy, nuz};
       #pragma unroll
@@ -242,7 +242,6 @@ __global__ void __launch_bounds__(256) step_tiled_kernel(Packets<T> src, Packets
         dst.x[d * np + i] = wrap_coord(xa[d] + st, L[d]);
       }
     } else {
-      const float s = (float)k.cdt_dx / g;
       const int n3[3] = {k.nx, k.ny, k.nz};
       const float un[3] = {nux, nuy, nuz};
       int hn[3];
@@ -267,7 +266,7 @@ __global__ void __launch_bounds__(256) step_tiled_kernel(Packets<T> src, Packets
     dst.u[np + i] = nuy;
     dst.u[2 * np + i] = nuz;
     if (copy_id) dst.id[i] = src.id[i];
-    if (bad) set_status(k.status, isfinite(g) ? ERR_COURANT : ERR_NAN);
+    if (bad) set_status(k.status, fin ? ERR_COURANT : ERR_NAN);
   }
 
   if (!deposit) return;

@@ -114,16 +114,49 @@ struct Kick {
   T dux, duy, duz, dg;
 };
 
+// 1/sqrt(x) and 1/x for x >= 1 (Lorentz factors and 1 + |t|^2): the hardware
+// estimate refined by Newton-Raphson steps, y <- y + y (1 - x y^2) / 2 and
+// r <- r + r (1 - x r); two steps in FP64, one in FP32, each roughly doubling the
+// correct bits of the estimate.  No IEEE division or square-root sequence.
+template <typename T>
+__device__ __forceinline__ T rsqrt_nr(T x) {
+  if constexpr (sizeof(T) == 8) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+  } else {
+    float y = __builtin_amdgcn_rsqf(x);
+    const float e = fmaf(-x * y, y, 1.0f);
+    return fmaf(0.5f * y, e, y);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T rcp_nr(T x) {
+  if constexpr (sizeof(T) == 8) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+  } else {
+    float r = __builtin_amdgcn_rcpf(x);
+    const float e = fmaf(-x, r, 1.0f);
+    return fmaf(r, e, r);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ Kick<T> boris_kick(T ux, T uy, T uz, T ex, T ey, T ez,
                                               T bx, T by, T bz, T h) {
   const T hex = h * ex, hey = h * ey, hez = h * ez;
   const T mx = ux + hex, my = uy + hey, mz = uz + hez;
-  const T gm = sqrt(T(1) + (mx * mx + my * my + mz * mz));
-  const T k = h / gm;
+  const T k = h * rsqrt_nr<T>(T(1) + (mx * mx + my * my + mz * mz));  // h / gamma-
   const T tx = k * bx, ty = k * by, tz = k * bz;
   const T tt = tx * tx + ty * ty + tz * tz;
-  const T sf = T(2) / (T(1) + tt);
+  const T sf = T(2) * rcp_nr<T>(T(1) + tt);
   const T sx = sf * tx, sy = sf * ty, sz = sf * tz;
   // u' = u- + u- x t
   const T px = mx + (my * tz - mz * ty);
@@ -138,16 +171,37 @@ __device__ __forceinline__ Kick<T> boris_kick(T ux, T uy, T uz, T ex, T ey, T ez
   o.duy = (hey + hey) + ry;
   o.duz = (hez + hez) + rz;
   const T nx = ux + o.dux, ny = uy + o.duy, nz = uz + o.duz;
-  const T g0 = sqrt(T(1) + (ux * ux + uy * uy + uz * uz));
-  const T g1 = sqrt(T(1) + (nx * nx + ny * ny + nz * nz));
-  o.dg = (o.dux * (nx + ux) + o.duy * (ny + uy) + o.duz * (nz + uz)) / (g0 + g1);
+  const T q0 = T(1) + (ux * ux + uy * uy + uz * uz);
+  const T q1 = T(1) + (nx * nx + ny * ny + nz * nz);
+  const T g0 = q0 * rsqrt_nr<T>(q0), g1 = q1 * rsqrt_nr<T>(q1);
+  o.dg = (o.dux * (nx + ux) + o.duy * (ny + uy) + o.duz * (nz + uz)) * rcp_nr<T>(g0 + g1);
   return o;
 }
 
-// Periodic wrap of an absolute coordinate into [0, L); a value that rounds to L maps to 0.
+// Drift length per unit momentum, (c_tilde dt or c_tilde dt / dx) / gamma with
+// gamma = sqrt(1 + |u|^2) (Sec. 2: dx/dt = c_tilde beta = c_tilde u / gamma); *ok is
+// false when gamma is not finite.
+template <typename T>
+__device__ __forceinline__ T drift_scale(T ux, T uy, T uz, T cdt, bool* ok) {
+  const T q = T(1) + (ux * ux + uy * uy + uz * uz);
+  const T gi = rsqrt_nr<T>(q);
+  *ok = isfinite(q) && isfinite(gi);
+  return cdt * gi;
+}
+
+// Periodic wrap of an absolute coordinate into [0, L); a value that rounds to L maps
+// to 0.  A step shorter than the box needs one add or subtract (exact for x in
+// [-L, 2L)); longer moves take the floor form.
 __device__ __forceinline__ double wrap_coord(double x, double L) {
-  double y = x - L * floor(x / L);
-  return y >= L ? y - L : y;
+  double y = x;
+  if (y < 0.0) y += L;
+  else if (y >= L) y -= L;
+  if (!(y >= 0.0 && y < L)) {
+    y = y - L * floor(y / L);
+    if (y >= L) y -= L;
+    if (y < 0.0) y = 0.0;
+  }
+  return y;
 }
 
 __device__ __forceinline__ void set_status(uint32_t* status, uint32_t bits) {
