@@ -2,16 +2,19 @@
 """Throughput of the fused RSOL packet step on one MI355X.
 
 A step is one pass of the whole hot path over every packet of the workload: the
-tiled fused kernel (gather E and B, relativistic Boris kick with the RSOL
-factors, exchange deposit, drift), plus the cell re-binning sort amortised
-every --sort-every steps.  Inputs are resident in HBM before the timed region;
-the timed region is exactly --steps steps bracketed by device synchronisation.
+cell-list fused kernel (gather E and B, relativistic Boris kick with the RSOL
+factors, exchange deposit, drift, and the move of every packet into the store of
+its new cell) plus the kernel that adds the per-tile exchange into the grid.  The
+packets are filed into the cell lists once per rsol_step call and copied back to
+the caller's arrays at its end; both are inside the timed region.  Inputs are
+resident in HBM before the timed region; the timed region is exactly --steps steps
+bracketed by device synchronisation.
 
 Prints ONE JSON line: value = particle-updates/s of the FP64 path on the
 workload; "fp32" = the precision form on the same workload; "roofline" = the
 step kernel's algorithmic HBM bytes per launch over its event-timed average
-duration against the 8 TB/s HBM3E peak; "cpu_baseline" = the CPU oracle timed on
-a bounded sample of the same workload.
+duration against the 8 TB/s HBM3E peak; "backward" = the differentiation form;
+"cpu_baseline" = the CPU oracle timed on a bounded sample of the same workload.
 """
 
 import argparse
@@ -96,7 +99,7 @@ def time_path(w, precision, steps, warmup, sort_every):
     traffic = measured_traffic(precision, w.name)
     out = dict(
         value=npk * steps / wall, ms_per_step=wall / steps * 1e3,
-        kernel_ms=kern_s * 1e3, sort_ms=(sort_ms / n_sort) if n_sort else 0.0, sorts=n_sort,
+        kernel_ms=kern_s * 1e3, rebin_ms=(sort_ms / n_sort) if n_sort else 0.0, rebins=n_sort,
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
                       traffic=traffic, bytes_per_packet_step=balg, kernel="cells_step_kernel"),
     )
@@ -175,7 +178,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", type=int, default=2, choices=[2, 4],
                     help="2: 64^3 x 64 ppc Alfven-mode field (default); 4: 128^3 x 32 ppc turbulence")
-    ap.add_argument("--sort-every", type=int, default=4)
+    ap.add_argument("--sort-every", type=int, default=4, help="re-sort interval of the tiled path (RSOL_FLAG_TILED only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
@@ -229,13 +232,13 @@ def main():
                     parallelism="none"),
         roofline=r64["roofline"],
         cpu_baseline=cpu,
-        kernel_ms=r64["kernel_ms"], sort_ms=r64["sort_ms"],
+        kernel_ms=r64["kernel_ms"], rebin_ms=r64["rebin_ms"],
     )
     if bwd:
         line["backward"] = bwd
     if r32:
         line["fp32"] = dict(value=r32["value"], ms_per_step=r32["ms_per_step"], kernel_ms=r32["kernel_ms"],
-                            sort_ms=r32["sort_ms"], dtype="f32", roofline=r32["roofline"],
+                            rebin_ms=r32["rebin_ms"], dtype="f32", roofline=r32["roofline"],
                             speedup_vs_fp64=r32["value"] / r64["value"])
     print(json.dumps(line), flush=True)
 
