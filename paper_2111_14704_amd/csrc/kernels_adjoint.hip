@@ -13,11 +13,14 @@
 // The adjoint of the exchange deposit (a scatter) is a gather of its cotangent, and
 // the adjoint of the moment deposit is a gather of the moment cotangents.
 //
-// These kernels run one thread per packet in the caller's packet order (no re-binning),
-// so stored states and adjoint arrays stay aligned.
+// The step adjoint runs either one thread per packet in the recorded order, or over
+// the step's starting state counting-sorted by tile (the sorted copy carries each
+// packet's index in the recorded order, through which the adjoint arrays are read and
+// written), so that dL/dE and dL/dB accumulate in LDS.
 #include <math.h>
 
 #include "rsol_adjoint.hpp"
+#include "rsol_sort.hpp"
 
 namespace rsol {
 
@@ -131,7 +134,223 @@ __global__ void record_kernel(Packets<T> P, void* slab) {
     slab_store<T>(slab, P, i);
 }
 
-// Reverse of one step for every packet.
+// Node access of the backward step.  GlobalAccess: the grid itself (wrapped indices,
+// device-scope atomics for dL/dE, dL/dB).  TileAccess: a workgroup's LDS copy of the
+// fields (and exchange cotangents) on its tile plus a one-cell halo, with the field
+// gradients accumulated in LDS and added to the grid once per workgroup.
+template <typename T>
+struct GlobalAccess {
+  const T* E;
+  const T* B;
+  const double* ldM;
+  const double* ldE;
+  double* gE;
+  double* gB;
+  int64_t nc;
+  int nx, ny, nz;
+  __device__ __forceinline__ int64_t node(const int base[3], int cx, int cy, int cz) const {
+    return wrapn(base[0] + cx, nx) + (int64_t)nx * (wrapn(base[1] + cy, ny) + (int64_t)ny * wrapn(base[2] + cz, nz));
+  }
+  __device__ __forceinline__ T e(int64_t n, int c) const { return E[c * nc + n]; }
+  __device__ __forceinline__ T b(int64_t n, int c) const { return B[c * nc + n]; }
+  __device__ __forceinline__ bool has_ld() const { return ldM != nullptr; }
+  __device__ __forceinline__ T lm(int64_t n, int c) const { return (T)ldM[c * nc + n]; }
+  __device__ __forceinline__ T le(int64_t n) const { return ldE ? (T)ldE[n] : T(0); }
+  __device__ __forceinline__ void scatter(int64_t n, const V3<T>& lE, const V3<T>& lB, T w) const {
+    atomicAdd(&gE[n], (double)(w * lE.x));
+    atomicAdd(&gE[nc + n], (double)(w * lE.y));
+    atomicAdd(&gE[2 * nc + n], (double)(w * lE.z));
+    atomicAdd(&gB[n], (double)(w * lB.x));
+    atomicAdd(&gB[nc + n], (double)(w * lB.y));
+    atomicAdd(&gB[2 * nc + n], (double)(w * lB.z));
+  }
+};
+
+constexpr int kAdjRegion = 216;  // region cells of a 4x4x4 tile with a one-cell halo
+
+template <typename T>
+struct TileAccess {
+  const T* F;        // [6][kAdjRegion] E then B
+  const double* L;   // [4][kAdjRegion] exchange cotangents, or NULL
+  double* G;         // [6][kAdjRegion] dL/dE then dL/dB accumulators
+  int ox, oy, oz;    // grid coordinates of region cell 0
+  int rx, ry;        // region extents along x and y
+  __device__ __forceinline__ int64_t node(const int base[3], int cx, int cy, int cz) const {
+    return (base[0] + cx - ox) + rx * ((base[1] + cy - oy) + ry * (base[2] + cz - oz));
+  }
+  __device__ __forceinline__ T e(int64_t n, int c) const { return F[c * kAdjRegion + n]; }
+  __device__ __forceinline__ T b(int64_t n, int c) const { return F[(3 + c) * kAdjRegion + n]; }
+  __device__ __forceinline__ bool has_ld() const { return L != nullptr; }
+  __device__ __forceinline__ T lm(int64_t n, int c) const { return (T)L[c * kAdjRegion + n]; }
+  __device__ __forceinline__ T le(int64_t n) const { return (T)L[3 * kAdjRegion + n]; }
+  __device__ __forceinline__ void scatter(int64_t n, const V3<T>& lE, const V3<T>& lB, T w) const {
+    atomicAdd(&G[n], (double)(w * lE.x));
+    atomicAdd(&G[kAdjRegion + n], (double)(w * lE.y));
+    atomicAdd(&G[2 * kAdjRegion + n], (double)(w * lE.z));
+    atomicAdd(&G[3 * kAdjRegion + n], (double)(w * lB.x));
+    atomicAdd(&G[4 * kAdjRegion + n], (double)(w * lB.y));
+    atomicAdd(&G[5 * kAdjRegion + n], (double)(w * lB.z));
+  }
+};
+
+// Reverse of one step for one packet: state (home, f, u0) before the step, lam_x and
+// lam_u hold dL/d(state after) on entry and dL/d(state before) on exit.
+template <int M, typename T, typename A>
+__device__ __forceinline__ void packet_backward(const A& acc, const int home[3], const T f[3], const T u0a[3],
+                                                T lxa[3], T lua[3], const RunConsts& k) {
+  const T h = (T)k.h;
+  const Stencil3<M, T> st = stencil_at<M, T>(home, f);
+  const int base[3] = {st.a[0].base, st.a[1].base, st.a[2].base};
+
+  // ---- recompute the forward gather
+  V3<T> Ep = {0, 0, 0}, Bp = {0, 0, 0};
+  #pragma unroll
+  for (int cz = 0; cz < M; ++cz)
+    #pragma unroll
+    for (int cy = 0; cy < M; ++cy) {
+      const T wyz = st.a[1].w[cy] * st.a[2].w[cz];
+      #pragma unroll
+      for (int cx = 0; cx < M; ++cx) {
+        const int64_t node = acc.node(base, cx, cy, cz);
+        const T w = st.a[0].w[cx] * wyz;
+        Ep.x += w * acc.e(node, 0);
+        Ep.y += w * acc.e(node, 1);
+        Ep.z += w * acc.e(node, 2);
+        Bp.x += w * acc.b(node, 0);
+        Bp.y += w * acc.b(node, 1);
+        Bp.z += w * acc.b(node, 2);
+      }
+    }
+
+  // ---- recompute the Boris kick (Eq. (11)), keeping its intermediates
+  const V3<T> u0 = {u0a[0], u0a[1], u0a[2]};
+  const V3<T> um = axpy(h, Ep, u0);
+  const T gm = sqrt(T(1) + dot(um, um));
+  const T kq = h / gm;
+  const V3<T> t = {kq * Bp.x, kq * Bp.y, kq * Bp.z};
+  const T tt = dot(t, t);
+  const T sf = T(2) / (T(1) + tt);
+  const V3<T> s = {sf * t.x, sf * t.y, sf * t.z};
+  const V3<T> up = [&] {
+    const V3<T> c = cross(um, t);
+    return V3<T>{um.x + c.x, um.y + c.y, um.z + c.z};
+  }();
+  const V3<T> r = cross(up, s);
+  const V3<T> du = {T(2) * h * Ep.x + r.x, T(2) * h * Ep.y + r.y, T(2) * h * Ep.z + r.z};
+  const V3<T> u1 = {u0.x + du.x, u0.y + du.y, u0.z + du.z};
+  const T g1 = sqrt(T(1) + dot(u1, u1));
+
+  // ---- drift adjoint: x1 = x0 + c_tilde dt u1 / g1
+  V3<T> lx = {lxa[0], lxa[1], lxa[2]};
+  V3<T> lu1 = {lua[0], lua[1], lua[2]};
+  {
+    const T cd = (T)k.cdt;
+    const T ig = T(1) / g1;
+    const T ul = dot(u1, lx) * ig * ig * ig;
+    lu1.x += cd * (lx.x * ig - u1.x * ul);
+    lu1.y += cd * (lx.y * ig - u1.y * ul);
+    lu1.z += cd * (lx.z * ig - u1.z * ul);
+  }
+
+  // ---- exchange-deposit adjoint (cotangent of the summed exchange, optional)
+  V3<T> lu0_extra = {0, 0, 0};
+  T gxw[3] = {0, 0, 0};  // d/dx of sum_i W_i (...)
+  if (acc.has_ld()) {
+    V3<T> ldu = {0, 0, 0};
+    T ldg = 0;
+    const T pf = (T)k.pfac, ef = (T)k.efac;
+    const T g0 = sqrt(T(1) + dot(u0, u0));
+    const T dg = dot(du, V3<T>{u1.x + u0.x, u1.y + u0.y, u1.z + u0.z}) / (g0 + g1);
+    #pragma unroll
+    for (int cz = 0; cz < M; ++cz)
+      #pragma unroll
+      for (int cy = 0; cy < M; ++cy)
+        #pragma unroll
+        for (int cx = 0; cx < M; ++cx) {
+          const int64_t node = acc.node(base, cx, cy, cz);
+          const T w = st.a[0].w[cx] * st.a[1].w[cy] * st.a[2].w[cz];
+          const T lmx = acc.lm(node, 0), lmy = acc.lm(node, 1), lmz = acc.lm(node, 2);
+          const T le = acc.le(node);
+          ldu.x += pf * w * lmx;
+          ldu.y += pf * w * lmy;
+          ldu.z += pf * w * lmz;
+          ldg += ef * w * le;
+          const T val = pf * (du.x * lmx + du.y * lmy + du.z * lmz) + ef * dg * le;
+          gxw[0] += st.dw[0][cx] * st.a[1].w[cy] * st.a[2].w[cz] * val;
+          gxw[1] += st.a[0].w[cx] * st.dw[1][cy] * st.a[2].w[cz] * val;
+          gxw[2] += st.a[0].w[cx] * st.a[1].w[cy] * st.dw[2][cz] * val;
+        }
+    // du = u1 - u0, dgamma = gamma(u1) - gamma(u0)
+    lu1.x += ldu.x + ldg * u1.x / g1;
+    lu1.y += ldu.y + ldg * u1.y / g1;
+    lu1.z += ldu.z + ldg * u1.z / g1;
+    lu0_extra.x = -ldu.x - ldg * u0.x / g0;
+    lu0_extra.y = -ldu.y - ldg * u0.y / g0;
+    lu0_extra.z = -ldu.z - ldg * u0.z / g0;
+  }
+
+  // ---- Boris adjoint, in reverse order of the forward sequence
+  // u1 = u+ + h E,  u+ = u- + u' x s
+  V3<T> lE = {h * lu1.x, h * lu1.y, h * lu1.z};
+  V3<T> lum = lu1;
+  const V3<T> lup = cross(s, lu1);   // d/du' of lu1 . (u' x s)
+  const V3<T> ls = cross(lu1, up);   // d/ds  of lu1 . (u' x s)
+  // u' = u- + u- x t
+  {
+    const V3<T> c = cross(t, lup);
+    lum.x += lup.x + c.x;
+    lum.y += lup.y + c.y;
+    lum.z += lup.z + c.z;
+  }
+  V3<T> lt = cross(lup, um);
+  // s = sf t, sf = 2/(1 + t.t): ds/dt = sf I - sf^2 t t^T
+  {
+    const T tl = dot(t, ls);
+    lt.x += sf * ls.x - sf * sf * tl * t.x;
+    lt.y += sf * ls.y - sf * sf * tl * t.y;
+    lt.z += sf * ls.z - sf * sf * tl * t.z;
+  }
+  // t = (h/gm) B_p
+  const V3<T> lB = {kq * lt.x, kq * lt.y, kq * lt.z};
+  const T lgm = -(kq / gm) * dot(Bp, lt);
+  // gm = sqrt(1 + u-.u-)
+  lum.x += lgm * um.x / gm;
+  lum.y += lgm * um.y / gm;
+  lum.z += lgm * um.z / gm;
+  // u- = u0 + h E
+  lE.x += h * lum.x;
+  lE.y += h * lum.y;
+  lE.z += h * lum.z;
+
+  // ---- gather adjoint: scatter into gE, gB and the weight-gradient term for x
+  #pragma unroll
+  for (int cz = 0; cz < M; ++cz)
+    #pragma unroll
+    for (int cy = 0; cy < M; ++cy) {
+      const T wy_wz = st.a[1].w[cy] * st.a[2].w[cz];
+      #pragma unroll
+      for (int cx = 0; cx < M; ++cx) {
+        const int64_t node = acc.node(base, cx, cy, cz);
+        const T w = st.a[0].w[cx] * wy_wz;
+        acc.scatter(node, lE, lB, w);
+        const T val = acc.e(node, 0) * lE.x + acc.e(node, 1) * lE.y + acc.e(node, 2) * lE.z +
+                      acc.b(node, 0) * lB.x + acc.b(node, 1) * lB.y + acc.b(node, 2) * lB.z;
+        gxw[0] += st.dw[0][cx] * wy_wz * val;
+        gxw[1] += st.a[0].w[cx] * st.dw[1][cy] * st.a[2].w[cz] * val;
+        gxw[2] += st.a[0].w[cx] * st.a[1].w[cy] * st.dw[2][cz] * val;
+      }
+    }
+  const T inv_dx = (T)k.inv_dx;
+  lxa[0] = lx.x + gxw[0] * inv_dx;
+  lxa[1] = lx.y + gxw[1] * inv_dx;
+  lxa[2] = lx.z + gxw[2] * inv_dx;
+  lua[0] = lum.x + lu0_extra.x;
+  lua[1] = lum.y + lu0_extra.y;
+  lua[2] = lum.z + lu0_extra.z;
+}
+
+// Reverse of one step for every packet, in the recorded order, with device-scope
+// atomics into the field gradients.
 template <int M, typename T>
 __global__ void __launch_bounds__(kBlock) step_backward_kernel(const void* __restrict__ slab, int64_t np,
                                                                T* __restrict__ lam_x, T* __restrict__ lam_u,
@@ -140,177 +359,121 @@ __global__ void __launch_bounds__(kBlock) step_backward_kernel(const void* __res
                                                                const double* __restrict__ lam_dE,
                                                                double* __restrict__ gE, double* __restrict__ gB,
                                                                RunConsts k) {
-  const int64_t nc = k.ncells;
-  const T h = (T)k.h;
-  const T inv_dx = (T)k.inv_dx;
+  GlobalAccess<T> acc{E, B, lam_dM, lam_dE, gE, gB, (int64_t)k.ncells, k.nx, k.ny, k.nz};
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
     int home[3];
     T f[3], u0a[3];
     double xa[3];
     slab_load<T>(slab, np, i, k, home, f, xa, u0a);
-    const Stencil3<M, T> st = stencil_at<M, T>(home, f);
-
-    // ---- recompute the forward gather
-    V3<T> Ep = {0, 0, 0}, Bp = {0, 0, 0};
+    T lx[3] = {lam_x[i], lam_x[np + i], lam_x[2 * np + i]};
+    T lu[3] = {lam_u[i], lam_u[np + i], lam_u[2 * np + i]};
+    packet_backward<M, T>(acc, home, f, u0a, lx, lu, k);
     #pragma unroll
-    for (int cz = 0; cz < M; ++cz) {
-      const int iz = wrapn(st.a[2].base + cz, k.nz);
-      #pragma unroll
-      for (int cy = 0; cy < M; ++cy) {
-        const int iy = wrapn(st.a[1].base + cy, k.ny);
-        const T wyz = st.a[1].w[cy] * st.a[2].w[cz];
-        #pragma unroll
-        for (int cx = 0; cx < M; ++cx) {
-          const int64_t node = wrapn(st.a[0].base + cx, k.nx) + (int64_t)k.nx * (iy + (int64_t)k.ny * iz);
-          const T w = st.a[0].w[cx] * wyz;
-          Ep.x += w * E[node];
-          Ep.y += w * E[nc + node];
-          Ep.z += w * E[2 * nc + node];
-          Bp.x += w * B[node];
-          Bp.y += w * B[nc + node];
-          Bp.z += w * B[2 * nc + node];
-        }
-      }
+    for (int d = 0; d < 3; ++d) {
+      lam_x[d * np + i] = lx[d];
+      lam_u[d * np + i] = lu[d];
     }
-
-    // ---- recompute the Boris kick (Eq. (11)), keeping its intermediates
-    const V3<T> u0 = {u0a[0], u0a[1], u0a[2]};
-    const V3<T> um = axpy(h, Ep, u0);
-    const T gm = sqrt(T(1) + dot(um, um));
-    const T kq = h / gm;
-    const V3<T> t = {kq * Bp.x, kq * Bp.y, kq * Bp.z};
-    const T tt = dot(t, t);
-    const T sf = T(2) / (T(1) + tt);
-    const V3<T> s = {sf * t.x, sf * t.y, sf * t.z};
-    const V3<T> up = [&] {
-      const V3<T> c = cross(um, t);
-      return V3<T>{um.x + c.x, um.y + c.y, um.z + c.z};
-    }();
-    const V3<T> r = cross(up, s);
-    const V3<T> du = {T(2) * h * Ep.x + r.x, T(2) * h * Ep.y + r.y, T(2) * h * Ep.z + r.z};
-    const V3<T> u1 = {u0.x + du.x, u0.y + du.y, u0.z + du.z};
-    const T g1 = sqrt(T(1) + dot(u1, u1));
-
-    // ---- drift adjoint: x1 = x0 + c_tilde dt u1 / g1
-    V3<T> lx = {lam_x[i], lam_x[np + i], lam_x[2 * np + i]};
-    V3<T> lu1 = {lam_u[i], lam_u[np + i], lam_u[2 * np + i]};
-    {
-      const T cd = (T)k.cdt;
-      const T ig = T(1) / g1;
-      const T ul = dot(u1, lx) * ig * ig * ig;
-      lu1.x += cd * (lx.x * ig - u1.x * ul);
-      lu1.y += cd * (lx.y * ig - u1.y * ul);
-      lu1.z += cd * (lx.z * ig - u1.z * ul);
-    }
-
-    // ---- exchange-deposit adjoint (cotangent of the summed exchange, optional)
-    V3<T> lu0_extra = {0, 0, 0};
-    T gxw[3] = {0, 0, 0};  // d/dx of sum_i W_i (...)
-    if (lam_dM) {
-      V3<T> ldu = {0, 0, 0};
-      T ldg = 0;
-      const T pf = (T)k.pfac, ef = (T)k.efac;
-      const T g0 = sqrt(T(1) + dot(u0, u0));
-      const T dg = dot(du, V3<T>{u1.x + u0.x, u1.y + u0.y, u1.z + u0.z}) / (g0 + g1);
-      #pragma unroll
-      for (int cz = 0; cz < M; ++cz) {
-        const int iz = wrapn(st.a[2].base + cz, k.nz);
-        #pragma unroll
-        for (int cy = 0; cy < M; ++cy) {
-          const int iy = wrapn(st.a[1].base + cy, k.ny);
-          #pragma unroll
-          for (int cx = 0; cx < M; ++cx) {
-            const int64_t node = wrapn(st.a[0].base + cx, k.nx) + (int64_t)k.nx * (iy + (int64_t)k.ny * iz);
-            const T w = st.a[0].w[cx] * st.a[1].w[cy] * st.a[2].w[cz];
-            const T lmx = (T)lam_dM[node], lmy = (T)lam_dM[nc + node], lmz = (T)lam_dM[2 * nc + node];
-            const T le = lam_dE ? (T)lam_dE[node] : T(0);
-            ldu.x += pf * w * lmx;
-            ldu.y += pf * w * lmy;
-            ldu.z += pf * w * lmz;
-            ldg += ef * w * le;
-            const T val = pf * (du.x * lmx + du.y * lmy + du.z * lmz) + ef * dg * le;
-            gxw[0] += st.dw[0][cx] * st.a[1].w[cy] * st.a[2].w[cz] * val;
-            gxw[1] += st.a[0].w[cx] * st.dw[1][cy] * st.a[2].w[cz] * val;
-            gxw[2] += st.a[0].w[cx] * st.a[1].w[cy] * st.dw[2][cz] * val;
-          }
-        }
-      }
-      // du = u1 - u0, dgamma = gamma(u1) - gamma(u0)
-      lu1.x += ldu.x + ldg * u1.x / g1;
-      lu1.y += ldu.y + ldg * u1.y / g1;
-      lu1.z += ldu.z + ldg * u1.z / g1;
-      lu0_extra.x = -ldu.x - ldg * u0.x / g0;
-      lu0_extra.y = -ldu.y - ldg * u0.y / g0;
-      lu0_extra.z = -ldu.z - ldg * u0.z / g0;
-    }
-
-    // ---- Boris adjoint, in reverse order of the forward sequence
-    // u1 = u+ + h E,  u+ = u- + u' x s
-    V3<T> lE = {h * lu1.x, h * lu1.y, h * lu1.z};
-    V3<T> lum = lu1;
-    const V3<T> lup = cross(s, lu1);   // d/du' of lu1 . (u' x s)
-    const V3<T> ls = cross(lu1, up);   // d/ds  of lu1 . (u' x s)
-    // u' = u- + u- x t
-    {
-      const V3<T> c = cross(t, lup);
-      lum.x += lup.x + c.x;
-      lum.y += lup.y + c.y;
-      lum.z += lup.z + c.z;
-    }
-    V3<T> lt = cross(lup, um);
-    // s = sf t, sf = 2/(1 + t.t): ds/dt = sf I - sf^2 t t^T
-    {
-      const T tl = dot(t, ls);
-      lt.x += sf * ls.x - sf * sf * tl * t.x;
-      lt.y += sf * ls.y - sf * sf * tl * t.y;
-      lt.z += sf * ls.z - sf * sf * tl * t.z;
-    }
-    // t = (h/gm) B_p
-    const V3<T> lB = {kq * lt.x, kq * lt.y, kq * lt.z};
-    const T lgm = -(kq / gm) * dot(Bp, lt);
-    // gm = sqrt(1 + u-.u-)
-    lum.x += lgm * um.x / gm;
-    lum.y += lgm * um.y / gm;
-    lum.z += lgm * um.z / gm;
-    // u- = u0 + h E
-    lE.x += h * lum.x;
-    lE.y += h * lum.y;
-    lE.z += h * lum.z;
-    const V3<T> lu0 = {lum.x + lu0_extra.x, lum.y + lu0_extra.y, lum.z + lu0_extra.z};
-
-    // ---- gather adjoint: scatter into gE, gB and the weight-gradient term for x
-    #pragma unroll
-    for (int cz = 0; cz < M; ++cz) {
-      const int iz = wrapn(st.a[2].base + cz, k.nz);
-      #pragma unroll
-      for (int cy = 0; cy < M; ++cy) {
-        const int iy = wrapn(st.a[1].base + cy, k.ny);
-        #pragma unroll
-        for (int cx = 0; cx < M; ++cx) {
-          const int64_t node = wrapn(st.a[0].base + cx, k.nx) + (int64_t)k.nx * (iy + (int64_t)k.ny * iz);
-          const T wy_wz = st.a[1].w[cy] * st.a[2].w[cz];
-          const T w = st.a[0].w[cx] * wy_wz;
-          atomicAdd(&gE[node], (double)(w * lE.x));
-          atomicAdd(&gE[nc + node], (double)(w * lE.y));
-          atomicAdd(&gE[2 * nc + node], (double)(w * lE.z));
-          atomicAdd(&gB[node], (double)(w * lB.x));
-          atomicAdd(&gB[nc + node], (double)(w * lB.y));
-          atomicAdd(&gB[2 * nc + node], (double)(w * lB.z));
-          const T val = E[node] * lE.x + E[nc + node] * lE.y + E[2 * nc + node] * lE.z + B[node] * lB.x +
-                        B[nc + node] * lB.y + B[2 * nc + node] * lB.z;
-          gxw[0] += st.dw[0][cx] * wy_wz * val;
-          gxw[1] += st.a[0].w[cx] * st.dw[1][cy] * st.a[2].w[cz] * val;
-          gxw[2] += st.a[0].w[cx] * st.a[1].w[cy] * st.dw[2][cz] * val;
-        }
-      }
-    }
-    lam_x[i] = lx.x + gxw[0] * inv_dx;
-    lam_x[np + i] = lx.y + gxw[1] * inv_dx;
-    lam_x[2 * np + i] = lx.z + gxw[2] * inv_dx;
-    lam_u[i] = lu0.x;
-    lam_u[np + i] = lu0.y;
-    lam_u[2 * np + i] = lu0.z;
   }
+}
+
+// Reverse of one step with the packets grouped by tile (the step's starting state
+// counting-sorted into `S`, S.id = the packets' indices in the recorded order): each
+// workgroup takes one part of one tile's packets, stages the fields of the tile and
+// its halo in LDS, accumulates dL/dE, dL/dB there, and adds the region to the grid
+// with one atomic per node and component.
+template <int M, typename T>
+__global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> S, const int32_t* __restrict__ offsets,
+                                                                     Tiling tl, int parts, T* __restrict__ lam_x,
+                                                                     T* __restrict__ lam_u, const T* __restrict__ E,
+                                                                     const T* __restrict__ B,
+                                                                     const double* __restrict__ lam_dM,
+                                                                     const double* __restrict__ lam_dE,
+                                                                     double* __restrict__ gE, double* __restrict__ gB,
+                                                                     RunConsts k) {
+  __shared__ T Fs[6 * kAdjRegion];
+  __shared__ double Ls[4 * kAdjRegion];
+  __shared__ double Gs[6 * kAdjRegion];
+  const int64_t tile = blockIdx.x / parts;
+  const int part = blockIdx.x - (int)(tile * parts);
+  const int ttx = (int)(tile % tl.ntx), tty = (int)((tile / tl.ntx) % tl.nty), ttz = (int)(tile / ((int64_t)tl.ntx * tl.nty));
+  const int ox = ttx * tl.tx - 1, oy = tty * tl.ty - 1, oz = ttz * tl.tz - 1;
+  const int rx = tl.tx + 2, ry = tl.ty + 2, rz = tl.tz + 2;
+  const int rc = rx * ry * rz;
+  const int64_t nc = k.ncells, np = S.np;
+  const bool ld = lam_dM != nullptr;
+  for (int r = threadIdx.x; r < rc; r += blockDim.x) {
+    const int ax = r % rx, ay = (r / rx) % ry, az = r / (rx * ry);
+    const int64_t g = wrapn(ox + ax, k.nx) + (int64_t)k.nx * (wrapn(oy + ay, k.ny) + (int64_t)k.ny * wrapn(oz + az, k.nz));
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      Fs[d * kAdjRegion + r] = E[d * nc + g];
+      Fs[(3 + d) * kAdjRegion + r] = B[d * nc + g];
+    }
+    if (ld) {
+      #pragma unroll
+      for (int d = 0; d < 3; ++d) Ls[d * kAdjRegion + r] = lam_dM[d * nc + g];
+      Ls[3 * kAdjRegion + r] = lam_dE ? lam_dE[g] : 0.0;
+    }
+    #pragma unroll
+    for (int d = 0; d < 6; ++d) Gs[d * kAdjRegion + r] = 0.0;
+  }
+  __syncthreads();
+  TileAccess<T> acc{Fs, ld ? Ls : nullptr, Gs, ox, oy, oz, rx, ry};
+  const int64_t b0 = offsets[tile * tl.cells_per_tile], b1 = offsets[(tile + 1) * tl.cells_per_tile];
+  const int64_t len = b1 - b0;
+  const int64_t j0 = b0 + len * part / parts, j1 = b0 + len * (part + 1) / parts;
+  const int n3[3] = {k.nx, k.ny, k.nz};
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+    int home[3];
+    T f[3], u0a[3];
+    if constexpr (is_fp64<T>()) {
+      #pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double q = S.x[d * np + j] * k.inv_dx;
+        const double fl = floor(q);
+        home[d] = wrapn((int)fl, n3[d]);  // the sort's home cell
+        f[d] = q - fl;
+        u0a[d] = S.u[d * np + j];
+      }
+    } else {
+      const int c = S.cell[j];
+      const int nxy = k.nx * k.ny;
+      home[2] = c / nxy;
+      const int rr = c - home[2] * nxy;
+      home[1] = rr / k.nx;
+      home[0] = rr - home[1] * k.nx;
+      #pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        f[d] = S.off[d * np + j];
+        u0a[d] = S.u[d * np + j];
+      }
+    }
+    const int64_t i = S.id[j];
+    T lx[3] = {lam_x[i], lam_x[np + i], lam_x[2 * np + i]};
+    T lu[3] = {lam_u[i], lam_u[np + i], lam_u[2 * np + i]};
+    packet_backward<M, T>(acc, home, f, u0a, lx, lu, k);
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      lam_x[d * np + i] = lx[d];
+      lam_u[d * np + i] = lu[d];
+    }
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < rc; r += blockDim.x) {
+    const int ax = r % rx, ay = (r / rx) % ry, az = r / (rx * ry);
+    const int64_t g = wrapn(ox + ax, k.nx) + (int64_t)k.nx * (wrapn(oy + ay, k.ny) + (int64_t)k.ny * wrapn(oz + az, k.nz));
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double ge = Gs[d * kAdjRegion + r], gb = Gs[(3 + d) * kAdjRegion + r];
+      if (ge != 0.0) atomicAdd(&gE[d * nc + g], ge);
+      if (gb != 0.0) atomicAdd(&gB[d * nc + g], gb);
+    }
+  }
+}
+
+__global__ void iota_kernel(int32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = (int32_t)i;
 }
 
 // Adjoint of rsol_moments at the current state (adds into lam_x, lam_u).
@@ -396,6 +559,34 @@ hipError_t launch_step_backward(int shape, const void* slab, int64_t np, T* lam_
   return hipGetLastError();
 }
 
+bool step_backward_tiled_fits(const Tiling& t) { return (t.tx + 2) * (t.ty + 2) * (t.tz + 2) <= kAdjRegion; }
+
+hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(iota_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, p, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_step_backward_tiled(int shape, const Packets<T>& sorted, const int32_t* offsets, const Tiling& t,
+                                      T* lam_x, T* lam_u, const T* E, const T* B, const double* lam_dM,
+                                      const double* lam_dE, double* gE, double* gB, const RunConsts& k,
+                                      hipStream_t s) {
+  if (!step_backward_tiled_fits(t)) return hipErrorInvalidValue;
+  // split a tile's packets over several workgroups when tiles are few and full
+  const int64_t ntiles = t.ntiles();
+  const int64_t per_tile = (sorted.np + ntiles - 1) / (ntiles > 0 ? ntiles : 1);
+  int parts = (int)((per_tile + 1023) / 1024);
+  parts = parts < 1 ? 1 : (parts > 4 ? 4 : parts);
+  const dim3 grid((unsigned)(ntiles * parts));
+  if (shape == kShapeCIC)
+    hipLaunchKernelGGL((step_backward_tiled_kernel<2, T>), grid, dim3(kBlock), 0, s, sorted, offsets, t, parts, lam_x,
+                       lam_u, E, B, lam_dM, lam_dE, gE, gB, k);
+  else
+    hipLaunchKernelGGL((step_backward_tiled_kernel<3, T>), grid, dim3(kBlock), 0, s, sorted, offsets, t, parts, lam_x,
+                       lam_u, E, B, lam_dM, lam_dE, gE, gB, k);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_moments_backward(int shape, const Packets<T>& P, const double* lrho, const double* lP,
                                    const double* le, T* lam_x, T* lam_u, const RunConsts& k, hipStream_t s) {
@@ -414,7 +605,10 @@ hipError_t launch_moments_backward(int shape, const Packets<T>& P, const double*
                                               const double*, const double*, double*, double*, const RunConsts&, \
                                               hipStream_t);                                                    \
   template hipError_t launch_moments_backward<T>(int, const Packets<T>&, const double*, const double*,         \
-                                                 const double*, T*, T*, const RunConsts&, hipStream_t);
+                                                 const double*, T*, T*, const RunConsts&, hipStream_t);        \
+  template hipError_t launch_step_backward_tiled<T>(int, const Packets<T>&, const int32_t*, const Tiling&, T*, T*, \
+                                                    const T*, const T*, const double*, const double*, double*,    \
+                                                    double*, const RunConsts&, hipStream_t);
 
 RSOL_ADJ_INSTANTIATE(double)
 RSOL_ADJ_INSTANTIATE(float)

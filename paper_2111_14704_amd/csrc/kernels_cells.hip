@@ -37,6 +37,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kTrashSlots = 8 * kThreads;
+constexpr int kRoundSlack = 2;  // quad-loop rounds beyond the tile's mean
 
 __device__ __host__ __forceinline__ int wrapm(int i, int n) {
   i %= n;
@@ -314,6 +315,8 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
   __shared__ int sDcap[kDirs];
   __shared__ int sDoff[kDirs + 1];
   __shared__ int sPre[kDirs + 1];   // prefix of this tile's inbox counts by direction
+  __shared__ int sLo[kCellTileCells + 1];  // prefix of the packets left over past the round cap
+  __shared__ int sR;                // round cap of the quad loop
   // per-wave exchange areas of the quad loop: per lane, the packet's weights and
   // exchange values (Pk) and the lane's partial field sums (Rs)
   __shared__ __attribute__((aligned(16))) T Pk[kThreads / 64][64 * kPkStride<T>];
@@ -343,6 +346,16 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
   const bool valid = home[0] < k.nx && home[1] < k.ny && home[2] < k.nz;
   const int64_t cell = valid ? home[0] + (int64_t)k.nx * (home[1] + (int64_t)k.ny * home[2]) : 0;
   const int n_raw = V.bcnt_in[cell];
+  // the first wave also reads the counts of all 64 cells (lane = cell in tile)
+  int64_t lcell = 0;
+  bool lvalid = false;
+  if (threadIdx.x < kCellTileCells) {
+    const int gx = ttx * kCellTile + (threadIdx.x & 3), gy = tty * kCellTile + ((threadIdx.x >> 2) & 3),
+              gz = ttz * kCellTile + (threadIdx.x >> 4);
+    lvalid = gx < k.nx && gy < k.ny && gz < k.nz;
+    lcell = lvalid ? gx + (int64_t)k.nx * (gy + (int64_t)k.ny * gz) : 0;
+  }
+  const int nl_raw = threadIdx.x < kCellTileCells ? V.bcnt_in[lcell] : 0;
 
   const SlotArrays& S = V.in;
   const T* su = (const T*)S.u;
@@ -406,6 +419,26 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
       if (lane >= o) incl += y;
     }
     if (threadIdx.x <= kDirs) sPre[threadIdx.x] = incl - c;
+    // round cap of the quad loop: the tile's mean rounds per cell, rounded up; a
+    // cell's packets past it are left to the per-packet phase, which spreads them
+    // over the whole workgroup instead of making every wave wait for the fullest cell
+    int nl = lvalid ? (nl_raw < V.cap ? nl_raw : V.cap) : 0;
+    int tot = nl;
+    #pragma unroll
+    for (int o = 1; o < 64; o <<= 1) tot += __shfl_xor(tot, o);
+    const int R = (tot + 4 * kCellTileCells - 1) / (4 * kCellTileCells) + kRoundSlack;
+    const int lo = nl > 4 * R ? nl - 4 * R : 0;
+    int lincl = lo;
+    #pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(lincl, o);
+      if (lane >= o) lincl += y;
+    }
+    sLo[threadIdx.x] = lincl - lo;
+    if (threadIdx.x == kCellTileCells - 1) {
+      sLo[kCellTileCells] = lincl;
+      sR = R > 0 ? R : 1;
+    }
   }
   __syncthreads();
 
@@ -419,6 +452,7 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
     T* rsw = &Rs[threadIdx.x >> 6][0];
     int n = valid ? n_raw : 0;
     n = n < V.cap ? n : V.cap;
+    n = n < 4 * sR ? n : 4 * sR;  // packets past the round cap go to the per-packet phase
 
     // this lane's field components on the 27 nodes around the cell
     T F0[27], F1[27], D[27];
@@ -579,20 +613,11 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
     }
   }
 
-  // ------------------------------------------------------------ inbox: one packet per thread
+  // ------------------------------------------------------------ per packet: leftovers, then inbox
   {
-    const int nin = sPre[kDirs];
-    for (int i = threadIdx.x; i < nin; i += kThreads) {
-      int dir = 0;
-      #pragma unroll
-      for (int d = 1; d < kDirs; ++d) dir += (i >= sPre[d]) ? 1 : 0;
-      const int64_t j = (int64_t)tile * V.per_tile + sDoff[dir] + (i - sPre[dir]);
-      int home[3];
-      T f[3], u[3];
-      double xa[3];
-      int32_t id;
-      load_free<T>(V.in, V.ib0 + j, k, home, f, xa, u, id);
-      // region coordinates of node home-1 (the inbox only holds packets of this tile)
+    // one packet per thread: gather from the staged fields, deposit with LDS atomics
+    auto process = [&](const int home[3], const T f[3], const double xa[3], const T u[3], int32_t id) {
+      // region coordinates of node home-1 (these packets all live in this tile)
       const int bx = home[0] - ttx * kCellTile, by = home[1] - tty * kCellTile, bz = home[2] - ttz * kCellTile;
       T w[9];
       weights3<M, T>(f[0], w);
@@ -631,6 +656,49 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
       int64_t j2 = place(V, ttx, tty, ttz, cntB, cntD, sDcap, sDoff, hn, &to_bucket);
       if (j2 < 0) j2 = place_overflow(V, trash, err);
       store_slot<T>(V.out, j2, to_bucket ? trash : j2, xn, fn, un, id, hn[0] + k.nx * (hn[1] + k.ny * hn[2]));
+    };
+    const int nlo = sLo[kCellTileCells];
+    const int nin = sPre[kDirs];
+    const int R = sR;
+    for (int i = threadIdx.x; i < nlo + nin; i += kThreads) {
+      int home[3];
+      T f[3], u[3];
+      double xa[3] = {0.0, 0.0, 0.0};
+      int32_t id;
+      if (i < nlo) {
+        // leftover packet: cell lc with sLo[lc] <= i < sLo[lc + 1], slot 4R + (i - sLo[lc])
+        int lo = 0, hi = kCellTileCells - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (sLo[mid] <= i) lo = mid;
+          else hi = mid - 1;
+        }
+        const int lc = lo;
+        home[0] = ttx * kCellTile + (lc & 3);
+        home[1] = tty * kCellTile + ((lc >> 2) & 3);
+        home[2] = ttz * kCellTile + (lc >> 4);
+        const int64_t j = ((int64_t)tile * V.cap + 4 * R + (i - sLo[lc])) * kCellTileCells + lc;
+        #pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          if constexpr (is_fp64<T>()) {
+            xa[d] = S.x[d * S.stride + j];
+            const double sc = xa[d] * k.inv_dx;
+            f[d] = sc - floor(sc);
+          } else {
+            f[d] = S.off[d * S.stride + j];
+          }
+          u[d] = su[d * S.stride + j];
+        }
+        id = S.id[j];
+      } else {
+        const int ii = i - nlo;
+        int dir = 0;
+        #pragma unroll
+        for (int d = 1; d < kDirs; ++d) dir += (ii >= sPre[d]) ? 1 : 0;
+        const int64_t j = (int64_t)tile * V.per_tile + sDoff[dir] + (ii - sPre[dir]);
+        load_free<T>(V.in, V.ib0 + j, k, home, f, xa, u, id);
+      }
+      process(home, f, xa, u, id);
     }
   }
 

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "rsol_launch.hpp"
+#include "rsol_sort.hpp"
 
 namespace rsol {
 
@@ -22,6 +23,18 @@ template <typename T>
 hipError_t launch_step_backward(int shape, const void* slab, int64_t np, T* lam_x, T* lam_u, const T* E, const T* B,
                                 const double* lam_dM, const double* lam_dE, double* gE, double* gB,
                                 const RunConsts& k, hipStream_t s);
+
+// Same reverse step with the starting state counting-sorted by tile (launch_sort of the
+// slab with id = the packets' recorded indices into `sorted`, offsets = the sort's bin
+// offsets): dL/dE, dL/dB accumulate per tile in LDS.  Needs a tiling whose tile plus a
+// one-cell halo fits the LDS region (step_backward_tiled_fits).
+bool step_backward_tiled_fits(const Tiling& t);
+hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t s);
+template <typename T>
+hipError_t launch_step_backward_tiled(int shape, const Packets<T>& sorted, const int32_t* offsets, const Tiling& t,
+                                      T* lam_x, T* lam_u, const T* E, const T* B, const double* lam_dM,
+                                      const double* lam_dE, double* gE, double* gB, const RunConsts& k,
+                                      hipStream_t s);
 
 // Adjoint of the moment deposit at the current state, added into lam_x, lam_u.
 template <typename T>

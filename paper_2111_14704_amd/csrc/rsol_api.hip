@@ -30,6 +30,7 @@ struct rsol_ctx {
   float* E32;
   float* B32;
   char* cells_base;     // cell-list buffers of the default step path
+  int32_t* iota;        // 0..np-1: recorded packet indices for the adjoint's sort
   // registered caller arrays
   const double* E;
   const double* B;
@@ -132,6 +133,7 @@ size_t layout(const rsol_params& p, int64_t np, rsol_ctx* h) {
     b32 = take(sizeof(float) * 3 * (size_t)n_cells(p));
   }
   const size_t cl = take(cell_list_bytes(p.nx, p.ny, p.nz, np, p.precision));
+  const size_t io = take(sizeof(int32_t) * (size_t)np + 64);
   if (h) {
     char* s = h->scratch;
     h->status = (uint32_t*)(s + st);
@@ -141,6 +143,7 @@ size_t layout(const rsol_params& p, int64_t np, rsol_ctx* h) {
     h->E32 = fp32(p) ? (float*)(s + e32) : nullptr;
     h->B32 = fp32(p) ? (float*)(s + b32) : nullptr;
     h->cells_base = s + cl;
+    h->iota = (int32_t*)(s + io);
   }
   return off;
 }
@@ -647,15 +650,51 @@ int rsol_step_backward(rsol_handle h, int32_t nsteps, const void* states, void* 
   if (!states || !lam_x || !lam_u || !gE || !gB) return fail(h, RSOL_EINVAL, "NULL pointer");
   const RunConsts k = consts(h);
   const size_t slab = rsol_state_bytes(h);
+  // group each step's starting state by tile (a counting sort of the slab whose ids are
+  // the recorded packet indices) so that dL/dE, dL/dB accumulate in LDS
+  const bool tiled = step_backward_tiled_fits(h->tiling);
+  if (tiled) RSOL_HIP(h, launch_iota(h->iota, h->np, h->stream), "iota");
   for (int32_t n = nsteps - 1; n >= 0; --n) {
     const void* at = (const char*)states + (size_t)n * slab;
-    if (fp32(h->p))
-      RSOL_HIP(h, launch_step_backward<float>(h->p.shape, at, h->np, (float*)lam_x, (float*)lam_u, h->E32, h->B32,
-                                              lam_dM, lam_dE, gE, gB, k, h->stream), "step backward");
-    else
-      RSOL_HIP(h, launch_step_backward<double>(h->p.shape, at, h->np, (double*)lam_x, (double*)lam_u, h->E, h->B,
-                                               lam_dM, lam_dE, gE, gB, k, h->stream), "step backward");
+    if (fp32(h->p)) {
+      if (tiled) {
+        Packets<float> src;
+        src.np = h->np;
+        src.x = nullptr;
+        src.cell = (int32_t*)at;
+        src.off = (float*)at + h->np;
+        src.u = (float*)at + 4 * h->np;
+        src.id = h->iota;
+        RSOL_HIP(h, launch_sort<float>(src, perm_packets<float>(h), k, h->tiling, h->sort_ints, h->stream),
+                 "adjoint sort");
+        RSOL_HIP(h, launch_step_backward_tiled<float>(h->p.shape, perm_packets<float>(h), h->sort_ints, h->tiling,
+                                                      (float*)lam_x, (float*)lam_u, h->E32, h->B32, lam_dM, lam_dE,
+                                                      gE, gB, k, h->stream), "step backward");
+      } else {
+        RSOL_HIP(h, launch_step_backward<float>(h->p.shape, at, h->np, (float*)lam_x, (float*)lam_u, h->E32, h->B32,
+                                                lam_dM, lam_dE, gE, gB, k, h->stream), "step backward");
+      }
+    } else {
+      if (tiled) {
+        Packets<double> src;
+        src.np = h->np;
+        src.x = (double*)at;
+        src.cell = nullptr;
+        src.off = nullptr;
+        src.u = (double*)at + 3 * h->np;
+        src.id = h->iota;
+        RSOL_HIP(h, launch_sort<double>(src, perm_packets<double>(h), k, h->tiling, h->sort_ints, h->stream),
+                 "adjoint sort");
+        RSOL_HIP(h, launch_step_backward_tiled<double>(h->p.shape, perm_packets<double>(h), h->sort_ints, h->tiling,
+                                                       (double*)lam_x, (double*)lam_u, h->E, h->B, lam_dM, lam_dE,
+                                                       gE, gB, k, h->stream), "step backward");
+      } else {
+        RSOL_HIP(h, launch_step_backward<double>(h->p.shape, at, h->np, (double*)lam_x, (double*)lam_u, h->E, h->B,
+                                                 lam_dM, lam_dE, gE, gB, k, h->stream), "step backward");
+      }
+    }
   }
+  h->sorted_valid = false;
   return RSOL_OK;
 }
 
