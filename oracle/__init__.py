@@ -12,10 +12,12 @@ Hopkins, "A Reduced-Speed-of-Light Formulation of the MHD-PIC Method"
 displayed equations in order: (1) Lorentz force, (3) RSOL Vlasov equation,
 (4) packet decomposition, (5) packet momentum equation, (6)-(10) definitions
 of v_eff, beta, gamma, E, p, (11) momentum equation in terms of gamma*beta,
-(12) back-reaction on the gas.
+(12) back-reaction on the gas.  ``coupled_step`` closes the gas side of Eq. (12)
+with a held-fixed density and magnetic field.
 """
 
 from .pic import (  # noqa: F401
     Params, electric_field, courant_dt, shape_weights, gather, deposit, boris_kick,
-    exchange, drift, wrap, moments, step, rollout, lorentz_gamma,
+    exchange, drift, wrap, moments, step, rollout, lorentz_gamma, coupled_step, coupled_rollout,
+    conserved_totals,
 )

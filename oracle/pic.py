@@ -217,3 +217,33 @@ def rollout(x, u, E, B, p: Params, nsteps, keep_history=False):
         dM_sum = dM_sum + dM
         dE_sum = dE_sum + dE
     return dict(x=x, u=u, dM=dM, dE=dE, dM_sum=dM_sum, dE_sum=dE_sum, history=hist)
+
+
+def coupled_step(x, u, mom, egas, rho, B, p: Params):
+    """One packet step coupled to a gas whose density rho and magnetic field B are held
+    fixed (no MHD solver).  The gas velocity is u_gas = mom / rho and the step's electric
+    field is E = -(u_gas/c) x B with the true c (Sec. 2, after Eq. (5)).  After the packet
+    step the gas takes the step's exchange: mom += dM (Eq. (12)) and egas += dE (the same
+    rule applied to the packet energy, Eq. (9)).
+    rho (n_cells), mom (3, n_cells), egas (n_cells).  Returns (x, u, mom, egas)."""
+    E = electric_field(mom / rho, B, p.c)
+    x1, u1, dM, dE = step(x, u, E, B, p)
+    return x1, u1, mom + dM, egas + dE
+
+
+def coupled_rollout(x, u, mom, egas, rho, B, p: Params, nsteps):
+    """nsteps coupled steps.  Returns the final packets and gas state and the electric
+    field of the final gas state (the field the next step would gather)."""
+    for _ in range(nsteps):
+        x, u, mom, egas = coupled_step(x, u, mom, egas, rho, B, p)
+    return dict(x=x, u=u, mom=mom, egas=egas, E=electric_field(mom / rho, B, p.c))
+
+
+def conserved_totals(u, mom, egas, p: Params):
+    """Totals the CR-gas exchange conserves (Sec. 2, discussion after Eq. (12)): the
+    momentum V sum_i (rho u)_i + (c/c_tilde) sum_j P_j with P_j = M_j c u_j, and the
+    energy V sum_i e_i + (c/c_tilde) sum_j M_j c^2 gamma_j.  Returns (momentum (3,), energy)."""
+    k = p.c / p.c_tilde
+    P = p.volume * mom.sum(axis=1) + k * p.mass * p.c * u.sum(axis=1)
+    En = p.volume * egas.sum() + k * p.mass * p.c * p.c * lorentz_gamma(u).sum()
+    return P, En

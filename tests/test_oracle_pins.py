@@ -387,6 +387,125 @@ def test_moment_totals_and_single_packet(shape):
     assert rho1[home] == pytest.approx(0.37 * (0.75 ** 3 if shape == "tsc" else 1.0), rel=1e-15)
 
 
+# ---------------------------------------------------------------- coupled gas (Eq. (12) closed)
+
+_GYR = dict(n=4, c=1000.0, c_tilde=100.0, qomc=4000.0, mass=0.14, rho=2.0, T=0.01, dt0=5e-5)
+
+
+def _coupled_lattice_run(dt):
+    """One packet per cell on the cell centres, all with u0 = (0, 1, 0) across B = x_hat, and
+    a gas of density rho carrying minus (c/c_tilde) times the CR momentum, so the total
+    momentum V rho u + (c/c_tilde) P is zero.  Returns u_y + i u_z of every packet after
+    T/dt coupled steps, the gas state and the Params."""
+    g = _GYR
+    n, nc = g["n"], g["n"] ** 3
+    p = oracle.Params(n, n, n, 1.0, "cic", g["c"], g["c_tilde"], g["qomc"], dt, g["mass"])
+    i = np.arange(nc)
+    x = np.stack([i % n, i // n % n, i // (n * n)]).astype(float) + 0.5
+    u0 = np.array([0.0, 1.0, 0.0])
+    u = np.tile(u0[:, None], (1, nc))
+    B = np.tile(np.array([1.0, 0.0, 0.0])[:, None], (1, nc))
+    rho = np.full(nc, g["rho"])
+    mom = np.tile((-(p.c / p.c_tilde) * p.mass * p.c * u0 / p.volume)[:, None], (1, nc))
+    r = oracle.coupled_rollout(x, u, mom, np.zeros(nc), rho, B, p, int(round(g["T"] / dt)))
+    return r["u"][1] + 1j * r["u"][2], r, p
+
+
+def _coupled_gyration_errors():
+    """|z - z_exact| at dt0, dt0/2, dt0/4 and of the two Richardson extrapolants 2 z(dt/2) - z(dt).
+
+    Closed form: with the gas momentum equal to -(c/c_tilde) M c u / V in every cell,
+    u_gas = mom/rho and E = -(u_gas/c) x B = (c/c_tilde)(M/(rho V)) u x B (Sec. 2, after
+    Eq. (5)), so Eq. (11) becomes du/dt = qomc [M/(rho V) + (c_tilde/c)/gamma] u x B: |u| and
+    gamma stay fixed and u turns about B at that rate.  For B = x_hat, u_y + i u_z advances
+    by exp(-i omega t).  The scheme is first order in dt (the gas field of a step comes from
+    the momentum before the kick), so the extrapolants converge at second order."""
+    g = _GYR
+    omega = g["qomc"] * (g["mass"] / g["rho"] + (g["c_tilde"] / g["c"]) / math.sqrt(2.0))
+    exact = np.exp(-1j * omega * g["T"])
+    zs = [_coupled_lattice_run(g["dt0"] / 2 ** k)[0] for k in range(3)]
+    errs = [float(np.max(np.abs(z - exact))) for z in zs]
+    rich = [float(np.max(np.abs(2 * zs[k + 1] - zs[k] - exact))) for k in range(2)]
+    return errs, rich
+
+
+def _assert_gyration_pin(errs, rich):
+    assert errs[2] < 0.02
+    assert 1.8 < errs[1] / errs[2] < 2.2 and 1.8 < errs[0] / errs[1] < 2.2
+    assert rich[1] < 1e-3 and rich[0] / rich[1] > 3.0
+
+
+def test_coupled_gyration_closed_form():
+    """The coupled packet-gas system turns at qomc |B| (M/(rho V) + (c_tilde/c)/gamma): the gas
+    term carries the sign and the 1/c of E = -(u/c) x B, the division by rho, and the c/c_tilde
+    of Eq. (12); the packet term the c_tilde/c of Eq. (11)."""
+    errs, rich = _coupled_gyration_errors()
+    _assert_gyration_pin(errs, rich)
+    z, r, p = _coupled_lattice_run(_GYR["dt0"] / 4)
+    # the gas follows the packets exactly: every cell keeps zero total momentum
+    k = p.c / p.c_tilde
+    res = p.volume * r["mom"] + k * p.mass * p.c * r["u"]
+    assert np.max(np.abs(res)) < 1e-12 * k * p.mass * p.c
+    assert np.max(np.abs(z - z[0])) < 1e-12
+
+
+def _coupled_conservation_residual():
+    """Largest change of the conserved totals over 8 coupled steps of a small Alfven-wave
+    workload with a non-uniform density, in units of the rounding bound of the sums."""
+    w = make_workload(2, n=8, ppc=4, ratio=30.0)
+    p = oracle_params(w)
+    rng = np.random.default_rng(7)
+    nc = w.n_cells
+    rho = rng.uniform(0.5, 1.5, nc)
+    B = w.B.reshape(3, -1)
+    mom = rho * w.u_gas.reshape(3, -1)
+    egas = rng.uniform(1.0, 2.0, nc)
+    P0, E0 = oracle.conserved_totals(w.u, mom, egas, p)
+    nsteps = 8
+    r = oracle.coupled_rollout(w.x, w.u, mom, egas, rho, B, p, nsteps)
+    P1, E1 = oracle.conserved_totals(r["u"], r["mom"], r["egas"], p)
+    k = p.c / p.c_tilde
+    eps = 2.0 ** -53
+    # each step's deposit and the running sums round at a few ulps of the largest terms
+    scale_p = k * p.mass * p.c * np.abs(w.u).sum() + p.volume * np.abs(mom).sum()
+    scale_e = k * p.mass * p.c ** 2 * oracle.lorentz_gamma(w.u).sum() + p.volume * egas.sum()
+    bound_p = 40 * nsteps * eps * scale_p
+    bound_e = 40 * nsteps * eps * scale_e
+    return max(float(np.max(np.abs(P1 - P0))) / bound_p, abs(E1 - E0) / bound_e)
+
+
+def test_coupled_rollout_conserves_momentum_and_energy():
+    """V sum rho u + (c/c_tilde) sum P and V sum e + (c/c_tilde) sum M c^2 gamma stay fixed to
+    rounding while the gas field evolves (Sec. 2, discussion after Eq. (12))."""
+    assert _coupled_conservation_residual() < 1.0
+
+
+def test_planted_mistakes_fail_the_coupled_pins(monkeypatch):
+    """Plausible mistakes in the coupled step each fail one of the pins above."""
+    pic = oracle.pic
+    good_field, good_exchange = pic.electric_field, pic.exchange
+
+    # E with the wrong sign, and E without the division by rho
+    with monkeypatch.context() as m:
+        m.setattr(pic, "electric_field", lambda u, B, c: -good_field(u, B, c))
+        errs, _ = _coupled_gyration_errors()
+        assert errs[2] > 0.1
+    with monkeypatch.context() as m:
+        def no_rho(x, u, mom, egas, rho, B, p):
+            E = good_field(mom, B, p.c)
+            x1, u1, dM, dE = pic.step(x, u, E, B, p)
+            return x1, u1, mom + dM, egas + dE
+        m.setattr(pic, "coupled_step", no_rho)
+        errs, _ = _coupled_gyration_errors()
+        assert errs[2] > 0.1
+    # exchange missing its c/c_tilde: gyration and conservation both fail
+    with monkeypatch.context() as m:
+        m.setattr(pic, "exchange", lambda u0, u1, p: tuple(v * (p.c_tilde / p.c) for v in good_exchange(u0, u1, p)))
+        errs, _ = _coupled_gyration_errors()
+        assert errs[2] > 0.1
+        assert _coupled_conservation_residual() > 100.0
+
+
 # ---------------------------------------------------------------- reference gradients
 
 def test_complex_step_gradient_matches_central_difference_and_full_rerun():
