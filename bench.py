@@ -13,7 +13,9 @@ bracketed by device synchronisation.
 Prints ONE JSON line: value = particle-updates/s of the FP64 path on the
 workload; "fp32" = the precision form on the same workload; "roofline" = the
 step kernel's algorithmic HBM bytes per launch over its event-timed average
-duration against the 8 TB/s HBM3E peak; "backward" = the differentiation form;
+duration against the 8 TB/s HBM3E peak; "coupled" = the FP64 step coupled to the
+workload's gas (exchange into the gas momentum and energy, E rebuilt every step);
+"backward" = the differentiation form;
 "cpu_baseline" = the CPU oracle timed on a bounded sample of the same workload.
 """
 
@@ -71,21 +73,34 @@ def measured_traffic(precision, workload):
     return rec.get("bytes_per_launch")
 
 
-def time_path(w, precision, steps, warmup, sort_every):
+def time_path(w, precision, steps, warmup, sort_every, coupled=False):
+    """Time `steps` steps in one call.  coupled=True runs them coupled to the workload's
+    seeded gas (rsol_step_coupled: the exchange goes into the gas momentum and energy and
+    E is rebuilt from the gas velocity after every step)."""
     import torch
     from paper_2111_14704_amd.sim import Simulation
+    from workloads import gas_state
 
     sim = Simulation.from_workload(w, precision=precision, sort_every=sort_every)
     h = sim.handle
-    dM = sim.zeros_grid(3)
-    dE = sim.zeros_grid(1)[0]
-    sim.step(warmup, dM, dE)
+    if coupled:
+        rho, mom, egas = (torch.as_tensor(a, dtype=torch.float64, device=sim.device) for a in gas_state(w))
+
+        def run(n):
+            sim.step_coupled(n, rho, mom, egas)
+    else:
+        dM = sim.zeros_grid(3)
+        dE = sim.zeros_grid(1)[0]
+
+        def run(n):
+            sim.step(n, dM, dE)
+    run(warmup)
     h.rsol_check()
     h.rsol_timing(True)
     h.rsol_timing_read()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim.step(steps, dM, dE)
+    run(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     step_ms, n_step, sort_ms, n_sort = h.rsol_timing_read()
@@ -182,6 +197,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--no-coupled", action="store_true", help="skip the run coupled to the gas")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="first run one plain device copy of BYTES bytes (a known-size reference for HBM counters)")
     args = ap.parse_args()
@@ -218,6 +234,11 @@ def main():
         b32 = time_backward("fp32")
         bwd["fp32"] = dict(value=b32["value"], backward_s=b32["backward_s"])
         print(f"[bench] backward fp32 {b32['value']:.3e} upd/s", file=sys.stderr, flush=True)
+    rc = None
+    if not args.no_coupled:
+        rc = time_path(w, "fp64", args.steps, args.warmup, args.sort_every, coupled=True)
+        print(f"[bench] coupled fp64 {rc['value']:.3e} upd/s, kernel {rc['kernel_ms']:.3f} ms", file=sys.stderr,
+              flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w)
@@ -240,6 +261,9 @@ def main():
         line["fp32"] = dict(value=r32["value"], ms_per_step=r32["ms_per_step"], kernel_ms=r32["kernel_ms"],
                             rebin_ms=r32["rebin_ms"], dtype="f32", roofline=r32["roofline"],
                             speedup_vs_fp64=r32["value"] / r64["value"])
+    if rc:
+        line["coupled"] = dict(value=rc["value"], ms_per_step=rc["ms_per_step"], kernel_ms=rc["kernel_ms"],
+                               dtype="f64", overhead_vs_static=rc["ms_per_step"] / r64["ms_per_step"] - 1.0)
     print(json.dumps(line), flush=True)
 
 

@@ -151,6 +151,24 @@ int rsol_sort(rsol_handle h);
  * RSOL_FLAG_KEEP_ORDER: packet order unchanged. */
 int rsol_step(rsol_handle h, int32_t nsteps, double* dM, double* dE);
 
+/* nsteps packet steps coupled to a gas whose density and magnetic field are held
+ * fixed (no MHD solver).  Every step gathers E = -(u_gas/c) x B built from the gas
+ * velocity u_gas = mom/rho with the true c (Sec. 2, after Eq. (5)); the step's exchange
+ * is added into the gas, mom += dM and egas += dE (Eq. (12) and the same rule for the
+ * packet energy of Eq. (9)), and E is rebuilt from the new mom before the next step.
+ * The sums V sum mom + (c/c_tilde) sum_j M c u_j and V sum egas + (c/c_tilde) sum_j
+ * M c^2 gamma_j are conserved up to rounding (Sec. 2, discussion after Eq. (12)).
+ *   rho  [n_cells]     gas density (> 0), in
+ *   mom  [3][n_cells]  gas momentum density rho u, in/out
+ *   egas [n_cells]     gas energy density, in/out (NULL: not tracked)
+ *   E    [3][n_cells]  out: on return the field of the final gas state.  E becomes the
+ *                      handle's registered electric field (in place of the one given
+ *                      to rsol_set_fields); B stays the registered one.
+ * dt stays the handle's.  Packet order and paths follow rsol_step and its flags.
+ * Errors: RSOL_EINVAL for NULL rho/mom/E or arrays that alias each other or B,
+ * RSOL_ESTATE before fields, packets and dt are set; step errors as rsol_step. */
+int rsol_step_coupled(rsol_handle h, int32_t nsteps, const double* rho, double* mom, double* egas, double* E);
+
 /* CR moments of the current state (Sec. 2 packet totals): rho[n_cells] = sum M W / V,
  * P[3][n_cells] = sum M c u W / V, e[n_cells] = sum M c^2 gamma W / V.  Outputs are
  * overwritten; any may be NULL. */

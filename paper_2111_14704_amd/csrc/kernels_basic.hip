@@ -35,6 +35,10 @@ __global__ void electric_field_kernel(const double* __restrict__ u, const double
   }
 }
 
+__global__ void gas_field_kernel(GasLink g, int64_t nc) {
+  for (int64_t i = gtid(); i < nc; i += gstride()) gas_refresh(g, i, nc);
+}
+
 __global__ void to_fp32_kernel(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
   for (int64_t i = gtid(); i < n; i += gstride()) dst[i] = (float)src[i];
 }
@@ -399,6 +403,11 @@ hipError_t launch_electric_field(const double* u_gas, const double* B, double* E
                                  hipStream_t s) {
   hipLaunchKernelGGL(electric_field_kernel, dim3(grid_for(ncells)), dim3(kBlock), 0, s, u_gas, B, E, ncells,
                      1.0 / c);
+  return hipGetLastError();
+}
+
+hipError_t launch_gas_field(const GasLink& g, int64_t ncells, hipStream_t s) {
+  hipLaunchKernelGGL(gas_field_kernel, dim3(grid_for(ncells)), dim3(kBlock), 0, s, g, ncells);
   return hipGetLastError();
 }
 

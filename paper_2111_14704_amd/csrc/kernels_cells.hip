@@ -786,8 +786,10 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
 
 // After a step: add the per-tile exchange accumulators into the grid (a cell takes
 // every region slot, of its own tile and of neighbouring tiles' halos, that maps onto
-// it) and clear the overflow counter of the buffer the step consumed.
-__global__ void cells_post_kernel(StepView V, double* __restrict__ dM, double* __restrict__ dE, RunConsts k) {
+// it) and clear the overflow counter of the buffer the step consumed.  In a coupled
+// step dM, dE are the gas momentum and energy, and the cell's E is refreshed from the
+// updated momentum.
+__global__ void cells_post_kernel(StepView V, double* dM, double* dE, GasLink gas, RunConsts k) {
   const int64_t nc = k.ncells;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   if (blockIdx.x == 0 && threadIdx.x == 0) V.icnt_in[V.ntiles * kDirs] = 0;
@@ -828,6 +830,7 @@ __global__ void cells_post_kernel(StepView V, double* __restrict__ dM, double* _
     dM[nc + c] += s[1];
     dM[2 * nc + c] += s[2];
     if (dE) dE[c] += s[3];
+    if (gas.rho) gas_refresh(gas, c, nc);
   }
 }
 
@@ -1099,7 +1102,8 @@ hipError_t launch_cells_build(const Packets<T>& P, CellLists& L, const RunConsts
 
 template <typename T>
 hipError_t launch_cells_step(int shape, CellLists& L, const T* E, const T* B, double* dM, double* dE,
-                             const RunConsts& k, hipStream_t s, hipEvent_t before, hipEvent_t after) {
+                             const GasLink& gas, const RunConsts& k, hipStream_t s, hipEvent_t before,
+                             hipEvent_t after) {
   const StepView V = step_view(L);
   if (before) (void)hipEventRecord(before, s);
   const dim3 grid((unsigned)L.ntiles), block(kThreads);
@@ -1114,7 +1118,7 @@ hipError_t launch_cells_step(int shape, CellLists& L, const T* E, const T* B, do
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t work = dM ? (int64_t)k.ncells : 1;
-  hipLaunchKernelGGL(cells_post_kernel, dim3(grid_for(work)), dim3(kThreads), 0, s, V, dM, dE, k);
+  hipLaunchKernelGGL(cells_post_kernel, dim3(grid_for(work)), dim3(kThreads), 0, s, V, dM, dE, gas, k);
   L.cur = 1 - L.cur;
   return hipGetLastError();
 }
@@ -1137,8 +1141,8 @@ hipError_t launch_cells_compact(const Packets<T>& P, CellLists& L, const RunCons
 
 #define RSOL_CELLS_INSTANTIATE(T)                                                                                  \
   template hipError_t launch_cells_build<T>(const Packets<T>&, CellLists&, const RunConsts&, hipStream_t);         \
-  template hipError_t launch_cells_step<T>(int, CellLists&, const T*, const T*, double*, double*, const RunConsts&, \
-                                           hipStream_t, hipEvent_t, hipEvent_t);                                   \
+  template hipError_t launch_cells_step<T>(int, CellLists&, const T*, const T*, double*, double*, const GasLink&,   \
+                                           const RunConsts&, hipStream_t, hipEvent_t, hipEvent_t);                 \
   template hipError_t launch_cells_compact<T>(const Packets<T>&, CellLists&, const RunConsts&, hipStream_t);
 
 RSOL_CELLS_INSTANTIATE(double)

@@ -296,7 +296,7 @@ int do_sort(rsol_ctx* h, bool copy) {
 // Default path: caller arrays -> cell buckets, nsteps cell-list steps, buckets ->
 // caller arrays (cell-major).
 template <typename T>
-int do_step_cells(rsol_ctx* h, int32_t nsteps, double* dM, double* dE) {
+int do_step_cells(rsol_ctx* h, int32_t nsteps, double* dM, double* dE, const GasLink& gas) {
   const RunConsts k = consts(h);
   const Packets<T> P = caller_packets<T>(h);
   auto ev = timed_begin(h);
@@ -308,8 +308,8 @@ int do_step_cells(rsol_ctx* h, int32_t nsteps, double* dM, double* dE) {
       pr.first = take_event(h);
       pr.second = take_event(h);
     }
-    RSOL_HIP(h, launch_cells_step<T>(h->p.shape, h->cells, field_E<T>(h), field_B<T>(h), dM, dE, k, h->stream,
-                                     pr.first, pr.second),
+    RSOL_HIP(h, launch_cells_step<T>(h->p.shape, h->cells, field_E<T>(h), field_B<T>(h), dM, dE, gas, k,
+                                     h->stream, pr.first, pr.second),
              "step (cells)");
     if (pr.first && pr.second) h->ev_step.push_back(pr);
   }
@@ -321,8 +321,9 @@ int do_step_cells(rsol_ctx* h, int32_t nsteps, double* dM, double* dE) {
 }
 
 template <typename T>
-int do_step(rsol_ctx* h, int32_t nsteps, double* dM, double* dE) {
-  if ((h->p.flags & (RSOL_FLAG_KEEP_ORDER | RSOL_FLAG_TILED)) == 0) return do_step_cells<T>(h, nsteps, dM, dE);
+int do_step(rsol_ctx* h, int32_t nsteps, double* dM, double* dE, const GasLink& gas) {
+  if ((h->p.flags & (RSOL_FLAG_KEEP_ORDER | RSOL_FLAG_TILED)) == 0)
+    return do_step_cells<T>(h, nsteps, dM, dE, gas);
   const RunConsts k = consts(h);
   const bool global = (h->p.flags & RSOL_FLAG_KEEP_ORDER) != 0 || !h->plan.tiled;
   for (int32_t s = 0; s < nsteps; ++s) {
@@ -333,6 +334,7 @@ int do_step(rsol_ctx* h, int32_t nsteps, double* dM, double* dE) {
                "step (global)");
       timed_end(h, ev, false);
       h->sorted_valid = false;
+      if (gas.rho) RSOL_HIP(h, launch_gas_field(gas, n_cells(h->p), h->stream), "gas field");
       continue;
     }
     bool from_perm = false;
@@ -348,6 +350,7 @@ int do_step(rsol_ctx* h, int32_t nsteps, double* dM, double* dE) {
              "step (tiled)");
     timed_end(h, ev, false);
     h->steps_since_sort += 1;
+    if (gas.rho) RSOL_HIP(h, launch_gas_field(gas, n_cells(h->p), h->stream), "gas field");
   }
   return RSOL_OK;
 }
@@ -585,7 +588,30 @@ int rsol_step(rsol_handle h, int32_t nsteps, double* dM, double* dE) {
   if (!(h->p.dt > 0)) return fail(h, RSOL_ESTATE, "dt not set");
   if (!dM && dE) return fail(h, RSOL_EINVAL, "dE without dM");
   if (h->np == 0 || nsteps == 0) return RSOL_OK;
-  return fp32(h->p) ? do_step<float>(h, nsteps, dM, dE) : do_step<double>(h, nsteps, dM, dE);
+  const GasLink none{};
+  return fp32(h->p) ? do_step<float>(h, nsteps, dM, dE, none) : do_step<double>(h, nsteps, dM, dE, none);
+}
+
+int rsol_step_coupled(rsol_handle h, int32_t nsteps, const double* rho, double* mom, double* egas, double* E) {
+  if (int rc = need(h, true, true)) return rc;
+  if (nsteps < 0) return fail(h, RSOL_EINVAL, "nsteps < 0");
+  if (!(h->p.dt > 0)) return fail(h, RSOL_ESTATE, "dt not set");
+  if (!rho || !mom || !E) return fail(h, RSOL_EINVAL, "NULL gas pointer");
+  const double* Ec = E;
+  if (Ec == h->B || Ec == rho || E == mom || (egas && (E == egas || egas == mom)))
+    return fail(h, RSOL_EINVAL, "gas arrays alias each other or B");
+  GasLink g{};
+  g.rho = rho;
+  g.mom = mom;
+  g.egas = egas;
+  g.B = h->B;
+  g.E = E;
+  g.E32 = fp32(h->p) ? h->E32 : nullptr;
+  g.inv_c = 1.0 / h->p.c;
+  h->E = E;
+  RSOL_HIP(h, launch_gas_field(g, n_cells(h->p), h->stream), "gas field");
+  if (h->np == 0 || nsteps == 0) return RSOL_OK;
+  return fp32(h->p) ? do_step<float>(h, nsteps, mom, egas, g) : do_step<double>(h, nsteps, mom, egas, g);
 }
 
 int rsol_moments(rsol_handle h, double* rho, double* P, double* e) {

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "rsol_launch.hpp"
 #include "rsol_particles.hpp"
 
 namespace rsol {
@@ -72,10 +73,13 @@ int64_t cell_list_scan_entries(int nx, int ny, int nz);
 template <typename T>
 hipError_t launch_cells_build(const Packets<T>& P, CellLists& L, const RunConsts& k, hipStream_t s);
 // One step: buffer cur -> buffer 1-cur; exchange added into dM/dE if dM != NULL.
-// `before`/`after` (may be NULL) are recorded around the step kernel itself.
+// With gas.rho set (then dM = gas.mom, dE = gas.egas) the kernel that adds the
+// exchange into the grid also refreshes the gas field E.  `before`/`after` (may be
+// NULL) are recorded around the step kernel itself.
 template <typename T>
 hipError_t launch_cells_step(int shape, CellLists& L, const T* E, const T* B, double* dM, double* dE,
-                             const RunConsts& k, hipStream_t s, hipEvent_t before, hipEvent_t after);
+                             const GasLink& gas, const RunConsts& k, hipStream_t s, hipEvent_t before,
+                             hipEvent_t after);
 // Buffer cur -> caller packets, cell-major (buckets by cell, then inboxes, then overflow).
 template <typename T>
 hipError_t launch_cells_compact(const Packets<T>& P, CellLists& L, const RunConsts& k, hipStream_t s);

@@ -12,7 +12,40 @@ namespace rsol {
 constexpr int kShapeCIC = 1;
 constexpr int kShapeTSC = 2;
 
+// Gas side of a coupled step (density and magnetic field held fixed, no MHD solver).
+// The step's exchange is added into the gas momentum mom and energy egas (Eq. (12));
+// afterwards every cell refreshes u_gas = mom/rho and E = -(u_gas/c) x B with the true
+// c (Sec. 2, after Eq. (5)), writing E and, in the FP32 form, its float copy.
+struct GasLink {
+  const double* rho;  // [n_cells] gas density; NULL when the step is not coupled
+  double* mom;        // [3][n_cells] gas momentum density rho u (the step's dM)
+  double* egas;       // [n_cells] gas energy density (the step's dE), may be NULL
+  const double* B;    // [3][n_cells]
+  double* E;          // [3][n_cells] out
+  float* E32;         // [3][n_cells] FP32 copy of E, or NULL
+  double inv_c;       // 1/c
+};
+
+// E of one cell from its gas momentum (the refresh of a coupled step).
+__device__ __forceinline__ void gas_refresh(const GasLink& g, int64_t c, int64_t nc) {
+  const double r = g.rho[c];
+  const double ux = g.mom[c] / r, uy = g.mom[nc + c] / r, uz = g.mom[2 * nc + c] / r;
+  const double bx = g.B[c], by = g.B[nc + c], bz = g.B[2 * nc + c];
+  const double ex = -(uy * bz - uz * by) * g.inv_c;
+  const double ey = -(uz * bx - ux * bz) * g.inv_c;
+  const double ez = -(ux * by - uy * bx) * g.inv_c;
+  g.E[c] = ex;
+  g.E[nc + c] = ey;
+  g.E[2 * nc + c] = ez;
+  if (g.E32) {
+    g.E32[c] = (float)ex;
+    g.E32[nc + c] = (float)ey;
+    g.E32[2 * nc + c] = (float)ez;
+  }
+}
+
 // fields and conversions
+hipError_t launch_gas_field(const GasLink& g, int64_t ncells, hipStream_t s);
 hipError_t launch_electric_field(const double* u_gas, const double* B, double* E, int ncells,
                                  double c, hipStream_t s);
 hipError_t launch_to_fp32(const double* src, float* dst, int64_t n, hipStream_t s);

@@ -75,6 +75,7 @@ def lib():
             "rsol_drift": (ctypes.c_int, [vp]),
             "rsol_sort": (ctypes.c_int, [vp]),
             "rsol_step": (ctypes.c_int, [vp, i32, vp, vp]),
+            "rsol_step_coupled": (ctypes.c_int, [vp, i32, vp, vp, vp, vp]),
             "rsol_moments": (ctypes.c_int, [vp, vp, vp, vp]),
             "rsol_check": (ctypes.c_int, [vp]),
             "rsol_timing": (ctypes.c_int, [vp, i32]),
@@ -102,7 +103,7 @@ def exported_symbols():
         "rsol_courant_dt", "rsol_set_dt", "rsol_gather", "rsol_push", "rsol_deposit", "rsol_drift",
         "rsol_sort", "rsol_step", "rsol_moments", "rsol_check", "rsol_timing", "rsol_timing_read",
         "rsol_stray_count", "rsol_set_flags", "rsol_state_bytes", "rsol_record_states", "rsol_step_backward",
-        "rsol_moments_backward",
+        "rsol_moments_backward", "rsol_step_coupled",
     ]
 
 
@@ -228,6 +229,10 @@ class Handle:
 
     def rsol_step(self, nsteps: int, dM=None, dE=None):
         _check(self.h, lib().rsol_step(self.h, int(nsteps), _ptr(dM), _ptr(dE)))
+
+    def rsol_step_coupled(self, nsteps: int, rho, mom, egas, E):
+        self._keep.update(rho=rho, mom=mom, egas=egas, E=E)
+        _check(self.h, lib().rsol_step_coupled(self.h, int(nsteps), _ptr(rho), _ptr(mom), _ptr(egas), _ptr(E)))
 
     def rsol_moments(self, rho=None, P=None, e=None):
         _check(self.h, lib().rsol_moments(self.h, _ptr(rho), _ptr(P), _ptr(e)))

@@ -68,6 +68,12 @@ class Simulation:
     def step(self, nsteps, dM=None, dE=None):
         self.handle.rsol_step(nsteps, dM, dE)
 
+    def step_coupled(self, nsteps, rho, mom, egas=None):
+        """nsteps steps coupled to the gas (rho, mom = rho u, egas: float64 device tensors of
+        shapes (n_cells,), (3, n_cells), (n_cells,)); mom and egas are updated in place and
+        ``self.E`` holds the field of the final gas state."""
+        self.handle.rsol_step_coupled(nsteps, rho, mom, egas, self.E)
+
     def positions64(self):
         """Absolute FP64 positions (3, Np) on the device, in the current packet order."""
         if not self.fp32:

@@ -82,5 +82,6 @@ def test_small_or_misaligned_scratch_is_rejected():
 def test_null_handle_calls_fail_cleanly():
     rsol, L = _lib()
     assert L.rsol_step(None, 1, None, None) == -1
+    assert L.rsol_step_coupled(None, 1, None, None, None, None) == -1
     assert L.rsol_check(None) == -1
     assert L.rsol_destroy(None) == 0

@@ -7,7 +7,8 @@ u_perp = gamma*beta_perp = 1 gyrates with radius 0.25 dx in B0 on the grid.
 
 Each workload is generated from ``numpy.random.SeedSequence(seed).spawn(5)``,
 one stream each for [positions, directions, momentum magnitudes, field modes,
-loss target and gradient-check coordinates].  Positions are stratified: exactly
+loss target and gradient-check coordinates]; ``gas_state`` draws from a sixth
+child of the same seed sequence.  Positions are stratified: exactly
 ``ppc`` packets per cell, packet j = cell * ppc + k with
 cell = ix + nx * (iy + ny * iz), offsets uniform in the cell.
 
@@ -218,3 +219,16 @@ def make_workload(k: int, seed: int = 0, n: Optional[int] = None, ppc: Optional[
             coords += [(kind, int(a), int(b)) for a, b in zip(comp, where)]
         w.grad_coords = coords
     return w
+
+
+def gas_state(w: Workload, seed: int = 0):
+    """Seeded gas for runs coupled to the packets (density and B held fixed): density
+    rho = UNITS["rho"] * U(0.5, 1.5) per cell, momentum density rho * u_gas, and an energy
+    density U(1, 2) times the mean magnetic energy density B0^2/2.
+    Returns (rho (n_cells,), mom (3, n_cells), egas (n_cells,)) as float64."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(6)[5])
+    nc = w.n_cells
+    rho = UNITS["rho"] * rng.uniform(0.5, 1.5, nc)
+    mom = rho * w.u_gas.reshape(3, -1)
+    egas = 0.5 * UNITS["B0"] ** 2 * rng.uniform(1.0, 2.0, nc)
+    return rho, np.ascontiguousarray(mom), egas
