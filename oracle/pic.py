@@ -31,6 +31,7 @@ class Params:
     qomc: float         # q / (m_s c) of the CR species
     dt: float
     mass: float         # packet mass weight M_j = N_j <m_s>
+    naive: bool = False  # naive substitution of c by c_tilde (contrast mode, see naive_constants)
 
     @property
     def n_cells(self):
@@ -53,16 +54,18 @@ def electric_field(u_gas, B, c):
     return -np.cross(u_gas, B, axis=0) / c
 
 
-def courant_dt(u, B, c, c_tilde, qomc, dx, courant):
+def courant_dt(u, B, c, c_tilde, qomc, dx, courant, naive=False):
     """One global RSOL timestep (Sec. 4, timestep constraints; Sec. 2, closing
     discussion).  Gyro limit dt < C / Omega_eff with Omega_eff = (c_tilde/c) q|B|/(gamma m c)
     and cell-crossing limit dt < C dx / |v_eff| with v_eff = c_tilde beta.
-    Both carry the factor c/c_tilde relative to c_tilde = c."""
+    Both carry the factor c/c_tilde relative to c_tilde = c.  Under the naive
+    substitution the gyro frequency is not reduced (Sec. 5, items (3)-(4)):
+    Omega = q|B|/(gamma m c)."""
     gamma = lorentz_gamma(u)
     beta = np.sqrt(u[0] ** 2 + u[1] ** 2 + u[2] ** 2) / gamma
     bmag = np.sqrt(np.sum(np.asarray(B).reshape(3, -1) ** 2, axis=0))
     dt_cell = courant * dx / (c_tilde * np.max(beta))
-    omega_max = (c_tilde / c) * qomc * np.max(bmag) / np.min(gamma)
+    omega_max = (1.0 if naive else c_tilde / c) * qomc * np.max(bmag) / np.min(gamma)
     dt_gyro = courant / omega_max
     return float(min(dt_cell, dt_gyro))
 
@@ -131,15 +134,19 @@ def deposit(idx, w, vals, n_cells):
     return np.stack(out)
 
 
-def boris_kick(u, Ep, Bp, h):
+def boris_kick(u, Ep, Bp, h, h_b=None):
     """Advance u = gamma*beta by one step of Eq. (11),
     d(gamma beta)/dt = (c_tilde/c) (q/(m c)) [E + beta x B],
     with the relativistic Boris scheme (half electric kick, magnetic rotation
     about B with gamma taken after the half kick, half electric kick).
-    h = (c_tilde/c) (q/(m c)) dt / 2; returns u at the next half step."""
+    h = (c_tilde/c) (q/(m c)) dt / 2; returns u at the next half step.
+    With h_b given, the electric half kick is h E and the rotation uses h_b: the
+    same scheme for du/dt = (2h/dt) E + (2h_b/dt) beta x B (the naive equation)."""
+    if h_b is None:
+        h_b = h
     um = u + h * Ep
     gm = lorentz_gamma(um)
-    t = (h / gm) * Bp
+    t = (h_b / gm) * Bp
     tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2]
     s = 2.0 * t / (1.0 + tt)
     up = um + np.cross(um, t, axis=0)
@@ -147,15 +154,45 @@ def boris_kick(u, Ep, Bp, h):
     return uplus + h * Ep
 
 
+def naive_constants(p: Params):
+    """Constants of the naive substitution of c by c_tilde (the prior approach the
+    paper contrasts with, Sec. 1 and Sec. 5): the Lorentz factor is formed with
+    c_tilde, gamma = c_tilde / sqrt(c_tilde^2 - v^2), so u = gamma v / c_tilde; the
+    momentum equation is d_t(gamma v_eff) = (q/(m c)) (c E + v_eff x B) (Sec. 5, item
+    (3)), i.e. du/dt = (q/(m c)) [(c/c_tilde) E + beta x B]; the packet momentum and
+    energy are M c_tilde u and M c_tilde^2 gamma (Sec. 5, item (1); Sec. 1, the c_tilde^1
+    and c_tilde^2 of the CR momentum and energy densities), and the gas takes their
+    change with no c/c_tilde factor.
+    Returns (electric half kick, magnetic half kick, speed in P and energy, exchange factor)."""
+    h_e = 0.5 * (p.c / p.c_tilde) * p.qomc * p.dt
+    h_b = 0.5 * p.qomc * p.dt
+    return h_e, h_b, p.c_tilde, 1.0
+
+
+def rsol_constants(p: Params):
+    """The RSOL counterparts: both half kicks (c_tilde/c) (q/(m c)) dt / 2 (Eq. (11)),
+    P_j = M c u and energy M c^2 gamma with the true c (Eqs. (9)-(10)), and the c/c_tilde
+    of the back-reaction (Eq. (12))."""
+    h = 0.5 * (p.c_tilde / p.c) * p.qomc * p.dt
+    return h, h, p.c, p.c / p.c_tilde
+
+
+def mode_constants(p: Params):
+    return naive_constants(p) if p.naive else rsol_constants(p)
+
+
 def exchange(u_old, u_new, p: Params):
     """Momentum and energy each packet hands to the gas over one step.
     Momentum: Eq. (12), d(rho u)/dt = -sum_j (1/V_j)(c/c_tilde) d_t P_j with
     P_j = M_j c u_j (Sec. 2, Eq. (10) and the packet totals).  Energy: the
     same equal-and-opposite rule applied to the packet energy M_j c^2 gamma_j
-    (Eq. (9)).  Returns (dP (3, Np), dE (Np)) per packet, before weighting."""
-    f = -(p.c / p.c_tilde) * p.mass * p.c
+    (Eq. (9)).  Naive mode: P_j = M_j c_tilde u_j, energy M_j c_tilde^2 gamma_j and
+    no c/c_tilde factor (naive_constants).
+    Returns (dP (3, Np), dE (Np)) per packet, before weighting."""
+    _, _, cp, k = mode_constants(p)
+    f = -k * p.mass * cp
     dP = f * (u_new - u_old)
-    dE = f * p.c * (lorentz_gamma(u_new) - lorentz_gamma(u_old))
+    dE = f * cp * (lorentz_gamma(u_new) - lorentz_gamma(u_old))
     return dP, dE
 
 
@@ -177,11 +214,13 @@ def drift(x, u_new, p: Params):
 def moments(x, u, p: Params):
     """CR mass, momentum and energy densities on the grid from the packet totals
     M_j, P_j = M_j c u_j and E_j = M_j c^2 gamma_j (Sec. 2, after Eq. (10)),
-    spread by the kernel W and divided by the cell volume."""
+    spread by the kernel W and divided by the cell volume (naive mode: c_tilde in
+    place of c, naive_constants)."""
     idx, w = shape_weights(x, p)
     g = lorentz_gamma(u)
+    cp = mode_constants(p)[2]
     m = p.mass * np.ones(u.shape[1], dtype=u.dtype)
-    vals = np.concatenate([m[None], p.mass * p.c * u, (p.mass * p.c * p.c * g)[None]])
+    vals = np.concatenate([m[None], p.mass * cp * u, (p.mass * cp * cp * g)[None]])
     d = deposit(idx, w, vals, p.n_cells) / p.volume
     return d[0], d[1:4], d[4]
 
@@ -194,8 +233,8 @@ def step(x, u, E, B, p: Params):
     idx, w = shape_weights(x, p)
     Ep = gather(E, idx, w)
     Bp = gather(B, idx, w)
-    h = 0.5 * (p.c_tilde / p.c) * p.qomc * p.dt
-    u_new = boris_kick(u, Ep, Bp, h)
+    h_e, h_b, _, _ = mode_constants(p)
+    u_new = boris_kick(u, Ep, Bp, h_e, h_b)
     dP, dEn = exchange(u, u_new, p)
     dep = deposit(idx, w, np.concatenate([dP, dEn[None]]), p.n_cells) / p.volume
     x_new = drift(x, u_new, p)
@@ -242,8 +281,10 @@ def coupled_rollout(x, u, mom, egas, rho, B, p: Params, nsteps):
 def conserved_totals(u, mom, egas, p: Params):
     """Totals the CR-gas exchange conserves (Sec. 2, discussion after Eq. (12)): the
     momentum V sum_i (rho u)_i + (c/c_tilde) sum_j P_j with P_j = M_j c u_j, and the
-    energy V sum_i e_i + (c/c_tilde) sum_j M_j c^2 gamma_j.  Returns (momentum (3,), energy)."""
-    k = p.c / p.c_tilde
-    P = p.volume * mom.sum(axis=1) + k * p.mass * p.c * u.sum(axis=1)
-    En = p.volume * egas.sum() + k * p.mass * p.c * p.c * lorentz_gamma(u).sum()
+    energy V sum_i e_i + (c/c_tilde) sum_j M_j c^2 gamma_j.  Naive mode: the totals its
+    own exchange conserves, with M_j c_tilde u_j, M_j c_tilde^2 gamma_j and no c/c_tilde.
+    Returns (momentum (3,), energy)."""
+    _, _, cp, k = mode_constants(p)
+    P = p.volume * mom.sum(axis=1) + k * p.mass * cp * u.sum(axis=1)
+    En = p.volume * egas.sum() + k * p.mass * cp * cp * lorentz_gamma(u).sum()
     return P, En

@@ -506,6 +506,201 @@ def test_planted_mistakes_fail_the_coupled_pins(monkeypatch):
         assert _coupled_conservation_residual() > 100.0
 
 
+# ---------------------------------------------------------------- naive substitution (contrast, Secs. 1 and 5)
+
+def _naive(p):
+    return oracle.Params(p.nx, p.ny, p.nz, p.dx, p.shape, p.c, p.c_tilde, p.qomc, p.dt, p.mass, naive=True)
+
+
+def _naive_force_errors(ratio=10.0):
+    """Relative errors against the ratios the paper states for the naive momentum equation
+    (Sec. 5, item (3)): (a) from rest in a pure E field the naive kick is (c/c_tilde)^2 times
+    the RSOL one; (b) in pure B the naive rotation per step is 2 atan(Omega dt/2) with the
+    unreduced Omega = q B/(gamma m c), c/c_tilde times the RSOL Omega_eff."""
+    n, c, qomc = 8, 1000.0, 4000.0
+    nc = n ** 3
+    p = _uniform_params(n, "cic", ratio, dt=1e-5)
+    x0 = np.array([[4.2], [4.7], [3.1]])
+    E = np.tile(np.array([[0.3], [-0.2], [0.5]]), (1, nc))
+    Z = np.zeros((3, nc))
+    _, u_r, _, _ = oracle.step(x0, np.zeros((3, 1)), E, Z, p)
+    _, u_n, _, _ = oracle.step(x0, np.zeros((3, 1)), E, Z, _naive(p))
+    err_e = float(np.max(np.abs(u_n - (c / p.c_tilde) ** 2 * u_r)) / np.max(np.abs(u_n)))
+    Ez, B = _uniform_fields(n)
+    u0 = np.array([[3.0], [8.0], [-2.0]])
+    gamma = math.sqrt(1.0 + float(np.sum(u0 ** 2)))
+    _, us = _run_single(np.array([[4.0], [4.0], [4.0]]), u0, Ez, B, _naive(p), 20)
+    want = -2.0 * math.atan(0.5 * qomc * 1.0 / gamma * p.dt)
+    ang = np.arctan2(us[:-1, 1] * us[1:, 2] - us[:-1, 2] * us[1:, 1], us[:-1, 1] * us[1:, 1] + us[:-1, 2] * us[1:, 2])
+    err_b = float(np.max(np.abs(ang - want)) / abs(want))
+    return err_e, err_b
+
+
+def test_naive_force_ratios_match_the_paper():
+    err_e, err_b = _naive_force_errors()
+    assert err_e < 1e-13 and err_b < 1e-12
+
+
+def test_naive_equals_rsol_at_c_tilde_equal_c():
+    """With c_tilde = c the naive substitution changes nothing (Sec. 1): bitwise equal."""
+    w = make_workload(2, n=8, ppc=2, ratio=1.0)
+    p = oracle_params(w)
+    E, B = oracle_fields(w)
+    a = oracle.rollout(w.x, w.u, E, B, p, 10)
+    b = oracle.rollout(w.x, w.u, E, B, _naive(p), 10)
+    for k in ("x", "u", "dM", "dE"):
+        assert np.array_equal(a[k], b[k]), k
+    for ma, mb in zip(oracle.moments(a["x"], a["u"], p), oracle.moments(b["x"], b["u"], _naive(p))):
+        assert np.array_equal(ma, mb)
+
+
+def _naive_gyroradius_errors():
+    """Naive gyro radius on the grid: positions on a circle of radius
+    (c_tilde u_perp/(qomc B)) sqrt(1 + (Omega dt/2)^2), Omega = qomc B/gamma, so it shrinks
+    with c_tilde (Sec. 1: the gyro radius varies with c_tilde; Sec. 5, item (4))."""
+    n = 16
+    E, B = _uniform_fields(n)
+    c, qomc = 1000.0, 4000.0
+    u0 = np.array([[0.0], [10.0], [0.0]])
+    gamma = math.sqrt(101.0)
+    errs = []
+    for ratio in (1.0, 10.0, 100.0):
+        p = _naive(_uniform_params(n, "cic", ratio, dt=0.03 / (c / ratio)))
+        xs, _ = _run_single(np.array([[8.0], [8.0], [8.0]]), u0, E, B, p, 400)
+        # centred before the fit: radii down to 0.025 cells sit on coordinates near 8
+        R, r_each = _circle_radius(xs[:, 1] - 8.0, xs[:, 2] - 8.0)
+        a = 0.5 * qomc / gamma * p.dt
+        want = p.c_tilde * 10.0 / qomc * math.sqrt(1.0 + a * a)
+        errs.append(max(abs(R / want - 1.0), float(np.max(np.abs(r_each - R)) / R)))
+    return max(errs)
+
+
+def test_naive_gyroradius_scales_with_c_tilde():
+    assert _naive_gyroradius_errors() < 1e-11
+
+
+def _naive_exb_error(ratio):
+    """Naive E x B drift: the force-free state (c/c_tilde) E + beta x B = 0 has
+    v_eff = c_tilde beta = u_gas_perp for every c_tilde, where the RSOL drift is
+    (c_tilde/c) u_gas_perp (contrast with the RSOL drift pin).  The relativistic Boris
+    step keeps that state up to the change of gamma over the half kick a = h_E |E|, a
+    relative error of about a^2 / 2.  Returns (relative drift error, a^2)."""
+    n, U, c, qomc = 8, 1.0, 1000.0, 4000.0
+    E, B = _uniform_fields(n, B=(1.0, 0.0, 0.0), u_gas=(0.0, U, 0.0))
+    ct = c / ratio
+    # the naive gyro frequency is not reduced: dt within both Courant limits
+    p = _naive(_uniform_params(n, "cic", ratio, dt=min(0.3 / ct, 0.3 / qomc)))
+    beta = U / p.c_tilde
+    u0 = np.array([[0.0], [beta / math.sqrt(1 - beta ** 2)], [0.0]])
+    xs, _ = _run_single(np.array([[4.0], [4.0], [4.0]]), u0, E, B, p, 200)
+    xu = _unwrapped(xs, np.array([n, n, n], float))
+    v = (xu[-1] - xu[0]) / (200 * p.dt)
+    a = 0.5 * (c / ct) * qomc * p.dt * (U / c)
+    return max(abs(v[1] / U - 1.0), abs(v[0]) / U, abs(v[2]) / U), a * a
+
+
+@pytest.mark.parametrize("ratio", [1.0, 10.0, 100.0])
+def test_naive_exb_drift_is_the_gas_velocity(ratio):
+    err, a2 = _naive_exb_error(ratio)
+    assert err < a2 + 1e-12
+
+
+def _naive_moment_errors(ratio=30.0):
+    """Naive CR densities for the same packets: energy, momentum and number density scale
+    by (c_tilde/c)^2, (c_tilde/c)^1 and (c_tilde/c)^0 against the RSOL (true) values (Sec. 1)."""
+    w = make_workload(2, n=8, ppc=2, ratio=ratio)
+    p = oracle_params(w)
+    r = oracle.moments(w.x, w.u, p)
+    q = oracle.moments(w.x, w.u, _naive(p))
+    s = p.c_tilde / p.c
+    return (float(np.max(np.abs(q[0] - r[0])) / np.max(r[0])),
+            float(np.max(np.abs(q[1] - s * r[1])) / np.max(np.abs(s * r[1]))),
+            float(np.max(np.abs(q[2] - s * s * r[2])) / np.max(s * s * r[2])))
+
+
+def test_naive_moment_scalings_match_the_paper():
+    assert max(_naive_moment_errors()) < 1e-14
+
+
+def _naive_exchange_residuals(ratio=30.0):
+    """Naive back-reaction: the gas takes minus the change of the naive CR momentum and
+    energy, so V sum dM equals minus the change of V sum of the naive moment P (and the
+    same for energy), while the RSOL conserved total (with c/c_tilde and the true c) is
+    not kept unless c_tilde = c.  Returns (naive momentum, naive energy, RSOL momentum)
+    residuals relative to the momentum exchanged."""
+    w = make_workload(2, n=8, ppc=2, ratio=ratio)
+    p = _naive(oracle_params(w))
+    E, B = oracle_fields(w)
+    x1, u1, dM, dE = oracle.step(w.x, w.u, E, B, p)
+    _, P0, e0 = oracle.moments(w.x, w.u, p)
+    _, P1, e1 = oracle.moments(x1, u1, p)
+    V = p.volume
+    scale_p = np.abs(dM).sum() * V
+    scale_e = np.abs(e1).sum() * V
+    res_p = float(np.max(np.abs(V * dM.sum(axis=1) + V * (P1.sum(axis=1) - P0.sum(axis=1))))) / scale_p
+    res_e = abs(V * dE.sum() + V * (e1.sum() - e0.sum())) / scale_e
+    k = p.c / p.c_tilde
+    rsol_total = V * dM.sum(axis=1) + k * p.mass * p.c * (u1 - w.u).sum(axis=1)
+    res_r = float(np.max(np.abs(rsol_total))) / scale_p
+    return res_p, res_e, res_r
+
+
+def test_naive_exchange_conserves_its_own_totals_only():
+    res_p, res_e, res_r = _naive_exchange_residuals()
+    assert res_p < 1e-12 and res_e < 1e-13
+    assert res_r > 0.1
+
+
+def test_naive_breaks_step_space_invariance_and_the_timestep_gain():
+    """Contrast with the RSOL invariance pin: naive rollouts at c/c_tilde = 1 and 10 with
+    dt ~ 1/c_tilde differ at O(1); and where the gyro limit binds, the naive timestep at
+    c_tilde < c is the c_tilde = c one (Sec. 5, item (4): no timestep gain from gyro orbits)."""
+    runs = []
+    for ratio in (1.0, 10.0):
+        w = make_workload(2, n=8, ppc=2, ratio=ratio)
+        p = _naive(oracle_params(w))
+        E, B = oracle_fields(w)
+        runs.append(oracle.rollout(w.x, w.u, E, B, p, 30))
+    du = np.linalg.norm(runs[0]["u"] - runs[1]["u"], axis=0) / np.linalg.norm(runs[0]["u"], axis=0)
+    assert np.median(du) > 0.1
+    w1 = make_workload(2, n=8, ppc=2, ratio=1.0)
+    w30 = make_workload(2, n=8, ppc=2, ratio=30.0)
+    dt_true = oracle.courant_dt(w1.u, w1.B, w1.c, w1.c_tilde, w1.qomc, w1.dx, w1.courant)
+    dt_naive = oracle.courant_dt(w30.u, w30.B, w30.c, w30.c_tilde, w30.qomc, w30.dx, w30.courant, naive=True)
+    dt_rsol = oracle.courant_dt(w30.u, w30.B, w30.c, w30.c_tilde, w30.qomc, w30.dx, w30.courant)
+    assert dt_naive == pytest.approx(dt_true, rel=1e-15)
+    assert dt_rsol == pytest.approx(30.0 * dt_true, rel=1e-12)
+
+
+def test_planted_mistakes_fail_the_naive_pins(monkeypatch):
+    """Plausible mistakes in the naive constants each fail one of the naive pins."""
+    pic = oracle.pic
+    good = pic.naive_constants
+
+    def variant(i):
+        def f(p):
+            h_e, h_b, cp, k = good(p)
+            r = p.c_tilde / p.c
+            return [(h_e * r * r, h_b, cp, k),      # E kick without (c/c_tilde)^2 over RSOL
+                    (h_e, h_b * r, cp, k),          # rotation reduced as in RSOL
+                    (h_e, h_b, cp / r, k),          # momentum/energy with the true c
+                    (h_e, h_b, cp, k / r)][i]       # c/c_tilde kept on the back-reaction
+        return f
+
+    with monkeypatch.context() as m:
+        m.setattr(pic, "naive_constants", variant(0))
+        assert max(_naive_force_errors()) > 1e-3 and _naive_exb_error(10.0)[0] > 1e-3
+    with monkeypatch.context() as m:
+        m.setattr(pic, "naive_constants", variant(1))
+        assert _naive_force_errors()[1] > 1e-3 and _naive_gyroradius_errors() > 1e-3
+    with monkeypatch.context() as m:
+        m.setattr(pic, "naive_constants", variant(2))
+        assert max(_naive_moment_errors()) > 1e-3
+    with monkeypatch.context() as m:
+        m.setattr(pic, "naive_constants", variant(3))
+        assert max(_naive_exchange_residuals()[:2]) > 1e-3
+
+
 # ---------------------------------------------------------------- reference gradients
 
 def test_complex_step_gradient_matches_central_difference_and_full_rerun():
