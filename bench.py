@@ -15,6 +15,8 @@ workload; "fp32" = the precision form on the same workload; "roofline" = the
 step kernel's algorithmic HBM bytes per launch over its event-timed average
 duration against the 8 TB/s HBM3E peak; "coupled" = the FP64 step coupled to the
 workload's gas (exchange into the gas momentum and energy, E rebuilt every step);
+"naive" = the FP64 step in the naive-substitution contrast mode (same kernels,
+naive constants);
 "backward" = the differentiation form;
 "cpu_baseline" = the CPU oracle timed on a bounded sample of the same workload.
 """
@@ -73,15 +75,15 @@ def measured_traffic(precision, workload):
     return rec.get("bytes_per_launch")
 
 
-def time_path(w, precision, steps, warmup, sort_every, coupled=False):
+def time_path(w, precision, steps, warmup, sort_every, coupled=False, flags=0):
     """Time `steps` steps in one call.  coupled=True runs them coupled to the workload's
     seeded gas (rsol_step_coupled: the exchange goes into the gas momentum and energy and
-    E is rebuilt from the gas velocity after every step)."""
+    E is rebuilt from the gas velocity after every step); flags are RSOL_FLAG_* bits."""
     import torch
     from paper_2111_14704_amd.sim import Simulation
     from workloads import gas_state
 
-    sim = Simulation.from_workload(w, precision=precision, sort_every=sort_every)
+    sim = Simulation.from_workload(w, precision=precision, sort_every=sort_every, flags=flags)
     h = sim.handle
     if coupled:
         rho, mom, egas = (torch.as_tensor(a, dtype=torch.float64, device=sim.device) for a in gas_state(w))
@@ -198,6 +200,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-coupled", action="store_true", help="skip the run coupled to the gas")
+    ap.add_argument("--no-naive", action="store_true", help="skip the naive-substitution contrast run")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="first run one plain device copy of BYTES bytes (a known-size reference for HBM counters)")
     args = ap.parse_args()
@@ -239,6 +242,12 @@ def main():
         rc = time_path(w, "fp64", args.steps, args.warmup, args.sort_every, coupled=True)
         print(f"[bench] coupled fp64 {rc['value']:.3e} upd/s, kernel {rc['kernel_ms']:.3f} ms", file=sys.stderr,
               flush=True)
+    rn = None
+    if not args.no_naive:
+        from paper_2111_14704_amd.rsol import RSOL_FLAG_NAIVE
+        rn = time_path(w, "fp64", args.steps, args.warmup, args.sort_every, flags=RSOL_FLAG_NAIVE)
+        print(f"[bench] naive fp64 {rn['value']:.3e} upd/s, kernel {rn['kernel_ms']:.3f} ms", file=sys.stderr,
+              flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w)
@@ -264,6 +273,8 @@ def main():
     if rc:
         line["coupled"] = dict(value=rc["value"], ms_per_step=rc["ms_per_step"], kernel_ms=rc["kernel_ms"],
                                dtype="f64", overhead_vs_static=rc["ms_per_step"] / r64["ms_per_step"] - 1.0)
+    if rn:
+        line["naive"] = dict(value=rn["value"], ms_per_step=rn["ms_per_step"], kernel_ms=rn["kernel_ms"], dtype="f64")
     print(json.dumps(line), flush=True)
 
 

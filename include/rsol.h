@@ -78,6 +78,15 @@ typedef struct rsol_params {
 #define RSOL_FLAG_TILED 2       /* rsol_step runs the tiled LDS kernel over packets re-sorted
                                    every sort_every steps instead of the default cell-list
                                    kernel (ignored under RSOL_FLAG_KEEP_ORDER)                */
+#define RSOL_FLAG_NAIVE 4       /* contrast mode: the naive substitution of c by c_tilde that
+                                   the RSOL formulation replaces (Sec. 1; Sec. 5, items (1)-(4)).
+                                   u = gamma v / c_tilde with du/dt = (q/(m c)) [(c/c_tilde) E +
+                                   beta x B] (the momentum equation of Sec. 5, item (3)); packet
+                                   momentum M c_tilde u and energy M c_tilde^2 gamma in the
+                                   exchange and the moments, no c/c_tilde on the back-reaction;
+                                   rsol_courant_dt's gyro limit uses the unreduced q|B|/(gamma m c).
+                                   Drift, E and every kernel are the RSOL ones; the
+                                   differentiation-form entry points return RSOL_EINVAL.      */
 
 typedef struct rsol_ctx* rsol_handle;
 

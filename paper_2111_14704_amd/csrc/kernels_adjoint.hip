@@ -198,7 +198,7 @@ struct TileAccess {
 template <int M, typename T, typename A>
 __device__ __forceinline__ void packet_backward(const A& acc, const int home[3], const T f[3], const T u0a[3],
                                                 T lxa[3], T lua[3], const RunConsts& k) {
-  const T h = (T)k.h;
+  const T h = (T)k.h;  // RSOL equations only: the electric and magnetic half kicks are equal
   const Stencil3<M, T> st = stencil_at<M, T>(home, f);
   const int base[3] = {st.a[0].base, st.a[1].base, st.a[2].base};
 
@@ -485,7 +485,7 @@ __global__ void __launch_bounds__(kBlock) moments_backward_kernel(Packets<T> P, 
                                                                   RunConsts k) {
   const int64_t nc = k.ncells, np = P.np;
   const double inv_v = 1.0 / (k.dx * k.dx * k.dx);
-  const double m = k.mass * inv_v, mc = k.mass * k.c * inv_v, mcc = k.mass * k.c * k.c * inv_v;
+  const double m = k.mass * inv_v, mc = k.mass * k.pc * inv_v, mcc = k.mass * k.pc * k.pc * inv_v;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
     int home[3];
     T f[3];

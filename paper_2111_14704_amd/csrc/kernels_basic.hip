@@ -194,12 +194,12 @@ __global__ void gather_kernel(Packets<T> P, const T* __restrict__ E, const T* __
 template <typename T>
 __global__ void push_kernel(Packets<T> P, const T* __restrict__ Ep, const T* __restrict__ Bp,
                             T* __restrict__ payload, RunConsts k) {
-  const T h = (T)k.h;
+  const T h = (T)k.h, hb = (T)k.hb;
   const int64_t np = P.np;
   for (int64_t i = gtid(); i < np; i += gstride()) {
     const T ux = P.u[i], uy = P.u[np + i], uz = P.u[2 * np + i];
     const Kick<T> q = boris_kick<T>(ux, uy, uz, Ep[i], Ep[np + i], Ep[2 * np + i],
-                                    Bp[i], Bp[np + i], Bp[2 * np + i], h);
+                                    Bp[i], Bp[np + i], Bp[2 * np + i], h, hb);
     P.u[i] = ux + q.dux;
     P.u[np + i] = uy + q.duy;
     P.u[2 * np + i] = uz + q.duz;
@@ -302,7 +302,7 @@ __global__ void moments_kernel(Packets<T> P, double* __restrict__ rho, double* _
                                double* __restrict__ e, RunConsts k) {
   const int64_t nc = k.ncells, np = P.np;
   const double inv_v = 1.0 / (k.dx * k.dx * k.dx);
-  const double m = k.mass * inv_v, mc = k.mass * k.c * inv_v, mcc = k.mass * k.c * k.c * inv_v;
+  const double m = k.mass * inv_v, mc = k.mass * k.pc * inv_v, mcc = k.mass * k.pc * k.pc * inv_v;
   for (int64_t i = gtid(); i < np; i += gstride()) {
     const Stencil<M, T> s = stencil_of<M, T>(P, i, k);
     const double ux = (double)P.u[i], uy = (double)P.u[np + i], uz = (double)P.u[2 * np + i];
@@ -338,7 +338,7 @@ __global__ void __launch_bounds__(kBlock) step_global_kernel(Packets<T> P, const
                                                              const T* __restrict__ B, double* __restrict__ dM,
                                                              double* __restrict__ dE, RunConsts k) {
   const int64_t nc = k.ncells, np = P.np;
-  const T h = (T)k.h;
+  const T h = (T)k.h, hb = (T)k.hb;
   for (int64_t i = gtid(); i < np; i += gstride()) {
     const Stencil<M, T> s = stencil_of<M, T>(P, i, k);
     T e[3] = {0, 0, 0}, b[3] = {0, 0, 0};
@@ -363,7 +363,7 @@ __global__ void __launch_bounds__(kBlock) step_global_kernel(Packets<T> P, const
       }
     }
     const T ux = P.u[i], uy = P.u[np + i], uz = P.u[2 * np + i];
-    const Kick<T> q = boris_kick<T>(ux, uy, uz, e[0], e[1], e[2], b[0], b[1], b[2], h);
+    const Kick<T> q = boris_kick<T>(ux, uy, uz, e[0], e[1], e[2], b[0], b[1], b[2], h, hb);
     const T nux = ux + q.dux, nuy = uy + q.duy, nuz = uz + q.duz;
     P.u[i] = nux;
     P.u[np + i] = nuy;

@@ -442,7 +442,7 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
   }
   __syncthreads();
 
-  const T h = (T)k.h;
+  const T h = (T)k.h, hb = (T)k.hb;
   const T pf = (T)k.pfac, ef = (T)k.efac;
 
   // ------------------------------------------------------------ quads: one cell each
@@ -550,7 +550,7 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
       }
 
       // kick (Eq. (11))
-      const Kick<T> kq = boris_kick<T>(u[0], u[1], u[2], eb[0], eb[1], eb[2], eb[3], eb[4], eb[5], h);
+      const Kick<T> kq = boris_kick<T>(u[0], u[1], u[2], eb[0], eb[1], eb[2], eb[3], eb[4], eb[5], h, hb);
       const T un[3] = {u[0] + kq.dux, u[1] + kq.duy, u[2] + kq.duz};
 
       // exchange (Eq. (12)) into the quad's registers, lane q taking component q
@@ -628,7 +628,7 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
         const int a = node % 3, b = (node / 3) % 3, c = node / 9;
         return Fs[d][(bx + a) + kRegionEdge * ((by + b) + kRegionEdge * (bz + c))];
       }, eb);
-      const Kick<T> kq = boris_kick<T>(u[0], u[1], u[2], eb[0], eb[1], eb[2], eb[3], eb[4], eb[5], h);
+      const Kick<T> kq = boris_kick<T>(u[0], u[1], u[2], eb[0], eb[1], eb[2], eb[3], eb[4], eb[5], h, hb);
       const T un[3] = {u[0] + kq.dux, u[1] + kq.duy, u[2] + kq.duz};
       if constexpr (deposit) {
         const T qv[4] = {pf * kq.dux, pf * kq.duy, pf * kq.duz, ef * kq.dg};
@@ -729,7 +729,7 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
       T eb[6];
       gather27<T>(w, [&](int node, int d) { return d < 3 ? E[d * nc + nodes[node]] : B[(d - 3) * nc + nodes[node]]; },
                   eb);
-      const Kick<T> kq = boris_kick<T>(u[0], u[1], u[2], eb[0], eb[1], eb[2], eb[3], eb[4], eb[5], h);
+      const Kick<T> kq = boris_kick<T>(u[0], u[1], u[2], eb[0], eb[1], eb[2], eb[3], eb[4], eb[5], h, hb);
       const T un[3] = {u[0] + kq.dux, u[1] + kq.duy, u[2] + kq.duz};
       if constexpr (deposit) {
         const T qv[4] = {pf * kq.dux, pf * kq.duy, pf * kq.duz, ef * kq.dg};

@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(256) step_tiled_kernel(Packets<T> src, Packets
   const int64_t seg0 = offsets[tile * t.cells_per_tile];
   const int64_t seg1 = offsets[(tile + 1) * t.cells_per_tile];
   const int64_t np = src.np;
-  const T h = (T)k.h;
+  const T h = (T)k.h, hb = (T)k.hb;
   const T pf = (T)k.pfac, ef = (T)k.efac;
 
   for (int64_t i = seg0 + threadIdx.x; i < seg1; i += blockDim.x) {
@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(256) step_tiled_kernel(Packets<T> src, Packets
     }
 
     // ---- kick (Eq. (11))
-    const Kick<T> q = boris_kick<T>(ux, uy, uz, e0, e1, e2, b0, b1, b2, h);
+    const Kick<T> q = boris_kick<T>(ux, uy, uz, e0, e1, e2, b0, b1, b2, h, hb);
     const T nux = ux + q.dux, nuy = uy + q.duy, nuz = uz + q.duz;
 
     // ---- exchange deposit at x^n (Eq. (12))

@@ -106,6 +106,8 @@ void timed_end(rsol_ctx* h, std::pair<hipEvent_t, hipEvent_t> pr, bool is_sort) 
 }
 
 bool fp32(const rsol_params& p) { return p.precision == RSOL_FP32; }
+bool naive(const rsol_params& p) { return (p.flags & RSOL_FLAG_NAIVE) != 0; }
+constexpr int32_t kKnownFlags = RSOL_FLAG_KEEP_ORDER | RSOL_FLAG_TILED | RSOL_FLAG_NAIVE;
 
 Tiling tiling_for(const rsol_params& p) {
   const StepPlan pl = plan_step(p.nx, p.ny, p.nz, p.shape, p.precision, p.sort_every, p.courant);
@@ -156,7 +158,7 @@ std::string validate(const rsol_params* p, int64_t np) {
   if (p->precision != RSOL_FP64 && p->precision != RSOL_FP32) return "precision must be RSOL_FP64 or RSOL_FP32";
   if (p->sort_every < 1 || p->sort_every > 8) return "sort_every must be in 1..8";
   if (p->reserved != 0) return "reserved must be 0";
-  if (p->flags & ~(RSOL_FLAG_KEEP_ORDER | RSOL_FLAG_TILED)) return "unknown flag bits";
+  if (p->flags & ~kKnownFlags) return "unknown flag bits";
   if (!(p->dx > 0)) return "dx must be > 0";
   if (!(p->c > 0) || !(p->c_tilde > 0) || p->c_tilde > p->c) return "need 0 < c_tilde <= c";
   if (!isfinite(p->qomc)) return "qomc must be finite";
@@ -189,12 +191,24 @@ RunConsts consts(const rsol_ctx* h) {
   k.qomc = p.qomc;
   k.dt = p.dt;
   k.mass = p.mass;
-  k.h = 0.5 * (p.c_tilde / p.c) * p.qomc * p.dt;
   k.cdt = p.c_tilde * p.dt;
   k.cdt_dx = p.c_tilde * p.dt / p.dx;
   const double vol = p.dx * p.dx * p.dx;
-  k.pfac = -(p.c / p.c_tilde) * p.mass * p.c / vol;
-  k.efac = -(p.c / p.c_tilde) * p.mass * p.c * p.c / vol;
+  if (naive(p)) {
+    // du/dt = (q/(m c)) [(c/c_tilde) E + beta x B], packet momentum M c_tilde u and
+    // energy M c_tilde^2 gamma, no c/c_tilde on the back-reaction
+    k.h = 0.5 * (p.c / p.c_tilde) * p.qomc * p.dt;
+    k.hb = 0.5 * p.qomc * p.dt;
+    k.pc = p.c_tilde;
+    k.pfac = -p.mass * p.c_tilde / vol;
+    k.efac = -p.mass * p.c_tilde * p.c_tilde / vol;
+  } else {
+    k.h = 0.5 * (p.c_tilde / p.c) * p.qomc * p.dt;
+    k.hb = k.h;
+    k.pc = p.c;
+    k.pfac = -(p.c / p.c_tilde) * p.mass * p.c / vol;
+    k.efac = -(p.c / p.c_tilde) * p.mass * p.c * p.c / vol;
+  }
   // a packet may never cross more than one cell per step; the tiled kernel's halo
   // additionally relies on the Courant bound (at most C cells per step)
   k.max_step = h->plan.max_step;
@@ -511,7 +525,7 @@ int rsol_courant_dt(rsol_handle h, double* dt) {
   const rsol_params& p = h->p;
   double lim = INFINITY;
   if (beta_max > 0) lim = fmin(lim, p.courant * p.dx / (p.c_tilde * beta_max));
-  const double omega = (p.c_tilde / p.c) * fabs(p.qomc) * b_max / gamma_min;
+  const double omega = (naive(p) ? 1.0 : p.c_tilde / p.c) * fabs(p.qomc) * b_max / gamma_min;
   if (omega > 0) lim = fmin(lim, p.courant / omega);
   if (!isfinite(lim)) return fail(h, RSOL_EINVAL, "timestep unbounded (no motion and no field)");
   *dt = lim;
@@ -632,7 +646,7 @@ int rsol_moments(rsol_handle h, double* rho, double* P, double* e) {
 
 int rsol_set_flags(rsol_handle h, int32_t flags) {
   if (int rc = need(h, false, false)) return rc;
-  if (flags & ~(RSOL_FLAG_KEEP_ORDER | RSOL_FLAG_TILED)) return fail(h, RSOL_EINVAL, "unknown flag bits");
+  if (flags & ~kKnownFlags) return fail(h, RSOL_EINVAL, "unknown flag bits");
   h->p.flags = flags;
   return RSOL_OK;
 }
@@ -644,6 +658,7 @@ size_t rsol_state_bytes(rsol_handle h) {
 
 int rsol_record_states(rsol_handle h, int32_t nsteps, void* states) {
   if (int rc = need(h, true, true)) return rc;
+  if (naive(h->p)) return fail(h, RSOL_EINVAL, "the differentiation form covers the RSOL equations only");
   if (nsteps < 0) return fail(h, RSOL_EINVAL, "nsteps < 0");
   if (!(h->p.dt > 0)) return fail(h, RSOL_ESTATE, "dt not set");
   if (h->np == 0 || nsteps == 0) return RSOL_OK;
@@ -669,6 +684,7 @@ int rsol_record_states(rsol_handle h, int32_t nsteps, void* states) {
 int rsol_step_backward(rsol_handle h, int32_t nsteps, const void* states, void* lam_x, void* lam_u,
                        const double* lam_dM, const double* lam_dE, double* gE, double* gB) {
   if (int rc = need(h, true, true)) return rc;
+  if (naive(h->p)) return fail(h, RSOL_EINVAL, "the differentiation form covers the RSOL equations only");
   if (nsteps < 0) return fail(h, RSOL_EINVAL, "nsteps < 0");
   if (!(h->p.dt > 0)) return fail(h, RSOL_ESTATE, "dt not set");
   if (!lam_dM && lam_dE) return fail(h, RSOL_EINVAL, "lam_dE without lam_dM");
@@ -727,6 +743,7 @@ int rsol_step_backward(rsol_handle h, int32_t nsteps, const void* states, void* 
 int rsol_moments_backward(rsol_handle h, const double* lam_rho, const double* lam_P, const double* lam_e,
                           void* lam_x, void* lam_u) {
   if (int rc = need(h, false, true)) return rc;
+  if (naive(h->p)) return fail(h, RSOL_EINVAL, "the differentiation form covers the RSOL equations only");
   if (h->np == 0) return RSOL_OK;
   if (!lam_x || !lam_u) return fail(h, RSOL_EINVAL, "NULL adjoint array");
   if (fp32(h->p))

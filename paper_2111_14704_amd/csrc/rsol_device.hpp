@@ -28,11 +28,15 @@ struct RunConsts {
   double dx, inv_dx;
   double Lx, Ly, Lz;
   double c, c_tilde, qomc, dt, mass;
-  double h;          // (c_tilde/c) (q/(m c)) dt / 2, the half kick of Eq. (11)
+  // RSOL (Eq. (11), (12)); the naive-substitution contrast mode (the momentum
+  // equation of Sec. 5, item (3), with u = gamma v / c_tilde) in brackets
+  double h;          // electric half kick: (c_tilde/c) (q/(m c)) dt / 2  [(c/c_tilde) (q/(m c)) dt / 2]
+  double hb;         // magnetic half kick (rotation): h                  [(q/(m c)) dt / 2]
+  double pc;         // speed in packet momentum M pc u, energy M pc^2 gamma: c  [c_tilde]
   double cdt;        // c_tilde dt, the drift length per unit beta
   double cdt_dx;     // c_tilde dt / dx
-  double pfac;       // -(c/c_tilde) M c / V: gas momentum per unit packet du (Eq. (12))
-  double efac;       // -(c/c_tilde) M c^2 / V: gas energy per unit packet dgamma
+  double pfac;       // gas momentum per unit packet du: -(c/c_tilde) M c / V  [-M c_tilde / V]
+  double efac;       // gas energy per unit packet dgamma: -(c/c_tilde) M c^2 / V  [-M c_tilde^2 / V]
   double max_step;   // largest allowed |dx| per step, in cells
   uint32_t* status;  // device status word
 };
@@ -106,9 +110,10 @@ __device__ __forceinline__ void axis_weight_derivs(int home, T f, T dw[M]) {
   }
 }
 
-// Relativistic Boris kick of u = gamma*beta with half kick h (Eq. (11)), written in
-// increment form: du = 2 h E + u' x s equals u_new - u exactly in real arithmetic but
-// carries no cancellation, and dgamma = du . (u_new + u) / (gamma_new + gamma).
+// Relativistic Boris kick of u = gamma*beta with electric half kick h and magnetic
+// half kick hb (both (c_tilde/c) q dt/(2 m c) for Eq. (11)), written in increment
+// form: du = 2 h E + u' x s equals u_new - u exactly in real arithmetic but carries
+// no cancellation, and dgamma = du . (u_new + u) / (gamma_new + gamma).
 template <typename T>
 struct Kick {
   T dux, duy, duz, dg;
@@ -150,10 +155,10 @@ __device__ __forceinline__ T rcp_nr(T x) {
 
 template <typename T>
 __device__ __forceinline__ Kick<T> boris_kick(T ux, T uy, T uz, T ex, T ey, T ez,
-                                              T bx, T by, T bz, T h) {
+                                              T bx, T by, T bz, T h, T hb) {
   const T hex = h * ex, hey = h * ey, hez = h * ez;
   const T mx = ux + hex, my = uy + hey, mz = uz + hez;
-  const T k = h * rsqrt_nr<T>(T(1) + (mx * mx + my * my + mz * mz));  // h / gamma-
+  const T k = hb * rsqrt_nr<T>(T(1) + (mx * mx + my * my + mz * mz));  // hb / gamma-
   const T tx = k * bx, ty = k * by, tz = k * bz;
   const T tt = tx * tx + ty * ty + tz * tz;
   const T sf = T(2) * rcp_nr<T>(T(1) + tt);

@@ -26,6 +26,7 @@ RSOL_CIC, RSOL_TSC = 1, 2
 RSOL_FP64, RSOL_FP32 = 0, 1
 RSOL_FLAG_KEEP_ORDER = 1
 RSOL_FLAG_TILED = 2
+RSOL_FLAG_NAIVE = 4
 
 
 class RSOLError(RuntimeError):
