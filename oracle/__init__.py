@@ -19,5 +19,6 @@ with a held-fixed density and magnetic field.
 from .pic import (  # noqa: F401
     Params, electric_field, courant_dt, shape_weights, gather, deposit, boris_kick,
     exchange, drift, wrap, moments, step, rollout, lorentz_gamma, coupled_step, coupled_rollout,
-    conserved_totals, naive_constants, rsol_constants, mode_constants,
+    conserved_totals, naive_constants, rsol_constants, mode_constants, loss_factor, exchange_weighted,
+    step_with_losses, rollout_with_losses,
 )

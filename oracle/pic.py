@@ -54,7 +54,7 @@ def electric_field(u_gas, B, c):
     return -np.cross(u_gas, B, axis=0) / c
 
 
-def courant_dt(u, B, c, c_tilde, qomc, dx, courant, naive=False):
+def courant_dt(u, B, c, c_tilde, qomc, dx, courant, naive=False, sigma=0.0, nn=None):
     """One global RSOL timestep (Sec. 4, timestep constraints; Sec. 2, closing
     discussion).  Gyro limit dt < C / Omega_eff with Omega_eff = (c_tilde/c) q|B|/(gamma m c)
     and cell-crossing limit dt < C dx / |v_eff| with v_eff = c_tilde beta.
@@ -67,7 +67,12 @@ def courant_dt(u, B, c, c_tilde, qomc, dx, courant, naive=False):
     dt_cell = courant * dx / (c_tilde * np.max(beta))
     omega_max = (1.0 if naive else c_tilde / c) * qomc * np.max(bmag) / np.min(gamma)
     dt_gyro = courant / omega_max
-    return float(min(dt_cell, dt_gyro))
+    dt = min(dt_cell, dt_gyro)
+    if sigma > 0 and nn is not None and np.max(nn) > 0 and np.max(beta) > 0:
+        # catastrophic losses (Sec. 4): dt < C N_j/|dN_j/dt| with the (c_tilde/c)-reduced
+        # rate (c_tilde/c) sigma c beta n_n, at the largest beta and n_n
+        dt = min(dt, courant / ((c_tilde / c) * sigma * c * np.max(beta) * np.max(nn)))
+    return float(dt)
 
 
 def _axis_weights(s, n, shape):
@@ -196,6 +201,60 @@ def exchange(u_old, u_new, p: Params):
     return dP, dE
 
 
+def loss_factor(u_new, nn_p, sigma, p: Params):
+    """Fraction of a packet kept over one step under catastrophic losses (Sec. 2, the
+    collisional terms): every packet total psi = (N, M, E, P) decays as
+    d_t psi = -(c_tilde/c) <sigma v> n_n psi, with the reduced rate.  Here
+    <sigma v> = sigma c beta for a constant cross-section sigma, beta from the step's
+    momentum u^{n+1/2}, and n_n the nucleon density at the packet at x^n; the decay over
+    the step is integrated exactly with that frozen rate.  The exponent is then
+    sigma n_n times the step's drift length c_tilde beta dt: the loss per distance
+    travelled does not depend on c_tilde (Sec. 2, closing discussion)."""
+    beta = np.sqrt(u_new[0] ** 2 + u_new[1] ** 2 + u_new[2] ** 2) / lorentz_gamma(u_new)
+    return np.exp(-(p.c_tilde / p.c) * sigma * p.c * beta * nn_p * p.dt)
+
+
+def exchange_weighted(u_old, w_old, u_new, w_new, p: Params):
+    """exchange() for packets whose weight changes over the step: the gas takes the change
+    of the packet totals P_j = w_j M c u_j and w_j M c^2 gamma_j (Eq. (12) and its energy
+    reading), so what the losses remove is handed to the gas as well."""
+    _, _, cp, k = mode_constants(p)
+    f = -k * p.mass * cp
+    dP = f * (w_new * u_new - w_old * u_old)
+    dE = f * cp * (w_new * lorentz_gamma(u_new) - w_old * lorentz_gamma(u_old))
+    return dP, dE
+
+
+def step_with_losses(x, u, w, E, B, nn, sigma, p: Params):
+    """One packet step with catastrophic losses: gather E, B and the nucleon density nn
+    (n_cells,) at x^n, kick, reduce the weight w (Np,) by loss_factor, deposit the change
+    of the weighted packet totals at x^n, drift.
+    Returns (x^{n+1}, u^{n+1/2}, w^{n+1}, dM, dE)."""
+    idx, wts = shape_weights(x, p)
+    Ep = gather(E, idx, wts)
+    Bp = gather(B, idx, wts)
+    nn_p = gather(np.asarray(nn)[None], idx, wts)[0]
+    h_e, h_b, _, _ = mode_constants(p)
+    u_new = boris_kick(u, Ep, Bp, h_e, h_b)
+    w_new = w * loss_factor(u_new, nn_p, sigma, p)
+    dP, dEn = exchange_weighted(u, w, u_new, w_new, p)
+    dep = deposit(idx, wts, np.concatenate([dP, dEn[None]]), p.n_cells) / p.volume
+    x_new = drift(x, u_new, p)
+    return x_new, u_new, w_new, dep[0:3], dep[3]
+
+
+def rollout_with_losses(x, u, w, E, B, nn, sigma, p: Params, nsteps):
+    """nsteps steps with losses; returns the final state and weights and the exchange
+    summed over the steps."""
+    dM_sum = np.zeros((3, p.n_cells))
+    dE_sum = np.zeros(p.n_cells)
+    for _ in range(nsteps):
+        x, u, w, dM, dE = step_with_losses(x, u, w, E, B, nn, sigma, p)
+        dM_sum = dM_sum + dM
+        dE_sum = dE_sum + dE
+    return dict(x=x, u=u, w=w, dM_sum=dM_sum, dE_sum=dE_sum)
+
+
 def wrap(x, length):
     """Periodic wrap into [0, length); a result equal to length maps to 0."""
     y = x - length * np.floor(np.real(x) / length)
@@ -211,17 +270,20 @@ def drift(x, u_new, p: Params):
     return np.stack([wrap(out[d], box[d]) for d in range(3)])
 
 
-def moments(x, u, p: Params):
+def moments(x, u, p: Params, w=None):
     """CR mass, momentum and energy densities on the grid from the packet totals
     M_j, P_j = M_j c u_j and E_j = M_j c^2 gamma_j (Sec. 2, after Eq. (10)),
     spread by the kernel W and divided by the cell volume (naive mode: c_tilde in
-    place of c, naive_constants)."""
-    idx, w = shape_weights(x, p)
+    place of c, naive_constants).  w: optional packet weights N_j / N (losses), which
+    scale every packet total."""
+    idx, wts = shape_weights(x, p)
     g = lorentz_gamma(u)
     cp = mode_constants(p)[2]
     m = p.mass * np.ones(u.shape[1], dtype=u.dtype)
-    vals = np.concatenate([m[None], p.mass * cp * u, (p.mass * cp * cp * g)[None]])
-    d = deposit(idx, w, vals, p.n_cells) / p.volume
+    if w is not None:
+        m = m * w
+    vals = np.concatenate([m[None], m * cp * u, (m * cp * cp * g)[None]])
+    d = deposit(idx, wts, vals, p.n_cells) / p.volume
     return d[0], d[1:4], d[4]
 
 
@@ -278,13 +340,14 @@ def coupled_rollout(x, u, mom, egas, rho, B, p: Params, nsteps):
     return dict(x=x, u=u, mom=mom, egas=egas, E=electric_field(mom / rho, B, p.c))
 
 
-def conserved_totals(u, mom, egas, p: Params):
+def conserved_totals(u, mom, egas, p: Params, w=None):
     """Totals the CR-gas exchange conserves (Sec. 2, discussion after Eq. (12)): the
     momentum V sum_i (rho u)_i + (c/c_tilde) sum_j P_j with P_j = M_j c u_j, and the
     energy V sum_i e_i + (c/c_tilde) sum_j M_j c^2 gamma_j.  Naive mode: the totals its
     own exchange conserves, with M_j c_tilde u_j, M_j c_tilde^2 gamma_j and no c/c_tilde.
-    Returns (momentum (3,), energy)."""
+    w: optional packet weights (losses).  Returns (momentum (3,), energy)."""
     _, _, cp, k = mode_constants(p)
-    P = p.volume * mom.sum(axis=1) + k * p.mass * cp * u.sum(axis=1)
-    En = p.volume * egas.sum() + k * p.mass * cp * cp * lorentz_gamma(u).sum()
+    wt = np.ones(u.shape[1]) if w is None else w
+    P = p.volume * mom.sum(axis=1) + k * p.mass * cp * (wt * u).sum(axis=1)
+    En = p.volume * egas.sum() + k * p.mass * cp * cp * (wt * lorentz_gamma(u)).sum()
     return P, En

@@ -14,7 +14,7 @@ from scipy.integrate import solve_ivp
 
 import oracle
 from oracle import adjoint
-from workloads import make_workload
+from workloads import make_workload, loss_state
 from tests.helpers import oracle_params, oracle_fields
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -699,6 +699,161 @@ def test_planted_mistakes_fail_the_naive_pins(monkeypatch):
     with monkeypatch.context() as m:
         m.setattr(pic, "naive_constants", variant(3))
         assert max(_naive_exchange_residuals()[:2]) > 1e-3
+
+
+# ---------------------------------------------------------------- catastrophic losses (Secs. 2 and 4)
+
+def _loss_gyration_errors():
+    """Weight of a gyrating packet in uniform B and uniform n_n.  B does no work, so beta is
+    constant and the weight after N steps is exp(-sigma n_n L) with L = N c_tilde beta dt
+    the path length on the grid (also measured from the positions).  (a) With dt ~ 1/c_tilde
+    the weight is the same for every c_tilde: the loss per distance does not depend on
+    c_tilde (Sec. 2, closing discussion).  (b) At a fixed dt the weight after a physical
+    time T is exp(-(c_tilde/c) sigma c beta n_n T): the loss rate is slowed by c_tilde/c.
+    Returns the largest relative error of the weight against these closed forms."""
+    n, c, qomc, sigma, nn0 = 16, 1000.0, 4000.0, 0.05, 1.3
+    E, B = _uniform_fields(n)
+    nn = np.full(n ** 3, nn0)
+    u0 = np.array([[3.0], [8.0], [-2.0]])
+    beta = math.sqrt(float(np.sum(u0 ** 2))) / math.sqrt(1.0 + float(np.sum(u0 ** 2)))
+    errs, ws = [], []
+    for ratio in (1.0, 10.0, 100.0):
+        p = _uniform_params(n, "cic", ratio, dt=0.3 / (c / ratio))  # 0.3 cells per step
+        x, u, w = np.array([[8.0], [8.0], [8.0]]), u0, np.ones(1)
+        L = 0.0
+        for _ in range(60):
+            x1, u, w, _, _ = oracle.step_with_losses(x, u, w, E, B, nn, sigma, p)
+            d = x1 - x
+            d -= n * np.round(d / n)
+            L += float(np.sqrt(np.sum(d * d)))
+            x = x1
+        want = math.exp(-sigma * nn0 * 60 * p.c_tilde * beta * p.dt)
+        errs += [abs(w[0] / want - 1.0), abs(L / (60 * p.c_tilde * beta * p.dt) - 1.0)]
+        ws.append(w[0])
+    errs.append(max(ws) / min(ws) - 1.0)
+    for ratio in (1.0, 10.0):
+        p = _uniform_params(n, "cic", ratio, dt=1e-4)
+        x, u, w = np.array([[8.0], [8.0], [8.0]]), u0, np.ones(1)
+        for _ in range(50):
+            x, u, w, _, _ = oracle.step_with_losses(x, u, w, E, B, nn, sigma, p)
+        want = math.exp(-(p.c_tilde / c) * sigma * c * beta * nn0 * 50 * p.dt)
+        errs.append(abs(w[0] / want - 1.0))
+    return max(errs)
+
+
+def test_loss_per_distance_independent_of_c_tilde():
+    assert _loss_gyration_errors() < 1e-12
+
+
+def _loss_density_sample_error(shape):
+    """A packet on a straight path (no fields) through a nucleon density that is linear
+    along x on the cell centres, n_n = a + b x (reproduced exactly by CIC and TSC): the
+    weight is exp(-sigma sum_n n_n(x^n) dl), the density taken at the start of every step,
+    whose closed form is sigma [(a + b x0) N dl + b dl^2 N (N-1)/2]."""
+    n, sigma, a, b = 32, 0.05, 1.0, 0.05
+    p = _uniform_params(n, shape, 10.0, dt=3e-3)
+    Z = np.zeros((3, n ** 3))
+    i = np.arange(n ** 3)
+    nn = a + b * ((i % n) + 0.5)
+    uz = 0.8
+    u = np.array([[uz], [0.0], [0.0]])
+    beta = uz / math.sqrt(1 + uz * uz)
+    x, w = np.array([[6.3], [9.5], [11.2]]), np.ones(1)
+    N = 40
+    for _ in range(N):
+        x, u, w, _, _ = oracle.pic.step_with_losses(x, u, w, Z, Z, nn, sigma, p)
+    dl = p.c_tilde * beta * p.dt
+    want = math.exp(-sigma * ((a + b * 6.3) * N * dl + b * dl * dl * N * (N - 1) / 2))
+    return abs(w[0] / want - 1.0)
+
+
+@pytest.mark.parametrize("shape", ["cic", "tsc"])
+def test_loss_takes_the_density_at_the_step_start(shape):
+    assert _loss_density_sample_error(shape) < 1e-12
+
+
+def _loss_conservation_residual():
+    """Over 8 steps with strong losses the gas takes both the Lorentz-force exchange and
+    what the losses remove: V sum dM + (c/c_tilde) sum_j w_j M c u_j and the energy total
+    stay fixed to rounding (Sec. 2: conserved rho u + (c/c_tilde) P)."""
+    w = make_workload(2, n=8, ppc=4, ratio=30.0)
+    p = oracle_params(w)
+    E, B = oracle_fields(w)
+    nn, _, wt = loss_state(w)
+    sigma = 2.0
+    r = oracle.rollout_with_losses(w.x, w.u, wt, E, B, nn, sigma, p, 8)
+    zero3, zero = np.zeros((3, w.n_cells)), np.zeros(w.n_cells)
+    P0, E0 = oracle.conserved_totals(w.u, zero3, zero, p, w=wt)
+    P1, E1 = oracle.conserved_totals(r["u"], r["dM_sum"], r["dE_sum"], p, w=r["w"])
+    k = p.c / p.c_tilde
+    eps = 2.0 ** -53
+    scale_p = k * p.mass * p.c * np.abs(w.u).sum()
+    scale_e = k * p.mass * p.c ** 2 * oracle.lorentz_gamma(w.u).sum()
+    lost = 1.0 - float(r["w"].mean())
+    return max(float(np.max(np.abs(P1 - P0))) / (40 * 8 * eps * scale_p),
+               abs(E1 - E0) / (40 * 8 * eps * scale_e)), lost
+
+
+def test_losses_hand_what_they_remove_to_the_gas():
+    res, lost = _loss_conservation_residual()
+    assert res < 1.0 and lost > 0.01
+
+
+def _loss_courant_error():
+    """Where the loss limit binds, one step of the Courant dt removes exactly C e-folds of
+    the fastest-losing packet (Sec. 4: dt < C N_j/|dN_j/dt|), and that dt grows as c/c_tilde."""
+    w = make_workload(2, n=8, ppc=2, ratio=30.0)
+    nn, _, _ = loss_state(w)
+    sigma = 50.0
+    dts, errs = [], []
+    for ratio in (1.0, 30.0):
+        ct = w.c / ratio
+        dt = oracle.courant_dt(w.u, w.B, w.c, ct, w.qomc, w.dx, w.courant, sigma=sigma, nn=nn)
+        p = oracle.Params(w.nx, w.ny, w.nz, w.dx, w.shape, w.c, ct, w.qomc, dt, w.mass)
+        g = oracle.lorentz_gamma(w.u)
+        j = int(np.argmax(np.linalg.norm(w.u, axis=0) / g))
+        f = oracle.pic.loss_factor(w.u[:, j:j + 1], np.array([nn.max()]), sigma, p)
+        dts.append(dt)
+        errs.append(abs(-math.log(float(f[0])) / w.courant - 1.0))
+    return max(errs + [abs(dts[1] / dts[0] / 30.0 - 1.0)])
+
+
+def test_loss_timestep_limit():
+    assert _loss_courant_error() < 1e-12
+
+
+def test_zero_cross_section_is_the_loss_free_step():
+    w = make_workload(2, n=8, ppc=2)
+    p = oracle_params(w)
+    E, B = oracle_fields(w)
+    nn, _, wt = loss_state(w)
+    a = oracle.step(w.x, w.u, E, B, p)
+    b = oracle.step_with_losses(w.x, w.u, wt, E, B, nn, 0.0, p)
+    assert np.array_equal(b[2], wt)
+    for ka, kb in ((0, 0), (1, 1), (2, 3), (3, 4)):
+        assert np.allclose(a[ka], b[kb], rtol=1e-15, atol=0), ka
+
+
+def test_planted_mistakes_fail_the_loss_pins(monkeypatch):
+    """Plausible mistakes in the loss stage each fail one of the loss pins."""
+    pic = oracle.pic
+    good_factor, good_step = pic.loss_factor, pic.step_with_losses
+    with monkeypatch.context() as m:
+        # rate without the c_tilde/c reduction
+        m.setattr(pic, "loss_factor", lambda u, nn, s, p: good_factor(u, nn, s * p.c / p.c_tilde, p))
+        assert _loss_gyration_errors() > 1e-3 and _loss_courant_error() > 1e-3
+    with monkeypatch.context() as m:
+        # density taken after the drift
+        def late(x, u, w, E, B, nn, sigma, p):
+            x1, u1, _, dM, dE = good_step(x, u, w, E, B, nn, 0.0, p)
+            idx, wts = pic.shape_weights(x1, p)
+            return x1, u1, w * good_factor(u1, pic.gather(nn[None], idx, wts)[0], sigma, p), dM, dE
+        m.setattr(pic, "step_with_losses", late)
+        assert _loss_density_sample_error("cic") > 1e-4
+    with monkeypatch.context() as m:
+        # the removed packet totals not handed to the gas
+        m.setattr(pic, "exchange_weighted", lambda u0, w0, u1, w1, p: tuple(w1 * v for v in pic.exchange(u0, u1, p)))
+        assert _loss_conservation_residual()[0] > 100.0
 
 
 # ---------------------------------------------------------------- reference gradients

@@ -8,4 +8,4 @@ no deposit, no timestep rule); both the CPU oracle and the GPU path take these
 arrays as their common input.
 """
 
-from .configs import Workload, make_workload, gas_state, WORKLOADS, UNITS  # noqa: F401
+from .configs import Workload, make_workload, gas_state, loss_state, WORKLOADS, UNITS  # noqa: F401

@@ -232,3 +232,14 @@ def gas_state(w: Workload, seed: int = 0):
     mom = rho * w.u_gas.reshape(3, -1)
     egas = 0.5 * UNITS["B0"] ** 2 * rng.uniform(1.0, 2.0, nc)
     return rho, np.ascontiguousarray(mom), egas
+
+
+def loss_state(w: Workload, seed: int = 0):
+    """Nucleon density and loss cross-section for runs with catastrophic losses: n_n is
+    the gas density of ``gas_state`` (nucleon mass 1 in code units) and sigma is set so
+    that the mean free path 1/(sigma <n_n>) is 40 cells.  Packets start with weight 1.
+    Returns (nn (n_cells,), sigma, weights (Np,))."""
+    rho, _, _ = gas_state(w, seed)
+    nn = rho / 1.0
+    sigma = 1.0 / (40.0 * w.dx * float(nn.mean()))
+    return nn, sigma, np.ones(w.n_particles)
