@@ -16,7 +16,8 @@ step kernel's algorithmic HBM bytes per launch over its event-timed average
 duration against the 8 TB/s HBM3E peak; "coupled" = the FP64 step coupled to the
 workload's gas (exchange into the gas momentum and energy, E rebuilt every step);
 "naive" = the FP64 step in the naive-substitution contrast mode (same kernels,
-naive constants);
+naive constants); "losses" = the FP64 step with catastrophic losses (packet weights
+in the cell lists, nucleon density gathered by the step);
 "backward" = the differentiation form;
 "cpu_baseline" = the CPU oracle timed on a bounded sample of the same workload.
 """
@@ -75,16 +76,23 @@ def measured_traffic(precision, workload):
     return rec.get("bytes_per_launch")
 
 
-def time_path(w, precision, steps, warmup, sort_every, coupled=False, flags=0):
+def time_path(w, precision, steps, warmup, sort_every, coupled=False, flags=0, losses=False):
     """Time `steps` steps in one call.  coupled=True runs them coupled to the workload's
     seeded gas (rsol_step_coupled: the exchange goes into the gas momentum and energy and
-    E is rebuilt from the gas velocity after every step); flags are RSOL_FLAG_* bits."""
+    E is rebuilt from the gas velocity after every step); losses=True adds catastrophic
+    losses with the seeded nucleon density and a 4-cell mean free path; flags are
+    RSOL_FLAG_* bits."""
     import torch
     from paper_2111_14704_amd.sim import Simulation
-    from workloads import gas_state
+    from paper_2111_14704_amd.rsol import RSOL_FLAG_LOSSES
+    from workloads import gas_state, loss_state
 
-    sim = Simulation.from_workload(w, precision=precision, sort_every=sort_every, flags=flags)
+    sim = Simulation.from_workload(w, precision=precision, sort_every=sort_every,
+                                   flags=flags | (RSOL_FLAG_LOSSES if losses else 0))
     h = sim.handle
+    if losses:
+        nn, sigma, wt = loss_state(w)
+        sim.set_losses(10.0 * sigma, nn, wt)
     if coupled:
         rho, mom, egas = (torch.as_tensor(a, dtype=torch.float64, device=sim.device) for a in gas_state(w))
 
@@ -201,6 +209,7 @@ def main():
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-coupled", action="store_true", help="skip the run coupled to the gas")
     ap.add_argument("--no-naive", action="store_true", help="skip the naive-substitution contrast run")
+    ap.add_argument("--no-losses", action="store_true", help="skip the run with catastrophic losses")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="first run one plain device copy of BYTES bytes (a known-size reference for HBM counters)")
     args = ap.parse_args()
@@ -248,6 +257,11 @@ def main():
         rn = time_path(w, "fp64", args.steps, args.warmup, args.sort_every, flags=RSOL_FLAG_NAIVE)
         print(f"[bench] naive fp64 {rn['value']:.3e} upd/s, kernel {rn['kernel_ms']:.3f} ms", file=sys.stderr,
               flush=True)
+    rl = None
+    if not args.no_losses:
+        rl = time_path(w, "fp64", args.steps, args.warmup, args.sort_every, losses=True)
+        print(f"[bench] losses fp64 {rl['value']:.3e} upd/s, kernel {rl['kernel_ms']:.3f} ms", file=sys.stderr,
+              flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w)
@@ -275,6 +289,9 @@ def main():
                                dtype="f64", overhead_vs_static=rc["ms_per_step"] / r64["ms_per_step"] - 1.0)
     if rn:
         line["naive"] = dict(value=rn["value"], ms_per_step=rn["ms_per_step"], kernel_ms=rn["kernel_ms"], dtype="f64")
+    if rl:
+        line["losses"] = dict(value=rl["value"], ms_per_step=rl["ms_per_step"], kernel_ms=rl["kernel_ms"], dtype="f64",
+                              overhead_vs_static=rl["ms_per_step"] / r64["ms_per_step"] - 1.0)
     print(json.dumps(line), flush=True)
 
 

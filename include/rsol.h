@@ -87,6 +87,9 @@ typedef struct rsol_params {
                                    rsol_courant_dt's gyro limit uses the unreduced q|B|/(gamma m c).
                                    Drift, E and every kernel are the RSOL ones; the
                                    differentiation-form entry points return RSOL_EINVAL.      */
+#define RSOL_FLAG_LOSSES 8      /* set at rsol_init: the scratch layout carries a weight per
+                                   packet so that rsol_set_losses can switch on catastrophic
+                                   losses; fixed for the life of the handle                   */
 
 typedef struct rsol_ctx* rsol_handle;
 
@@ -114,6 +117,25 @@ int rsol_electric_field(rsol_handle h, const double* u_gas, const double* B, dou
 /* Register the grid fields E, B ([3][n_cells] doubles) used by the gather.  The
  * FP32 form takes float copies into scratch here, so call again after changing them. */
 int rsol_set_fields(rsol_handle h, const double* E, const double* B);
+
+/* Catastrophic losses (Sec. 2, collisional terms; Sec. 4 for the timestep).  Every
+ * packet total (N, M, energy, P) decays at the reduced rate (c_tilde/c) <sigma v> n_n with
+ * <sigma v> = sigma c beta, beta from the packet's momentum after the kick and n_n the
+ * nucleon density gathered at the packet's position before the drift with the kernel W;
+ * the decay over a step is integrated exactly with that frozen rate.  The exchange
+ * deposit becomes the change of the weighted packet totals, so what the losses remove
+ * goes to the gas with the same -(c/c_tilde) factor (Eq. (12)).
+ *   sigma  cross-section (area in the units of dx^2), >= 0
+ *   nn     [n_cells] nucleon number density (doubles); read by every later step (the
+ *          FP32 form takes a float copy here, so call again after changing it)
+ *   w      [np] packet weights N_j/N (precision type), in/out: updated by rsol_step and
+ *          rsol_step_coupled and permuted with the packets; the moments weight by it.
+ * Needs a handle created with RSOL_FLAG_LOSSES (else RSOL_ESTATE).  Supported by the
+ * default cell-list path and RSOL_FLAG_KEEP_ORDER; with losses registered, the tiled
+ * path, rsol_sort, the separate phases (gather/push/deposit/drift) and the
+ * differentiation form return RSOL_EINVAL.  rsol_courant_dt adds the limit
+ * dt < C / ((c_tilde/c) sigma c beta_max n_n,max). */
+int rsol_set_losses(rsol_handle h, double sigma, const double* nn, void* w);
 
 /* Register the packet state (Sec. 2, Eq. (4): packets {x, p} with weights N_j).
  * FP64 form: pos = double x[3][np], off = NULL, u = double[3][np].
@@ -183,7 +205,7 @@ int rsol_step_coupled(rsol_handle h, int32_t nsteps, const double* rho, double* 
  * overwritten; any may be NULL. */
 int rsol_moments(rsol_handle h, double* rho, double* P, double* e);
 
-/* Set the RSOL_FLAG_* bits of the handle. */
+/* Set the RSOL_FLAG_* bits of the handle (RSOL_FLAG_LOSSES cannot change). */
 int rsol_set_flags(rsol_handle h, int32_t flags);
 
 /* ---- Differentiation form (reverse mode through gather -> push -> drift) ----

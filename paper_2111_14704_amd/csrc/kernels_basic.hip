@@ -94,10 +94,10 @@ __global__ void cells_to_positions_kernel(const int32_t* __restrict__ cell, cons
 __device__ __forceinline__ unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
 
 template <typename T>
-__global__ void dt_inputs_kernel(Packets<T> P, const double* __restrict__ B, int nc,
+__global__ void dt_inputs_kernel(Packets<T> P, const double* __restrict__ B, const double* __restrict__ nn, int nc,
                                  unsigned long long* out) {
-  __shared__ double s_beta[kBlock], s_gamma[kBlock], s_b[kBlock];
-  double bmax = 0.0, gmin = INFINITY, bb = 0.0;
+  __shared__ double s_beta[kBlock], s_gamma[kBlock], s_b[kBlock], s_n[kBlock];
+  double bmax = 0.0, gmin = INFINITY, bb = 0.0, nmax = 0.0;
   for (int64_t i = gtid(); i < P.np; i += gstride()) {
     const double ux = (double)P.u[i], uy = (double)P.u[P.np + i], uz = (double)P.u[2 * P.np + i];
     const double uu = ux * ux + uy * uy + uz * uz;
@@ -108,16 +108,19 @@ __global__ void dt_inputs_kernel(Packets<T> P, const double* __restrict__ B, int
   for (int64_t i = gtid(); i < nc; i += gstride()) {
     const double bx = B[i], by = B[nc + i], bz = B[2 * (int64_t)nc + i];
     bb = fmax(bb, sqrt(bx * bx + by * by + bz * bz));
+    if (nn) nmax = fmax(nmax, fmax(nn[i], 0.0));
   }
   s_beta[threadIdx.x] = bmax;
   s_gamma[threadIdx.x] = gmin;
   s_b[threadIdx.x] = bb;
+  s_n[threadIdx.x] = nmax;
   __syncthreads();
   for (int w = blockDim.x / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) {
       s_beta[threadIdx.x] = fmax(s_beta[threadIdx.x], s_beta[threadIdx.x + w]);
       s_gamma[threadIdx.x] = fmin(s_gamma[threadIdx.x], s_gamma[threadIdx.x + w]);
       s_b[threadIdx.x] = fmax(s_b[threadIdx.x], s_b[threadIdx.x + w]);
+      s_n[threadIdx.x] = fmax(s_n[threadIdx.x], s_n[threadIdx.x + w]);
     }
     __syncthreads();
   }
@@ -126,6 +129,7 @@ __global__ void dt_inputs_kernel(Packets<T> P, const double* __restrict__ B, int
     atomicMax(&out[0], dbits(s_beta[0]));
     atomicMin(&out[1], dbits(s_gamma[0]));
     atomicMax(&out[2], dbits(s_b[0]));
+    atomicMax(&out[3], dbits(s_n[0]));
   }
 }
 
@@ -133,6 +137,7 @@ __global__ void dt_init_kernel(unsigned long long* out) {
   out[0] = dbits(0.0);
   out[1] = dbits(INFINITY);
   out[2] = dbits(0.0);
+  out[3] = dbits(0.0);
 }
 
 // ---------------------------------------------------------------- unfused phases
@@ -307,6 +312,7 @@ __global__ void moments_kernel(Packets<T> P, double* __restrict__ rho, double* _
     const Stencil<M, T> s = stencil_of<M, T>(P, i, k);
     const double ux = (double)P.u[i], uy = (double)P.u[np + i], uz = (double)P.u[2 * np + i];
     const double g = sqrt(1.0 + (ux * ux + uy * uy + uz * uz));
+    const double pw = P.w ? (double)P.w[i] : 1.0;  // packet weight under losses
     #pragma unroll
     for (int cz = 0; cz < M; ++cz) {
       const int iz = wrap_index(s.az.base + cz, k.nz);
@@ -318,7 +324,7 @@ __global__ void moments_kernel(Packets<T> P, double* __restrict__ rho, double* _
         for (int cx = 0; cx < M; ++cx) {
           const int ix = wrap_index(s.ax.base + cx, k.nx);
           const int64_t node = ix + (int64_t)k.nx * (iy + (int64_t)k.ny * iz);
-          const double w = (double)s.ax.w[cx] * wyz;
+          const double w = (double)s.ax.w[cx] * wyz * pw;
           if (rho) atomicAdd(&rho[node], w * m);
           if (Pm) {
             atomicAdd(&Pm[node], w * mc * ux);
@@ -333,15 +339,18 @@ __global__ void moments_kernel(Packets<T> P, double* __restrict__ rho, double* _
 }
 
 // Fused step with global atomics: gather at x^n, kick, exchange deposit at x^n, drift.
-template <int M, typename T>
+// LOSS: also gather the nucleon density NN, reduce the packet weight (catastrophic
+// losses) and deposit the change of the weighted packet totals.
+template <int M, typename T, bool LOSS>
 __global__ void __launch_bounds__(kBlock) step_global_kernel(Packets<T> P, const T* __restrict__ E,
-                                                             const T* __restrict__ B, double* __restrict__ dM,
-                                                             double* __restrict__ dE, RunConsts k) {
+                                                             const T* __restrict__ B, const T* __restrict__ NN,
+                                                             double* __restrict__ dM, double* __restrict__ dE,
+                                                             RunConsts k) {
   const int64_t nc = k.ncells, np = P.np;
   const T h = (T)k.h, hb = (T)k.hb;
   for (int64_t i = gtid(); i < np; i += gstride()) {
     const Stencil<M, T> s = stencil_of<M, T>(P, i, k);
-    T e[3] = {0, 0, 0}, b[3] = {0, 0, 0};
+    T e[3] = {0, 0, 0}, b[3] = {0, 0, 0}, nnp = 0;
     #pragma unroll
     for (int cz = 0; cz < M; ++cz) {
       const int iz = wrap_index(s.az.base + cz, k.nz);
@@ -359,6 +368,7 @@ __global__ void __launch_bounds__(kBlock) step_global_kernel(Packets<T> P, const
             e[d] += w * E[d * nc + node];
             b[d] += w * B[d * nc + node];
           }
+          if constexpr (LOSS) nnp += w * NN[node];
         }
       }
     }
@@ -368,9 +378,18 @@ __global__ void __launch_bounds__(kBlock) step_global_kernel(Packets<T> P, const
     P.u[i] = nux;
     P.u[np + i] = nuy;
     P.u[2 * np + i] = nuz;
+    T wv = T(1), wn = T(1), lost = T(0);
+    if constexpr (LOSS) {
+      wv = P.w[i];
+      loss_step<T>(nux, nuy, nuz, nnp, (T)k.lrate, wv, &wn, &lost);
+      P.w[i] = wn;
+    }
     if (dM) {
-      const T qx = (T)k.pfac * q.dux, qy = (T)k.pfac * q.duy, qz = (T)k.pfac * q.duz;
-      const T qe = (T)k.efac * q.dg;
+      const T wl = wv * lost;
+      const T qx = LOSS ? (T)k.pfac * (wn * q.dux - wl * ux) : (T)k.pfac * q.dux;
+      const T qy = LOSS ? (T)k.pfac * (wn * q.duy - wl * uy) : (T)k.pfac * q.duy;
+      const T qz = LOSS ? (T)k.pfac * (wn * q.duz - wl * uz) : (T)k.pfac * q.duz;
+      const T qe = LOSS ? (T)k.efac * (wn * q.dg - wl * q.g0) : (T)k.efac * q.dg;
       #pragma unroll
       for (int cz = 0; cz < M; ++cz) {
         const int iz = wrap_index(s.az.base + cz, k.nz);
@@ -439,12 +458,12 @@ hipError_t launch_cells_to_positions(const int32_t* cell, const float* off, doub
 }
 
 template <typename T>
-hipError_t launch_dt_inputs(const Packets<T>& P, const double* B, int ncells, unsigned long long* out,
-                            hipStream_t s) {
+hipError_t launch_dt_inputs(const Packets<T>& P, const double* B, const double* nn, int ncells,
+                            unsigned long long* out, hipStream_t s) {
   hipLaunchKernelGGL(dt_init_kernel, dim3(1), dim3(1), 0, s, out);
   const int64_t n = P.np > ncells ? P.np : ncells;
   hipLaunchKernelGGL(dt_inputs_kernel<T>, dim3(grid_for(n) > 4096 ? 4096 : grid_for(n)), dim3(kBlock), 0, s, P,
-                     B, ncells, out);
+                     B, nn, ncells, out);
   return hipGetLastError();
 }
 
@@ -492,18 +511,23 @@ hipError_t launch_moments(int shape, const Packets<T>& P, double* rho, double* P
 }
 
 template <typename T>
-hipError_t launch_step_global(int shape, const Packets<T>& P, const T* E, const T* B, double* dM, double* dE,
-                              const RunConsts& k, hipStream_t s) {
-  if (shape == kShapeCIC)
-    hipLaunchKernelGGL((step_global_kernel<2, T>), dim3(grid_for(P.np)), dim3(kBlock), 0, s, P, E, B, dM, dE, k);
-  else
-    hipLaunchKernelGGL((step_global_kernel<3, T>), dim3(grid_for(P.np)), dim3(kBlock), 0, s, P, E, B, dM, dE, k);
+hipError_t launch_step_global(int shape, const Packets<T>& P, const T* E, const T* B, const T* NN, double* dM,
+                              double* dE, const RunConsts& k, hipStream_t s) {
+  if (NN && !P.w) return hipErrorInvalidValue;
+  const dim3 g(grid_for(P.np)), b(kBlock);
+  if (shape == kShapeCIC) {
+    if (NN) hipLaunchKernelGGL((step_global_kernel<2, T, true>), g, b, 0, s, P, E, B, NN, dM, dE, k);
+    else hipLaunchKernelGGL((step_global_kernel<2, T, false>), g, b, 0, s, P, E, B, NN, dM, dE, k);
+  } else {
+    if (NN) hipLaunchKernelGGL((step_global_kernel<3, T, true>), g, b, 0, s, P, E, B, NN, dM, dE, k);
+    else hipLaunchKernelGGL((step_global_kernel<3, T, false>), g, b, 0, s, P, E, B, NN, dM, dE, k);
+  }
   return hipGetLastError();
 }
 
 #define RSOL_INSTANTIATE(T)                                                                                    \
-  template hipError_t launch_dt_inputs<T>(const Packets<T>&, const double*, int, unsigned long long*,         \
-                                          hipStream_t);                                                        \
+  template hipError_t launch_dt_inputs<T>(const Packets<T>&, const double*, const double*, int,               \
+                                          unsigned long long*, hipStream_t);                                   \
   template hipError_t launch_gather<T>(int, const Packets<T>&, const T*, const T*, T*, T*, const RunConsts&, \
                                        hipStream_t);                                                           \
   template hipError_t launch_push<T>(const Packets<T>&, const T*, const T*, T*, const RunConsts&, hipStream_t); \
@@ -512,8 +536,8 @@ hipError_t launch_step_global(int shape, const Packets<T>& P, const T* E, const 
   template hipError_t launch_drift<T>(const Packets<T>&, const RunConsts&, hipStream_t);                      \
   template hipError_t launch_moments<T>(int, const Packets<T>&, double*, double*, double*, const RunConsts&,  \
                                         hipStream_t);                                                          \
-  template hipError_t launch_step_global<T>(int, const Packets<T>&, const T*, const T*, double*, double*,     \
-                                            const RunConsts&, hipStream_t);
+  template hipError_t launch_step_global<T>(int, const Packets<T>&, const T*, const T*, const T*, double*,     \
+                                            double*, const RunConsts&, hipStream_t);
 
 RSOL_INSTANTIATE(double)
 RSOL_INSTANTIATE(float)

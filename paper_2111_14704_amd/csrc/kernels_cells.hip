@@ -85,21 +85,21 @@ __device__ __forceinline__ void weights3(T f, T* w) {
   }
 }
 
-// Interpolate six field components at one packet from the 27 nodes around its home
-// cell, fetch(node, comp) giving the node values; the summation order (x first, then
-// y-z pairs) is the one the quad path uses, so a packet's arithmetic does not depend
-// on the store it was read from.
-template <typename T, typename F>
-__device__ __forceinline__ void gather27(const T* w, F fetch, T out[6]) {
+// Interpolate NC grid components (E, B and, with losses, the nucleon density) at one
+// packet from the 27 nodes around its home cell, fetch(node, comp) giving the node
+// values; the summation order (x first, then y-z pairs) is the one the quad path
+// uses, so a packet's arithmetic does not depend on the store it was read from.
+template <int NC, typename T, typename F>
+__device__ __forceinline__ void gather27(const T* w, F fetch, T out[NC]) {
   #pragma unroll
-  for (int d = 0; d < 6; ++d) out[d] = T(0);
+  for (int d = 0; d < NC; ++d) out[d] = T(0);
   #pragma unroll
   for (int c = 0; c < 3; ++c)
     #pragma unroll
     for (int b = 0; b < 3; ++b) {
       const T wyz = w[3 + b] * w[6 + c];
       #pragma unroll
-      for (int d = 0; d < 6; ++d) {
+      for (int d = 0; d < NC; ++d) {
         T t = T(0);
         #pragma unroll
         for (int a = 0; a < 3; ++a) t += w[a] * fetch(a + 3 * (b + 3 * c), d);
@@ -169,11 +169,12 @@ StepView step_view(const CellLists& L) {
 }
 
 // Store a packet into slot j of S (FP32: its home cell into slot jc, which is a trash
-// slot for buckets, where the slot implies the cell).
-template <typename T>
+// slot for buckets, where the slot implies the cell); W: with its weight wv.
+template <typename T, bool W>
 __device__ __forceinline__ void store_slot(const SlotArrays& S, int64_t j, int64_t jc, const double x[3],
-                                           const T f[3], const T u[3], int32_t id, int32_t cell) {
+                                           const T f[3], const T u[3], T wv, int32_t id, int32_t cell) {
   T* su = (T*)S.u;
+  if constexpr (W) ((T*)S.w)[j] = wv;
   #pragma unroll
   for (int c = 0; c < 3; ++c) {
     if constexpr (is_fp64<T>()) S.x[c * S.stride + j] = x[c];
@@ -185,10 +186,11 @@ __device__ __forceinline__ void store_slot(const SlotArrays& S, int64_t j, int64
 }
 
 // Load a packet from an inbox or the overflow list (home cell not implied by the slot).
-template <typename T>
+template <typename T, bool W>
 __device__ __forceinline__ void load_free(const SlotArrays& S, int64_t j, const RunConsts& k, int home[3], T f[3],
-                                          double xa[3], T u[3], int32_t& id) {
+                                          double xa[3], T u[3], T& wv, int32_t& id) {
   const T* su = (const T*)S.u;
+  wv = W ? ((const T*)S.w)[j] : T(1);
   if constexpr (is_fp64<T>()) {
     const int n3[3] = {k.nx, k.ny, k.nz};
     #pragma unroll
@@ -304,11 +306,16 @@ __device__ __forceinline__ uint32_t drift3(const RunConsts& k, const int home[3]
   return fin ? (uint32_t)ERR_COURANT : (uint32_t)ERR_NAN;
 }
 
-template <int M, typename T, bool DEP>
+// LOSS: catastrophic losses.  The tile stages the nucleon density NN as a seventh
+// field, the quad's lane 3 (idle in the field gather otherwise) gathers it, and the
+// packet weight travels with the packet through the slot stores.
+template <int M, typename T, bool DEP, bool LOSS>
 __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const T* __restrict__ E,
-                                                              const T* __restrict__ B, double* __restrict__ dM,
-                                                              double* __restrict__ dE, RunConsts k) {
-  __shared__ T Fs[6][kRegionCells];
+                                                              const T* __restrict__ B, const T* __restrict__ NN,
+                                                              double* __restrict__ dM, double* __restrict__ dE,
+                                                              RunConsts k) {
+  constexpr int NF = LOSS ? 7 : 6;
+  __shared__ T Fs[NF][kRegionCells];
   __shared__ double Acc[4][kRegionCells];
   __shared__ int cntB[kCellTileCells];
   __shared__ int cntD[kDirs];
@@ -365,7 +372,8 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
   T pua[3], pub[3];
   double pxa[3], pxb[3];
   int32_t pida, pidb;
-  auto fetch = [&](int rd, double (&px)[3], T (&pu)[3], int32_t& pid) {
+  T pwa = T(1), pwb = T(1);
+  auto fetch = [&](int rd, double (&px)[3], T (&pu)[3], int32_t& pid, T& pw) {
     int kk = 4 * rd + q;
     kk = kk < V.cap ? kk : V.cap - 1;
     const int64_t j = ((int64_t)tile * V.cap + kk) * kCellTileCells + quad;
@@ -376,9 +384,10 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
       pu[d] = su[d * S.stride + j];
     }
     pid = S.id[j];
+    if constexpr (LOSS) pw = ((const T*)S.w)[j];
   };
-  fetch(0, pxa, pua, pida);
-  fetch(1, pxb, pub, pidb);
+  fetch(0, pxa, pua, pida, pwa);
+  fetch(1, pxb, pub, pidb, pwb);
   // this tile's inbox counts by direction, one per lane of the first wave
   const int cin = threadIdx.x < kDirs ? V.icnt_in[(int64_t)tile * kDirs + threadIdx.x] : 0;
 
@@ -391,6 +400,7 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
       Fs[d][r] = E[d * nc + rc];
       Fs[3 + d][r] = B[d * nc + rc];
     }
+    if constexpr (LOSS) Fs[6][r] = NN[rc];
     if constexpr (deposit) {
       #pragma unroll
       for (int d = 0; d < 4; ++d) Acc[d][r] = 0.0;
@@ -444,6 +454,7 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
 
   const T h = (T)k.h, hb = (T)k.hb;
   const T pf = (T)k.pfac, ef = (T)k.efac;
+  const T lrate = (T)k.lrate;
 
   // ------------------------------------------------------------ quads: one cell each
   {
@@ -464,7 +475,8 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
         for (int a = 0; a < 3; ++a) {
           const int node = a + 3 * (b + 3 * c);
           const int r = (lx + a) + kRegionEdge * ((ly + b) + kRegionEdge * (lz + c));
-          F0[node] = q < 3 ? Fs[q][r] : T(0);
+          if constexpr (LOSS) F0[node] = q < 3 ? Fs[q][r] : Fs[6][r];
+          else F0[node] = q < 3 ? Fs[q][r] : T(0);
           F1[node] = q < 3 ? Fs[3 + q][r] : T(0);
           D[node] = T(0);
         }
@@ -475,15 +487,17 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
     int64_t oj = trash, ojc = trash;
     double oxn[3] = {0.0, 0.0, 0.0};
     T ofn[3] = {T(0), T(0), T(0)}, oun[3] = {T(0), T(0), T(0)};
+    T ow = T(1);
     int32_t oid = 0, ocell = 0;
     auto flush = [&]() {
-      store_slot<T>(V.out, oj, ojc, oxn, ofn, oun, oid, ocell);
+      store_slot<T, LOSS>(V.out, oj, ojc, oxn, ofn, oun, ow, oid, ocell);
     };
-    auto round = [&](const int rd, double (&px)[3], T (&pu)[3], int32_t& pid) {
+    auto round = [&](const int rd, double (&px)[3], T (&pu)[3], int32_t& pid, T& pw) {
       const bool act = 4 * rd + q < n;
       T f[3], u[3];
       double xa[3] = {0.0, 0.0, 0.0};
       const int32_t id = pid;
+      const T wv = act ? pw : T(1);
       #pragma unroll
       for (int d = 0; d < 3; ++d) {
         if constexpr (is_fp64<T>()) {
@@ -496,7 +510,7 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
         u[d] = act ? pu[d] : T(0);
       }
       flush();
-      fetch(rd + 2, px, pu, pid);
+      fetch(rd + 2, px, pu, pid, pw);
 
       // own weights -> LDS: x weights, then the nine y-z products
       {
@@ -552,14 +566,29 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
       // kick (Eq. (11))
       const Kick<T> kq = boris_kick<T>(u[0], u[1], u[2], eb[0], eb[1], eb[2], eb[3], eb[4], eb[5], h, hb);
       const T un[3] = {u[0] + kq.dux, u[1] + kq.duy, u[2] + kq.duz};
+      // losses: weight update; the exchange becomes the change of the weighted totals,
+      // wn du - w lost u (momentum) and wn dgamma - w lost gamma (energy)
+      T wn = wv, lost = T(0);
+      if constexpr (LOSS) {
+        const T nnp = rsw[(qbase + 3) * kRsStride<T> + 2 * q];
+        loss_step<T>(un[0], un[1], un[2], nnp, lrate, wv, &wn, &lost);
+      }
 
       // exchange (Eq. (12)) into the quad's registers, lane q taking component q
       if constexpr (deposit) {
         T* o = pkw + lane * kPkStride<T>;
-        o[12] = act ? pf * kq.dux : T(0);
-        o[13] = act ? pf * kq.duy : T(0);
-        o[14] = act ? pf * kq.duz : T(0);
-        o[15] = act ? ef * kq.dg : T(0);
+        if constexpr (LOSS) {
+          const T wl = wv * lost;
+          o[12] = act ? pf * (wn * kq.dux - wl * u[0]) : T(0);
+          o[13] = act ? pf * (wn * kq.duy - wl * u[1]) : T(0);
+          o[14] = act ? pf * (wn * kq.duz - wl * u[2]) : T(0);
+          o[15] = act ? ef * (wn * kq.dg - wl * kq.g0) : T(0);
+        } else {
+          o[12] = act ? pf * kq.dux : T(0);
+          o[13] = act ? pf * kq.duy : T(0);
+          o[14] = act ? pf * kq.duz : T(0);
+          o[15] = act ? ef * kq.dg : T(0);
+        }
         wave_sync();
         #pragma unroll
         for (int J = 0; J < 4; ++J) {
@@ -591,13 +620,14 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
       ojc = to_bucket ? trash : oj;
       #pragma unroll
       for (int d = 0; d < 3; ++d) oun[d] = un[d];
+      ow = wn;
       oid = id;
       ocell = hn[0] + k.nx * (hn[1] + k.ny * hn[2]);
     };
     for (int rd = 0; __ballot(rd < rounds) != 0; rd += 2) {
-      round(rd, pxa, pua, pida);
+      round(rd, pxa, pua, pida, pwa);
       if (__ballot(rd + 1 < rounds) == 0) break;
-      round(rd + 1, pxb, pub, pidb);
+      round(rd + 1, pxb, pub, pidb, pwb);
     }
     flush();
     if (deposit && n > 0) {
@@ -616,22 +646,28 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
   // ------------------------------------------------------------ per packet: leftovers, then inbox
   {
     // one packet per thread: gather from the staged fields, deposit with LDS atomics
-    auto process = [&](const int home[3], const T f[3], const double xa[3], const T u[3], int32_t id) {
+    auto process = [&](const int home[3], const T f[3], const double xa[3], const T u[3], T wv, int32_t id) {
       // region coordinates of node home-1 (these packets all live in this tile)
       const int bx = home[0] - ttx * kCellTile, by = home[1] - tty * kCellTile, bz = home[2] - ttz * kCellTile;
       T w[9];
       weights3<M, T>(f[0], w);
       weights3<M, T>(f[1], w + 3);
       weights3<M, T>(f[2], w + 6);
-      T eb[6];
-      gather27<T>(w, [&](int node, int d) {
+      T eb[NF];
+      gather27<NF, T>(w, [&](int node, int d) {
         const int a = node % 3, b = (node / 3) % 3, c = node / 9;
         return Fs[d][(bx + a) + kRegionEdge * ((by + b) + kRegionEdge * (bz + c))];
       }, eb);
       const Kick<T> kq = boris_kick<T>(u[0], u[1], u[2], eb[0], eb[1], eb[2], eb[3], eb[4], eb[5], h, hb);
       const T un[3] = {u[0] + kq.dux, u[1] + kq.duy, u[2] + kq.duz};
+      T wn = wv, lost = T(0);
+      if constexpr (LOSS) loss_step<T>(un[0], un[1], un[2], eb[NF - 1], lrate, wv, &wn, &lost);
       if constexpr (deposit) {
-        const T qv[4] = {pf * kq.dux, pf * kq.duy, pf * kq.duz, ef * kq.dg};
+        const T wl = wv * lost;
+        const T qv[4] = {LOSS ? pf * (wn * kq.dux - wl * u[0]) : pf * kq.dux,
+                         LOSS ? pf * (wn * kq.duy - wl * u[1]) : pf * kq.duy,
+                         LOSS ? pf * (wn * kq.duz - wl * u[2]) : pf * kq.duz,
+                         LOSS ? ef * (wn * kq.dg - wl * kq.g0) : ef * kq.dg};
         #pragma unroll
         for (int c = 0; c < 3; ++c)
           #pragma unroll
@@ -655,7 +691,7 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
       bool to_bucket = false;
       int64_t j2 = place(V, ttx, tty, ttz, cntB, cntD, sDcap, sDoff, hn, &to_bucket);
       if (j2 < 0) j2 = place_overflow(V, trash, err);
-      store_slot<T>(V.out, j2, to_bucket ? trash : j2, xn, fn, un, id, hn[0] + k.nx * (hn[1] + k.ny * hn[2]));
+      store_slot<T, LOSS>(V.out, j2, to_bucket ? trash : j2, xn, fn, un, wn, id, hn[0] + k.nx * (hn[1] + k.ny * hn[2]));
     };
     const int nlo = sLo[kCellTileCells];
     const int nin = sPre[kDirs];
@@ -665,6 +701,7 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
       T f[3], u[3];
       double xa[3] = {0.0, 0.0, 0.0};
       int32_t id;
+      T wv = T(1);
       if (i < nlo) {
         // leftover packet: cell lc with sLo[lc] <= i < sLo[lc + 1], slot 4R + (i - sLo[lc])
         int lo = 0, hi = kCellTileCells - 1;
@@ -690,15 +727,16 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
           u[d] = su[d * S.stride + j];
         }
         id = S.id[j];
+        if constexpr (LOSS) wv = ((const T*)S.w)[j];
       } else {
         const int ii = i - nlo;
         int dir = 0;
         #pragma unroll
         for (int d = 1; d < kDirs; ++d) dir += (ii >= sPre[d]) ? 1 : 0;
         const int64_t j = (int64_t)tile * V.per_tile + sDoff[dir] + (ii - sPre[dir]);
-        load_free<T>(V.in, V.ib0 + j, k, home, f, xa, u, id);
+        load_free<T, LOSS>(V.in, V.ib0 + j, k, home, f, xa, u, wv, id);
       }
-      process(home, f, xa, u, id);
+      process(home, f, xa, u, wv, id);
     }
   }
 
@@ -712,7 +750,8 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
       T f[3], u[3];
       double xa[3];
       int32_t id;
-      load_free<T>(V.in, V.ov0 + i, k, home, f, xa, u, id);
+      T wv;
+      load_free<T, LOSS>(V.in, V.ov0 + i, k, home, f, xa, u, wv, id);
       T w[9];
       weights3<M, T>(f[0], w);
       weights3<M, T>(f[1], w + 3);
@@ -726,13 +765,20 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
           for (int a = 0; a < 3; ++a)
             nodes[a + 3 * (b + 3 * c)] = wrapm(home[0] - 1 + a, n3[0]) +
                 (int64_t)k.nx * (wrapm(home[1] - 1 + b, n3[1]) + (int64_t)k.ny * wrapm(home[2] - 1 + c, n3[2]));
-      T eb[6];
-      gather27<T>(w, [&](int node, int d) { return d < 3 ? E[d * nc + nodes[node]] : B[(d - 3) * nc + nodes[node]]; },
-                  eb);
+      T eb[NF];
+      gather27<NF, T>(w, [&](int node, int d) {
+        return d < 3 ? E[d * nc + nodes[node]] : (d < 6 ? B[(d - 3) * nc + nodes[node]] : NN[nodes[node]]);
+      }, eb);
       const Kick<T> kq = boris_kick<T>(u[0], u[1], u[2], eb[0], eb[1], eb[2], eb[3], eb[4], eb[5], h, hb);
       const T un[3] = {u[0] + kq.dux, u[1] + kq.duy, u[2] + kq.duz};
+      T wn = wv, lost = T(0);
+      if constexpr (LOSS) loss_step<T>(un[0], un[1], un[2], eb[NF - 1], lrate, wv, &wn, &lost);
       if constexpr (deposit) {
-        const T qv[4] = {pf * kq.dux, pf * kq.duy, pf * kq.duz, ef * kq.dg};
+        const T wl = wv * lost;
+        const T qv[4] = {LOSS ? pf * (wn * kq.dux - wl * u[0]) : pf * kq.dux,
+                         LOSS ? pf * (wn * kq.duy - wl * u[1]) : pf * kq.duy,
+                         LOSS ? pf * (wn * kq.duz - wl * u[2]) : pf * kq.duz,
+                         LOSS ? ef * (wn * kq.dg - wl * kq.g0) : ef * kq.dg};
         #pragma unroll
         for (int c = 0; c < 3; ++c)
           #pragma unroll
@@ -753,7 +799,7 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
       T fn[3];
       err |= drift3<T>(k, home, f, xa, un, hn, xn, fn);
       const int64_t j2 = place_overflow(V, trash, err);
-      store_slot<T>(V.out, j2, j2, xn, fn, un, id, hn[0] + k.nx * (hn[1] + k.ny * hn[2]));
+      store_slot<T, LOSS>(V.out, j2, j2, xn, fn, un, wn, id, hn[0] + k.nx * (hn[1] + k.ny * hn[2]));
     }
   }
   if (err) set_status(k.status, err);
@@ -903,7 +949,8 @@ __global__ void __launch_bounds__(kThreads) cells_build_kernel(Packets<T> P, Cel
       }
       jc = j;
     }
-    store_slot<T>(L.buf[0], j, jc, x, f, u, id, key);
+    store_slot<T, false>(L.buf[0], j, jc, x, f, u, T(1), id, key);
+    if (P.w && L.buf[0].w) ((T*)L.buf[0].w)[j] = P.w[i];
   }
 }
 
@@ -943,6 +990,7 @@ __device__ __forceinline__ void copy_out(const Packets<T>& P, const SlotArrays& 
   }
   if constexpr (!is_fp64<T>()) P.cell[o] = cell;
   P.id[o] = S.id[j];
+  if (P.w && S.w) P.w[o] = ((const T*)S.w)[j];
 }
 
 // Every occupied slot of buffer cur -> caller arrays at its prefix-sum offset.
@@ -1014,7 +1062,7 @@ struct Carver {
   }
 };
 
-SlotArrays carve_slots(Carver& cv, int64_t nslots, bool f32, bool with_cell) {
+SlotArrays carve_slots(Carver& cv, int64_t nslots, bool f32, bool with_cell, bool weights) {
   SlotArrays S;
   S.stride = nslots;
   const size_t n = (size_t)nslots;
@@ -1023,10 +1071,11 @@ SlotArrays carve_slots(Carver& cv, int64_t nslots, bool f32, bool with_cell) {
   S.cell = (f32 && with_cell) ? (int32_t*)cv.take(n * sizeof(int32_t)) : nullptr;
   S.u = (void*)cv.take(3 * n * (f32 ? sizeof(float) : sizeof(double)));
   S.id = (int32_t*)cv.take(n * sizeof(int32_t));
+  S.w = weights ? (void*)cv.take(n * (f32 ? sizeof(float) : sizeof(double))) : nullptr;
   return S;
 }
 
-CellLists carve(int nx, int ny, int nz, int64_t np, int precision, uintptr_t base, size_t* bytes) {
+CellLists carve(int nx, int ny, int nz, int64_t np, int precision, bool weights, uintptr_t base, size_t* bytes) {
   CellLists L;
   const int64_t ncells = (int64_t)nx * ny * nz;
   L.ntx = (nx + kCellTile - 1) / kCellTile;
@@ -1058,7 +1107,7 @@ CellLists carve(int nx, int ny, int nz, int64_t np, int precision, uintptr_t bas
   L.tr0 = L.ov0 + L.ocap;
   const int64_t slots = L.tr0 + kTrashSlots;
   for (int b = 0; b < 2; ++b) {
-    L.buf[b] = carve_slots(cv, slots, f32, true);
+    L.buf[b] = carve_slots(cv, slots, f32, true, weights);
     L.bcnt[b] = (int32_t*)cv.take((size_t)ncells * sizeof(int32_t));
     L.icnt[b] = (int32_t*)cv.take((size_t)(L.ntiles * kDirs + 1) * sizeof(int32_t));
   }
@@ -1073,14 +1122,14 @@ CellLists carve(int nx, int ny, int nz, int64_t np, int precision, uintptr_t bas
 
 }  // namespace
 
-size_t cell_list_bytes(int nx, int ny, int nz, int64_t np, int precision) {
+size_t cell_list_bytes(int nx, int ny, int nz, int64_t np, int precision, bool weights) {
   size_t bytes = 0;
-  (void)carve(nx, ny, nz, np, precision, 0, &bytes);
+  (void)carve(nx, ny, nz, np, precision, weights, 0, &bytes);
   return bytes;
 }
 
-CellLists cell_list_carve(int nx, int ny, int nz, int64_t np, int precision, char* base) {
-  return carve(nx, ny, nz, np, precision, (uintptr_t)base, nullptr);
+CellLists cell_list_carve(int nx, int ny, int nz, int64_t np, int precision, bool weights, char* base) {
+  return carve(nx, ny, nz, np, precision, weights, (uintptr_t)base, nullptr);
 }
 
 int64_t cell_list_scan_entries(int nx, int ny, int nz) {
@@ -1101,19 +1150,34 @@ hipError_t launch_cells_build(const Packets<T>& P, CellLists& L, const RunConsts
 }
 
 template <typename T>
-hipError_t launch_cells_step(int shape, CellLists& L, const T* E, const T* B, double* dM, double* dE,
+hipError_t launch_cells_step(int shape, CellLists& L, const T* E, const T* B, const T* NN, double* dM, double* dE,
                              const GasLink& gas, const RunConsts& k, hipStream_t s, hipEvent_t before,
                              hipEvent_t after) {
   const StepView V = step_view(L);
+  if (NN && !(L.buf[0].w && L.buf[1].w)) return hipErrorInvalidValue;
   if (before) (void)hipEventRecord(before, s);
   const dim3 grid((unsigned)L.ntiles), block(kThreads);
+  const bool dep = dM != nullptr, loss = NN != nullptr;
+#define RSOL_CELLS_LAUNCH(M_, D_, L_) \
+  hipLaunchKernelGGL((cells_step_kernel<M_, T, D_, L_>), grid, block, 0, s, V, E, B, NN, dM, dE, k)
   if (shape == kShapeCIC) {
-    if (dM) hipLaunchKernelGGL((cells_step_kernel<2, T, true>), grid, block, 0, s, V, E, B, dM, dE, k);
-    else hipLaunchKernelGGL((cells_step_kernel<2, T, false>), grid, block, 0, s, V, E, B, dM, dE, k);
+    if (loss) {
+      if (dep) RSOL_CELLS_LAUNCH(2, true, true);
+      else RSOL_CELLS_LAUNCH(2, false, true);
+    } else {
+      if (dep) RSOL_CELLS_LAUNCH(2, true, false);
+      else RSOL_CELLS_LAUNCH(2, false, false);
+    }
   } else {
-    if (dM) hipLaunchKernelGGL((cells_step_kernel<3, T, true>), grid, block, 0, s, V, E, B, dM, dE, k);
-    else hipLaunchKernelGGL((cells_step_kernel<3, T, false>), grid, block, 0, s, V, E, B, dM, dE, k);
+    if (loss) {
+      if (dep) RSOL_CELLS_LAUNCH(3, true, true);
+      else RSOL_CELLS_LAUNCH(3, false, true);
+    } else {
+      if (dep) RSOL_CELLS_LAUNCH(3, true, false);
+      else RSOL_CELLS_LAUNCH(3, false, false);
+    }
   }
+#undef RSOL_CELLS_LAUNCH
   if (after) (void)hipEventRecord(after, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -1141,8 +1205,8 @@ hipError_t launch_cells_compact(const Packets<T>& P, CellLists& L, const RunCons
 
 #define RSOL_CELLS_INSTANTIATE(T)                                                                                  \
   template hipError_t launch_cells_build<T>(const Packets<T>&, CellLists&, const RunConsts&, hipStream_t);         \
-  template hipError_t launch_cells_step<T>(int, CellLists&, const T*, const T*, double*, double*, const GasLink&,   \
-                                           const RunConsts&, hipStream_t, hipEvent_t, hipEvent_t);                 \
+  template hipError_t launch_cells_step<T>(int, CellLists&, const T*, const T*, const T*, double*, double*,        \
+                                           const GasLink&, const RunConsts&, hipStream_t, hipEvent_t, hipEvent_t); \
   template hipError_t launch_cells_compact<T>(const Packets<T>&, CellLists&, const RunConsts&, hipStream_t);
 
 RSOL_CELLS_INSTANTIATE(double)

@@ -31,6 +31,7 @@ struct rsol_ctx {
   float* B32;
   char* cells_base;     // cell-list buffers of the default step path
   int32_t* iota;        // 0..np-1: recorded packet indices for the adjoint's sort
+  float* nn32;          // FP32 copy of the nucleon density (FP32 form with RSOL_FLAG_LOSSES)
   // registered caller arrays
   const double* E;
   const double* B;
@@ -38,7 +39,10 @@ struct rsol_ctx {
   float* off;
   void* u;
   int32_t* id;
-  bool have_fields, have_packets, sorted_valid;
+  const double* nn;     // catastrophic losses: nucleon density per cell, packet weights, sigma
+  void* w;
+  double sigma;
+  bool have_fields, have_packets, sorted_valid, have_losses;
   int steps_since_sort;
   Tiling tiling;
   StepPlan plan;
@@ -107,7 +111,8 @@ void timed_end(rsol_ctx* h, std::pair<hipEvent_t, hipEvent_t> pr, bool is_sort) 
 
 bool fp32(const rsol_params& p) { return p.precision == RSOL_FP32; }
 bool naive(const rsol_params& p) { return (p.flags & RSOL_FLAG_NAIVE) != 0; }
-constexpr int32_t kKnownFlags = RSOL_FLAG_KEEP_ORDER | RSOL_FLAG_TILED | RSOL_FLAG_NAIVE;
+bool loss_layout(const rsol_params& p) { return (p.flags & RSOL_FLAG_LOSSES) != 0; }
+constexpr int32_t kKnownFlags = RSOL_FLAG_KEEP_ORDER | RSOL_FLAG_TILED | RSOL_FLAG_NAIVE | RSOL_FLAG_LOSSES;
 
 Tiling tiling_for(const rsol_params& p) {
   const StepPlan pl = plan_step(p.nx, p.ny, p.nz, p.shape, p.precision, p.sort_every, p.courant);
@@ -134,8 +139,9 @@ size_t layout(const rsol_params& p, int64_t np, rsol_ctx* h) {
     e32 = take(sizeof(float) * 3 * (size_t)n_cells(p));
     b32 = take(sizeof(float) * 3 * (size_t)n_cells(p));
   }
-  const size_t cl = take(cell_list_bytes(p.nx, p.ny, p.nz, np, p.precision));
+  const size_t cl = take(cell_list_bytes(p.nx, p.ny, p.nz, np, p.precision, loss_layout(p)));
   const size_t io = take(sizeof(int32_t) * (size_t)np + 64);
+  const size_t n32 = (fp32(p) && loss_layout(p)) ? take(sizeof(float) * (size_t)n_cells(p)) : 0;
   if (h) {
     char* s = h->scratch;
     h->status = (uint32_t*)(s + st);
@@ -146,6 +152,7 @@ size_t layout(const rsol_params& p, int64_t np, rsol_ctx* h) {
     h->B32 = fp32(p) ? (float*)(s + b32) : nullptr;
     h->cells_base = s + cl;
     h->iota = (int32_t*)(s + io);
+    h->nn32 = (fp32(p) && loss_layout(p)) ? (float*)(s + n32) : nullptr;
   }
   return off;
 }
@@ -211,6 +218,7 @@ RunConsts consts(const rsol_ctx* h) {
   }
   // a packet may never cross more than one cell per step; the tiled kernel's halo
   // additionally relies on the Courant bound (at most C cells per step)
+  k.lrate = h->have_losses ? (p.c_tilde / p.c) * h->sigma * p.c * p.dt : 0.0;
   k.max_step = h->plan.max_step;
   k.status = h->status;
   return k;
@@ -231,6 +239,7 @@ Packets<T> caller_packets(const rsol_ctx* h) {
   }
   P.u = (T*)h->u;
   P.id = h->id;
+  P.w = h->have_losses ? (T*)h->w : nullptr;
   return P;
 }
 
@@ -263,6 +272,13 @@ int need(rsol_ctx* h, bool fields, bool packets) {
   return RSOL_OK;
 }
 
+// The tiled path carries no packet weights.
+int losses_path_ok(rsol_ctx* h) {
+  if (h->have_losses && (h->p.flags & RSOL_FLAG_TILED) && !(h->p.flags & RSOL_FLAG_KEEP_ORDER))
+    return fail(h, RSOL_EINVAL, "the tiled path does not carry losses");
+  return RSOL_OK;
+}
+
 template <typename T>
 const T* field_E(const rsol_ctx* h) {
   if constexpr (is_fp64<T>()) return h->E; else return h->E32;
@@ -270,6 +286,12 @@ const T* field_E(const rsol_ctx* h) {
 template <typename T>
 const T* field_B(const rsol_ctx* h) {
   if constexpr (is_fp64<T>()) return h->B; else return h->B32;
+}
+// nucleon density of the loss step, or NULL without losses
+template <typename T>
+const T* field_NN(const rsol_ctx* h) {
+  if (!h->have_losses) return nullptr;
+  if constexpr (is_fp64<T>()) return h->nn; else return h->nn32;
 }
 
 // Copy the permuted packets back over the caller's arrays.
@@ -322,8 +344,8 @@ int do_step_cells(rsol_ctx* h, int32_t nsteps, double* dM, double* dE, const Gas
       pr.first = take_event(h);
       pr.second = take_event(h);
     }
-    RSOL_HIP(h, launch_cells_step<T>(h->p.shape, h->cells, field_E<T>(h), field_B<T>(h), dM, dE, gas, k,
-                                     h->stream, pr.first, pr.second),
+    RSOL_HIP(h, launch_cells_step<T>(h->p.shape, h->cells, field_E<T>(h), field_B<T>(h), field_NN<T>(h), dM, dE,
+                                     gas, k, h->stream, pr.first, pr.second),
              "step (cells)");
     if (pr.first && pr.second) h->ev_step.push_back(pr);
   }
@@ -343,8 +365,8 @@ int do_step(rsol_ctx* h, int32_t nsteps, double* dM, double* dE, const GasLink& 
   for (int32_t s = 0; s < nsteps; ++s) {
     if (global) {
       auto ev = timed_begin(h);
-      RSOL_HIP(h, launch_step_global<T>(h->p.shape, caller_packets<T>(h), field_E<T>(h), field_B<T>(h), dM, dE,
-                                        k, h->stream),
+      RSOL_HIP(h, launch_step_global<T>(h->p.shape, caller_packets<T>(h), field_E<T>(h), field_B<T>(h),
+                                        field_NN<T>(h), dM, dE, k, h->stream),
                "step (global)");
       timed_end(h, ev, false);
       h->sorted_valid = false;
@@ -400,7 +422,7 @@ int rsol_init(const rsol_params* p, int64_t n_particles, void* stream, void* scr
   h->plan = plan_step(p->nx, p->ny, p->nz, p->shape, p->precision, p->sort_every, p->courant);
   h->tiling = make_tiling(p->nx, p->ny, p->nz, h->plan.tx, h->plan.ty, h->plan.tz);
   layout(*p, n_particles, h);
-  h->cells = cell_list_carve(p->nx, p->ny, p->nz, n_particles, p->precision, h->cells_base);
+  h->cells = cell_list_carve(p->nx, p->ny, p->nz, n_particles, p->precision, loss_layout(*p), h->cells_base);
   hipError_t e = launch_fill_u32(h->status, 0u, 4, h->stream);
   if (e != hipSuccess) {
     int rc = hip_fail(nullptr, e, "init status");
@@ -474,6 +496,21 @@ int rsol_set_fields(rsol_handle h, const double* E, const double* B) {
   return RSOL_OK;
 }
 
+int rsol_set_losses(rsol_handle h, double sigma, const double* nn, void* w) {
+  if (int rc = need(h, false, false)) return rc;
+  if (!loss_layout(h->p)) return fail(h, RSOL_ESTATE, "handle created without RSOL_FLAG_LOSSES");
+  if (!(sigma >= 0) || !isfinite(sigma)) return fail(h, RSOL_EINVAL, "sigma must be finite and >= 0");
+  if (!nn || (!w && h->np > 0)) return fail(h, RSOL_EINVAL, "NULL loss array");
+  if (h->p.flags & RSOL_FLAG_TILED && !(h->p.flags & RSOL_FLAG_KEEP_ORDER))
+    return fail(h, RSOL_EINVAL, "the tiled path does not carry losses");
+  h->sigma = sigma;
+  h->nn = nn;
+  h->w = w;
+  if (fp32(h->p)) RSOL_HIP(h, launch_to_fp32(nn, h->nn32, n_cells(h->p), h->stream), "nn to fp32");
+  h->have_losses = true;
+  return RSOL_OK;
+}
+
 int rsol_set_particles(rsol_handle h, void* pos, float* off, void* u, int32_t* id) {
   if (int rc = need(h, false, false)) return rc;
   if (h->np > 0 && (!pos || !u || !id)) return fail(h, RSOL_EINVAL, "NULL packet pointer");
@@ -510,23 +547,28 @@ int rsol_courant_dt(rsol_handle h, double* dt) {
   if (!dt) return fail(h, RSOL_EINVAL, "dt is NULL");
   if (h->np == 0) return fail(h, RSOL_EINVAL, "no packets");
   if (fp32(h->p)) {
-    RSOL_HIP(h, launch_dt_inputs<float>(caller_packets<float>(h), h->B, (int)n_cells(h->p), h->red, h->stream),
+    RSOL_HIP(h, launch_dt_inputs<float>(caller_packets<float>(h), h->B, h->have_losses ? h->nn : nullptr,
+                                        (int)n_cells(h->p), h->red, h->stream),
              "dt inputs");
   } else {
-    RSOL_HIP(h, launch_dt_inputs<double>(caller_packets<double>(h), h->B, (int)n_cells(h->p), h->red, h->stream),
+    RSOL_HIP(h, launch_dt_inputs<double>(caller_packets<double>(h), h->B, h->have_losses ? h->nn : nullptr,
+                                         (int)n_cells(h->p), h->red, h->stream),
              "dt inputs");
   }
-  unsigned long long bits[3];
+  unsigned long long bits[4];
   RSOL_HIP(h, hipMemcpyAsync(bits, h->red, sizeof(bits), hipMemcpyDeviceToHost, h->stream), "dt copy");
   RSOL_HIP(h, hipStreamSynchronize(h->stream), "dt sync");
-  double v[3];
+  double v[4];
   memcpy(v, bits, sizeof(v));
-  const double beta_max = v[0], gamma_min = v[1], b_max = v[2];
+  const double beta_max = v[0], gamma_min = v[1], b_max = v[2], nn_max = v[3];
   const rsol_params& p = h->p;
   double lim = INFINITY;
   if (beta_max > 0) lim = fmin(lim, p.courant * p.dx / (p.c_tilde * beta_max));
   const double omega = (naive(p) ? 1.0 : p.c_tilde / p.c) * fabs(p.qomc) * b_max / gamma_min;
   if (omega > 0) lim = fmin(lim, p.courant / omega);
+  // catastrophic losses (Sec. 4): dt < C N/|dN/dt| with the rate (c_tilde/c) sigma c beta n_n
+  const double lrate = (p.c_tilde / p.c) * h->sigma * p.c * beta_max * nn_max;
+  if (h->have_losses && lrate > 0) lim = fmin(lim, p.courant / lrate);
   if (!isfinite(lim)) return fail(h, RSOL_EINVAL, "timestep unbounded (no motion and no field)");
   *dt = lim;
   return RSOL_OK;
@@ -541,6 +583,7 @@ int rsol_set_dt(rsol_handle h, double dt) {
 
 int rsol_gather(rsol_handle h, void* Ep, void* Bp) {
   if (int rc = need(h, true, true)) return rc;
+  if (h->have_losses) return fail(h, RSOL_EINVAL, "losses registered: the separate phases carry no losses (use rsol_step)");
   if (h->np == 0) return RSOL_OK;
   if (!Ep || !Bp) return fail(h, RSOL_EINVAL, "NULL output");
   if (fp32(h->p))
@@ -554,6 +597,7 @@ int rsol_gather(rsol_handle h, void* Ep, void* Bp) {
 
 int rsol_push(rsol_handle h, const void* Ep, const void* Bp, void* payload) {
   if (int rc = need(h, false, true)) return rc;
+  if (h->have_losses) return fail(h, RSOL_EINVAL, "losses registered: the separate phases carry no losses (use rsol_step)");
   if (h->np == 0) return RSOL_OK;
   if (!Ep || !Bp || !payload) return fail(h, RSOL_EINVAL, "NULL pointer");
   if (!(h->p.dt > 0)) return fail(h, RSOL_ESTATE, "dt not set");
@@ -568,6 +612,7 @@ int rsol_push(rsol_handle h, const void* Ep, const void* Bp, void* payload) {
 
 int rsol_deposit(rsol_handle h, const void* payload, double* dM, double* dE) {
   if (int rc = need(h, false, true)) return rc;
+  if (h->have_losses) return fail(h, RSOL_EINVAL, "losses registered: the separate phases carry no losses (use rsol_step)");
   if (h->np == 0) return RSOL_OK;
   if (!payload || !dM) return fail(h, RSOL_EINVAL, "NULL pointer");
   if (fp32(h->p))
@@ -581,6 +626,7 @@ int rsol_deposit(rsol_handle h, const void* payload, double* dM, double* dE) {
 
 int rsol_drift(rsol_handle h) {
   if (int rc = need(h, false, true)) return rc;
+  if (h->have_losses) return fail(h, RSOL_EINVAL, "losses registered: the separate phases carry no losses (use rsol_step)");
   if (h->np == 0) return RSOL_OK;
   if (!(h->p.dt > 0)) return fail(h, RSOL_ESTATE, "dt not set");
   if (fp32(h->p))
@@ -593,11 +639,13 @@ int rsol_drift(rsol_handle h) {
 
 int rsol_sort(rsol_handle h) {
   if (int rc = need(h, false, true)) return rc;
+  if (h->have_losses) return fail(h, RSOL_EINVAL, "losses registered: packets are re-binned by rsol_step only");
   return fp32(h->p) ? do_sort<float>(h, true) : do_sort<double>(h, true);
 }
 
 int rsol_step(rsol_handle h, int32_t nsteps, double* dM, double* dE) {
   if (int rc = need(h, true, true)) return rc;
+  if (int rc = losses_path_ok(h)) return rc;
   if (nsteps < 0) return fail(h, RSOL_EINVAL, "nsteps < 0");
   if (!(h->p.dt > 0)) return fail(h, RSOL_ESTATE, "dt not set");
   if (!dM && dE) return fail(h, RSOL_EINVAL, "dE without dM");
@@ -608,6 +656,7 @@ int rsol_step(rsol_handle h, int32_t nsteps, double* dM, double* dE) {
 
 int rsol_step_coupled(rsol_handle h, int32_t nsteps, const double* rho, double* mom, double* egas, double* E) {
   if (int rc = need(h, true, true)) return rc;
+  if (int rc = losses_path_ok(h)) return rc;
   if (nsteps < 0) return fail(h, RSOL_EINVAL, "nsteps < 0");
   if (!(h->p.dt > 0)) return fail(h, RSOL_ESTATE, "dt not set");
   if (!rho || !mom || !E) return fail(h, RSOL_EINVAL, "NULL gas pointer");
@@ -647,6 +696,9 @@ int rsol_moments(rsol_handle h, double* rho, double* P, double* e) {
 int rsol_set_flags(rsol_handle h, int32_t flags) {
   if (int rc = need(h, false, false)) return rc;
   if (flags & ~kKnownFlags) return fail(h, RSOL_EINVAL, "unknown flag bits");
+  if ((flags ^ h->p.flags) & RSOL_FLAG_LOSSES) return fail(h, RSOL_EINVAL, "RSOL_FLAG_LOSSES is fixed at rsol_init");
+  if (h->have_losses && (flags & RSOL_FLAG_TILED) && !(flags & RSOL_FLAG_KEEP_ORDER))
+    return fail(h, RSOL_EINVAL, "the tiled path does not carry losses");
   h->p.flags = flags;
   return RSOL_OK;
 }
@@ -659,6 +711,7 @@ size_t rsol_state_bytes(rsol_handle h) {
 int rsol_record_states(rsol_handle h, int32_t nsteps, void* states) {
   if (int rc = need(h, true, true)) return rc;
   if (naive(h->p)) return fail(h, RSOL_EINVAL, "the differentiation form covers the RSOL equations only");
+  if (h->have_losses) return fail(h, RSOL_EINVAL, "the differentiation form carries no losses");
   if (nsteps < 0) return fail(h, RSOL_EINVAL, "nsteps < 0");
   if (!(h->p.dt > 0)) return fail(h, RSOL_ESTATE, "dt not set");
   if (h->np == 0 || nsteps == 0) return RSOL_OK;
@@ -669,11 +722,11 @@ int rsol_record_states(rsol_handle h, int32_t nsteps, void* states) {
     void* at = (char*)states + (size_t)n * slab;
     if (fp32(h->p)) {
       RSOL_HIP(h, launch_record<float>(caller_packets<float>(h), at, h->stream), "record");
-      RSOL_HIP(h, launch_step_global<float>(h->p.shape, caller_packets<float>(h), h->E32, h->B32, nullptr, nullptr, k,
+      RSOL_HIP(h, launch_step_global<float>(h->p.shape, caller_packets<float>(h), h->E32, h->B32, nullptr, nullptr, nullptr, k,
                                             h->stream), "record step");
     } else {
       RSOL_HIP(h, launch_record<double>(caller_packets<double>(h), at, h->stream), "record");
-      RSOL_HIP(h, launch_step_global<double>(h->p.shape, caller_packets<double>(h), h->E, h->B, nullptr, nullptr, k,
+      RSOL_HIP(h, launch_step_global<double>(h->p.shape, caller_packets<double>(h), h->E, h->B, nullptr, nullptr, nullptr, k,
                                              h->stream), "record step");
     }
   }
@@ -685,6 +738,7 @@ int rsol_step_backward(rsol_handle h, int32_t nsteps, const void* states, void* 
                        const double* lam_dM, const double* lam_dE, double* gE, double* gB) {
   if (int rc = need(h, true, true)) return rc;
   if (naive(h->p)) return fail(h, RSOL_EINVAL, "the differentiation form covers the RSOL equations only");
+  if (h->have_losses) return fail(h, RSOL_EINVAL, "the differentiation form carries no losses");
   if (nsteps < 0) return fail(h, RSOL_EINVAL, "nsteps < 0");
   if (!(h->p.dt > 0)) return fail(h, RSOL_ESTATE, "dt not set");
   if (!lam_dM && lam_dE) return fail(h, RSOL_EINVAL, "lam_dE without lam_dM");
@@ -744,6 +798,7 @@ int rsol_moments_backward(rsol_handle h, const double* lam_rho, const double* la
                           void* lam_x, void* lam_u) {
   if (int rc = need(h, false, true)) return rc;
   if (naive(h->p)) return fail(h, RSOL_EINVAL, "the differentiation form covers the RSOL equations only");
+  if (h->have_losses) return fail(h, RSOL_EINVAL, "the differentiation form carries no losses");
   if (h->np == 0) return RSOL_OK;
   if (!lam_x || !lam_u) return fail(h, RSOL_EINVAL, "NULL adjoint array");
   if (fp32(h->p))

@@ -28,6 +28,7 @@ struct SlotArrays {
   void* u;          // momentum, precision type
   int32_t* id;
   int64_t stride;   // slots in the store
+  void* w;          // packet weights, precision type (NULL when the layout carries none)
 };
 
 // Sizes and buffers of the cell-list layout (all in the library's scratch).
@@ -62,22 +63,24 @@ struct CellLists {
   int cur;                // buffer holding the current state
 };
 
-// Scratch bytes the layout needs.
-size_t cell_list_bytes(int nx, int ny, int nz, int64_t np, int precision);
+// Scratch bytes the layout needs (`weights`: the slot stores carry packet weights).
+size_t cell_list_bytes(int nx, int ny, int nz, int64_t np, int precision, bool weights);
 // Carve the layout out of `base` (256-byte aligned, cell_list_bytes long).
-CellLists cell_list_carve(int nx, int ny, int nz, int64_t np, int precision, char* base);
+CellLists cell_list_carve(int nx, int ny, int nz, int64_t np, int precision, bool weights, char* base);
 // Entries of the compaction's prefix sum (cells, tile directions, overflow).
 int64_t cell_list_scan_entries(int nx, int ny, int nz);
 
-// Caller packets -> buffer 0 (counters cleared first).
+// Caller packets -> buffer 0 (counters cleared first); P.w is copied when both P and
+// the layout carry weights.
 template <typename T>
 hipError_t launch_cells_build(const Packets<T>& P, CellLists& L, const RunConsts& k, hipStream_t s);
 // One step: buffer cur -> buffer 1-cur; exchange added into dM/dE if dM != NULL.
 // With gas.rho set (then dM = gas.mom, dE = gas.egas) the kernel that adds the
-// exchange into the grid also refreshes the gas field E.  `before`/`after` (may be
-// NULL) are recorded around the step kernel itself.
+// exchange into the grid also refreshes the gas field E.  NN (nucleon density per
+// cell, precision type) selects the step with catastrophic losses (the layout must
+// carry weights).  `before`/`after` (may be NULL) are recorded around the step kernel.
 template <typename T>
-hipError_t launch_cells_step(int shape, CellLists& L, const T* E, const T* B, double* dM, double* dE,
+hipError_t launch_cells_step(int shape, CellLists& L, const T* E, const T* B, const T* NN, double* dM, double* dE,
                              const GasLink& gas, const RunConsts& k, hipStream_t s, hipEvent_t before,
                              hipEvent_t after);
 // Buffer cur -> caller packets, cell-major (buckets by cell, then inboxes, then overflow).

@@ -37,6 +37,7 @@ struct RunConsts {
   double cdt_dx;     // c_tilde dt / dx
   double pfac;       // gas momentum per unit packet du: -(c/c_tilde) M c / V  [-M c_tilde / V]
   double efac;       // gas energy per unit packet dgamma: -(c/c_tilde) M c^2 / V  [-M c_tilde^2 / V]
+  double lrate;      // catastrophic losses: (c_tilde/c) sigma c dt, the loss exponent per unit beta n_n
   double max_step;   // largest allowed |dx| per step, in cells
   uint32_t* status;  // device status word
 };
@@ -117,6 +118,7 @@ __device__ __forceinline__ void axis_weight_derivs(int home, T f, T dw[M]) {
 template <typename T>
 struct Kick {
   T dux, duy, duz, dg;
+  T g0;  // gamma before the kick
 };
 
 // 1/sqrt(x) and 1/x for x >= 1 (Lorentz factors and 1 + |t|^2): the hardware
@@ -180,7 +182,25 @@ __device__ __forceinline__ Kick<T> boris_kick(T ux, T uy, T uz, T ex, T ey, T ez
   const T q1 = T(1) + (nx * nx + ny * ny + nz * nz);
   const T g0 = q0 * rsqrt_nr<T>(q0), g1 = q1 * rsqrt_nr<T>(q1);
   o.dg = (o.dux * (nx + ux) + o.duy * (ny + uy) + o.duz * (nz + uz)) * rcp_nr<T>(g0 + g1);
+  o.g0 = g0;
   return o;
+}
+
+// Catastrophic losses over one step (Sec. 2, collisional terms): every packet total
+// decays at the reduced rate (c_tilde/c) <sigma v> n_n with <sigma v> = sigma c beta,
+// beta from the new momentum u and n_n at the packet, integrated exactly over the step.
+// With r = lrate beta n_n the packet keeps w exp(-r); *lost = 1 - exp(-r) is formed
+// without cancellation.
+template <typename T>
+__device__ __forceinline__ void loss_step(T ux, T uy, T uz, T nn, T lrate, T w, T* wn, T* lost) {
+  const T uu = ux * ux + uy * uy + uz * uz;
+  const T beta = sqrt(uu) * rsqrt_nr<T>(T(1) + uu);
+  const T r = lrate * beta * nn;
+  T em1;
+  if constexpr (sizeof(T) == 8) em1 = expm1(-r);
+  else em1 = expm1f(-r);
+  *lost = -em1;
+  *wn = w + w * em1;
 }
 
 // Drift length per unit momentum, (c_tilde dt or c_tilde dt / dx) / gamma with

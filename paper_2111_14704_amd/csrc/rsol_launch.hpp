@@ -56,9 +56,10 @@ hipError_t launch_cells_to_positions(const int32_t* cell, const float* off, doub
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s);
 
-// timestep inputs: out[0] = max beta (bits), out[1] = min gamma (bits), out[2] = max |B| (bits)
+// timestep inputs: out[0] = max beta (bits), out[1] = min gamma (bits), out[2] = max |B| (bits),
+// out[3] = max nucleon density (bits; 0 when nn is NULL)
 template <typename T>
-hipError_t launch_dt_inputs(const Packets<T>& P, const double* B, int ncells,
+hipError_t launch_dt_inputs(const Packets<T>& P, const double* B, const double* nn, int ncells,
                             unsigned long long* out, hipStream_t s);
 
 // unfused phases (one thread per packet, any packet order)
@@ -77,9 +78,10 @@ template <typename T>
 hipError_t launch_moments(int shape, const Packets<T>& P, double* rho, double* Pm, double* e,
                           const RunConsts& k, hipStream_t s);
 
-// fused step, one thread per packet with global atomics (any packet order)
+// fused step, one thread per packet with global atomics (any packet order); NN (nucleon
+// density, precision type) selects the step with catastrophic losses (needs P.w)
 template <typename T>
-hipError_t launch_step_global(int shape, const Packets<T>& P, const T* E, const T* B, double* dM,
+hipError_t launch_step_global(int shape, const Packets<T>& P, const T* E, const T* B, const T* NN, double* dM,
                               double* dE, const RunConsts& k, hipStream_t s);
 
 }  // namespace rsol

@@ -21,6 +21,7 @@ struct Packets {
   T* u;
   int32_t* id;
   int64_t np;
+  T* w = nullptr;  // packet weights N_j / N under catastrophic losses, NULL otherwise
 };
 
 template <typename T>

@@ -27,6 +27,7 @@ RSOL_FP64, RSOL_FP32 = 0, 1
 RSOL_FLAG_KEEP_ORDER = 1
 RSOL_FLAG_TILED = 2
 RSOL_FLAG_NAIVE = 4
+RSOL_FLAG_LOSSES = 8
 
 
 class RSOLError(RuntimeError):
@@ -77,6 +78,7 @@ def lib():
             "rsol_sort": (ctypes.c_int, [vp]),
             "rsol_step": (ctypes.c_int, [vp, i32, vp, vp]),
             "rsol_step_coupled": (ctypes.c_int, [vp, i32, vp, vp, vp, vp]),
+            "rsol_set_losses": (ctypes.c_int, [vp, dbl, vp, vp]),
             "rsol_moments": (ctypes.c_int, [vp, vp, vp, vp]),
             "rsol_check": (ctypes.c_int, [vp]),
             "rsol_timing": (ctypes.c_int, [vp, i32]),
@@ -104,7 +106,7 @@ def exported_symbols():
         "rsol_courant_dt", "rsol_set_dt", "rsol_gather", "rsol_push", "rsol_deposit", "rsol_drift",
         "rsol_sort", "rsol_step", "rsol_moments", "rsol_check", "rsol_timing", "rsol_timing_read",
         "rsol_stray_count", "rsol_set_flags", "rsol_state_bytes", "rsol_record_states", "rsol_step_backward",
-        "rsol_moments_backward", "rsol_step_coupled",
+        "rsol_moments_backward", "rsol_step_coupled", "rsol_set_losses",
     ]
 
 
@@ -194,6 +196,10 @@ class Handle:
     def rsol_set_fields(self, E, B):
         self._keep["E"], self._keep["B"] = E, B
         _check(self.h, lib().rsol_set_fields(self.h, _ptr(E), _ptr(B)))
+
+    def rsol_set_losses(self, sigma: float, nn, w):
+        self._keep.update(nn=nn, w=w)
+        _check(self.h, lib().rsol_set_losses(self.h, float(sigma), _ptr(nn), _ptr(w)))
 
     def rsol_set_particles(self, pos, off, u, ids):
         self._keep.update(pos=pos, off=off, u=u, ids=ids)

@@ -68,6 +68,21 @@ class Simulation:
     def step(self, nsteps, dM=None, dE=None):
         self.handle.rsol_step(nsteps, dM, dE)
 
+    def set_losses(self, sigma, nn, w):
+        """Catastrophic losses (needs flags with RSOL_FLAG_LOSSES at construction): nn is the
+        nucleon density per cell (n_cells,), w the initial packet weights (Np,); the weights
+        live in ``self.w`` (packet precision) and follow the packets."""
+        f64 = dict(dtype=torch.float64, device=self.device)
+        self.nn = torch.as_tensor(np.ascontiguousarray(np.asarray(nn).reshape(-1)), **f64)
+        self.w = torch.as_tensor(np.ascontiguousarray(w), dtype=torch.float32 if self.fp32 else torch.float64,
+                                 device=self.device)
+        self.handle.rsol_set_losses(sigma, self.nn, self.w)
+
+    def weights_by_id(self):
+        """Packet weights (float64 numpy) indexed by packet id."""
+        ids = self.ids.cpu().numpy()
+        return self.w.double().cpu().numpy()[np.argsort(ids, kind="stable")]
+
     def step_coupled(self, nsteps, rho, mom, egas=None):
         """nsteps steps coupled to the gas (rho, mom = rho u, egas: float64 device tensors of
         shapes (n_cells,), (3, n_cells), (n_cells,)); mom and egas are updated in place and

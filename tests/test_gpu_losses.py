@@ -1,0 +1,193 @@
+"""Parity of the step with catastrophic losses (rsol_set_losses) with the oracle's
+step_with_losses, through the C ABI, on the cell-list and keep-order paths.
+
+Compared after the run: packet positions, momenta and weights by id, the summed
+exchange and the weighted moments.  Tolerances: FP64 1e-10, FP32 1e-5 (weights
+relative per packet; the rest as in the loss-free parity tests)."""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import make_workload, loss_state
+from tests.helpers import oracle_params, oracle_fields, periodic_distance, rel_l2, max_rel_momentum
+
+pytestmark = pytest.mark.gpu
+
+LOSSES, KEEP_ORDER, TILED = 8, 1, 2
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _gpu(w, nsteps, sigma, nn, wt, flags=0, per_call=None):
+    import torch
+    from paper_2111_14704_amd.sim import Simulation
+    sim = Simulation.from_workload(w, flags=flags | LOSSES)
+    sim.set_losses(sigma, nn, wt)
+    dM, dE = sim.zeros_grid(3), sim.zeros_grid(1)[0]
+    per_call = per_call or nsteps
+    done = 0
+    while done < nsteps:
+        n = min(per_call, nsteps - done)
+        sim.step(n, dM, dE)
+        done += n
+    sim.handle.rsol_check()
+    rho, P, e = sim.moments()
+    torch.cuda.synchronize()
+    x, u = sim.state_by_id()
+    return dict(x=x, u=u, w=sim.weights_by_id(), dM=dM.cpu().numpy(), dE=dE.cpu().numpy(), rho=rho.cpu().numpy(),
+                P=P.cpu().numpy(), e=e.cpu().numpy(), dt=sim.dt), sim
+
+
+def _oracle(w, nsteps, sigma, nn, wt, dt):
+    p = oracle_params(w, dt=dt)
+    E, B = oracle_fields(w)
+    r = oracle.rollout_with_losses(w.x, w.u, wt, E, B, nn, sigma, p, nsteps)
+    r["rho"], r["P"], r["e"] = oracle.moments(r["x"], r["u"], p, w=r["w"])
+    r["p"] = p
+    return r
+
+
+def _compare(w, got, ref, tol, label):
+    p = ref["p"]
+    dist = float(np.max(periodic_distance(got["x"], ref["x"], w.box)))
+    g = np.sqrt(1 + np.sum(w.u ** 2, axis=0)).mean()
+    escale = (p.c / p.c_tilde) * p.mass * p.c ** 2 * g * w.ppc * math.sqrt(w.n_cells) / p.volume
+    errs = dict(x=dist / max(w.box), u=max_rel_momentum(got["u"], ref["u"]),
+                w=float(np.max(np.abs(got["w"] - ref["w"]) / ref["w"])),
+                dM=rel_l2(got["dM"], ref["dM_sum"]), dE_abs=float(np.linalg.norm(got["dE"] - ref["dE_sum"]) / escale),
+                rho=rel_l2(got["rho"], ref["rho"]), P=rel_l2(got["P"], ref["P"]), e=rel_l2(got["e"], ref["e"]))
+    lost = 1.0 - float(ref["w"].mean())
+    _say(f"{label}: lost {lost:.3f}, x_cells={dist / w.dx:.2e}, " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    for k, v in errs.items():
+        assert v <= tol, (label, k, v)
+    assert dist / w.dx <= (1e-10 if tol <= 1e-10 else 1e-4), (label, "x_cells", dist / w.dx)
+    return lost
+
+
+@pytest.mark.parametrize("flags", [0, KEEP_ORDER], ids=["cells", "global"])
+def test_losses_config1_fp64(flags):
+    """Workload 1 (16^3, 8 ppc, CIC) with the seeded nucleon density and a 4-cell mean free
+    path, 20 steps in one call."""
+    w = make_workload(1)
+    nn, sigma, wt = loss_state(w)
+    _say(f"losses config1 fp64 flags={flags}")
+    got, _ = _gpu(w, 20, 10 * sigma, nn, wt, flags)
+    lost = _compare(w, got, _oracle(w, 20, 10 * sigma, nn, wt, got["dt"]), 1e-10, f"losses config1 flags={flags}")
+    assert lost > 0.05
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+@pytest.mark.parametrize("flags,per_call", [(0, 20), (0, 3), (KEEP_ORDER, 20)], ids=["cells", "cells-3-per-call",
+                                                                                    "global"])
+def test_losses_alfven_ragged(precision, tol, flags, per_call):
+    """Workload 2 recipe on a ragged 10^3 grid (TSC, 4 ppc), 20 steps, packets with
+    non-uniform starting weights."""
+    w = make_workload(2, n=10, ppc=4, precision=precision)
+    nn, sigma, _ = loss_state(w)
+    wt = np.random.default_rng(5).uniform(0.5, 1.0, w.n_particles)
+    _say(f"losses alfven n=10 {precision} flags={flags} per_call={per_call}")
+    got, _ = _gpu(w, 20, 10 * sigma, nn, wt, flags, per_call)
+    _compare(w, got, _oracle(w, 20, 10 * sigma, nn, wt, got["dt"]), tol,
+             f"losses alfven {precision} flags={flags} per_call={per_call}")
+
+
+def test_zero_cross_section_matches_the_loss_free_step():
+    """sigma = 0 with losses registered runs the loss kernel variant; packets and weights
+    come out bit for bit as in the loss-free step, and the exchange equal up to the order
+    of its LDS atomic sums."""
+    import torch
+    from paper_2111_14704_amd.sim import Simulation
+    w = make_workload(2, n=10, ppc=4)
+    nn, _, wt = loss_state(w)
+    _say("losses sigma=0 vs loss-free")
+    got, _ = _gpu(w, 10, 0.0, nn, wt)
+    sim = Simulation.from_workload(w)
+    dM, dE = sim.zeros_grid(3), sim.zeros_grid(1)[0]
+    sim.step(10, dM, dE)
+    torch.cuda.synchronize()
+    x, u = sim.state_by_id()
+    assert np.array_equal(got["x"], x) and np.array_equal(got["u"], u)
+    assert rel_l2(got["dM"], dM.cpu().numpy()) <= 1e-13 and rel_l2(got["dE"], dE.cpu().numpy()) <= 1e-13
+    assert np.all(got["w"] == 1.0)
+
+
+def test_losses_timestep_matches_oracle():
+    """rsol_courant_dt adds the loss limit of Sec. 4 (binding for a large cross-section)."""
+    from paper_2111_14704_amd.sim import Simulation
+    w = make_workload(2, n=16, ppc=4)
+    nn, sigma, wt = loss_state(w)
+    _say("losses dt")
+    sim = Simulation.from_workload(w, flags=LOSSES, dt=1e-3)
+    for s in (sigma, 1000 * sigma):
+        sim.set_losses(s, nn, wt)
+        want = oracle.courant_dt(w.u, w.B, w.c, w.c_tilde, w.qomc, w.dx, w.courant, sigma=s, nn=nn)
+        assert sim.handle.rsol_courant_dt() == pytest.approx(want, rel=1e-15)
+    p_free = oracle.courant_dt(w.u, w.B, w.c, w.c_tilde, w.qomc, w.dx, w.courant)
+    assert want < 0.5 * p_free
+
+
+def test_losses_conservation_and_sample_at_full_size():
+    """Workload 2 at full size (64^3 x 64 ppc, 16.8M packets, TSC, FP64) with a 4-cell mean
+    free path, 10 steps on the cell-list path: the momentum and energy totals with weights
+    are unchanged up to rounding while packets lose weight, and 2048 packets sampled by id
+    match the oracle run one by one."""
+    import torch
+    w = make_workload(2)
+    nn, sigma, wt = loss_state(w)
+    sigma *= 10
+    nsteps = 10
+    _say(f"losses full-size workload 2, {w.n_particles} packets")
+    got, sim = _gpu(w, nsteps, sigma, nn, wt)
+    p = oracle_params(w, dt=got["dt"])
+    zero3, zero = np.zeros((3, w.n_cells)), np.zeros(w.n_cells)
+    P0, E0 = oracle.conserved_totals(w.u, zero3, zero, p, w=wt)
+    P1, E1 = oracle.conserved_totals(got["u"], got["dM"], got["dE"], p, w=got["w"])
+    k = p.c / p.c_tilde
+    scale_p = k * p.mass * p.c * np.abs(w.u).sum()
+    scale_e = k * p.mass * p.c ** 2 * oracle.lorentz_gamma(w.u).sum()
+    res_p, res_e = np.abs(P1 - P0) / scale_p, abs(E1 - E0) / scale_e
+    lost = 1.0 - float(got["w"].mean())
+    _say(f"momentum residual {res_p}, energy residual {res_e:.2e}, lost {lost:.3f}")
+    assert np.all(res_p <= 1e-12) and res_e <= 1e-12 and lost > 0.01
+    pick = np.sort(np.random.default_rng(99).choice(w.n_particles, 2048, replace=False))
+    E, B = oracle_fields(w)
+    r = oracle.rollout_with_losses(w.x[:, pick], w.u[:, pick], wt[pick], E, B, nn, sigma, p, nsteps)
+    dist = float(np.max(periodic_distance(got["x"][:, pick], r["x"], w.box)))
+    eu = max_rel_momentum(got["u"][:, pick], r["u"])
+    ew = float(np.max(np.abs(got["w"][pick] - r["w"]) / r["w"]))
+    _say(f"sample: x_cells={dist:.2e} e_u={eu:.2e} e_w={ew:.2e}")
+    assert dist / w.dx <= 1e-10 and eu <= 1e-10 and ew <= 1e-10
+
+
+def test_losses_rejected_where_not_carried():
+    """With losses registered: the tiled path, rsol_sort, the separate phases and the
+    differentiation form refuse (RSOL_EINVAL); the flag is fixed at creation; a handle
+    created without it refuses rsol_set_losses (RSOL_ESTATE)."""
+    import torch
+    from paper_2111_14704_amd.rsol import RSOLError
+    from paper_2111_14704_amd.sim import Simulation
+    w = make_workload(1, n=8, ppc=1)
+    nn, sigma, wt = loss_state(w)
+    _say("losses rejections")
+    sim = Simulation.from_workload(w, flags=LOSSES)
+    sim.set_losses(sigma, nn, wt)
+    h = sim.handle
+    Ep = torch.empty((3, w.n_particles), dtype=torch.float64, device=sim.device)
+    states = torch.empty(h.rsol_state_bytes(), dtype=torch.uint8, device=sim.device)
+    for call in (lambda: h.rsol_sort(), lambda: h.rsol_gather(Ep, Ep.clone()), lambda: h.rsol_drift(),
+                 lambda: h.rsol_record_states(1, states), lambda: h.rsol_set_flags(LOSSES | TILED),
+                 lambda: h.rsol_set_flags(0)):
+        with pytest.raises(RSOLError) as ei:
+            call()
+        assert ei.value.code == -1
+    plain = Simulation.from_workload(w)
+    with pytest.raises(RSOLError) as ei:
+        plain.set_losses(sigma, nn, wt)
+    assert ei.value.code == -2
