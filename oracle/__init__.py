@@ -20,5 +20,5 @@ from .pic import (  # noqa: F401
     Params, electric_field, courant_dt, shape_weights, gather, deposit, boris_kick,
     exchange, drift, wrap, moments, step, rollout, lorentz_gamma, coupled_step, coupled_rollout,
     conserved_totals, naive_constants, rsol_constants, mode_constants, loss_factor, exchange_weighted,
-    step_with_losses, rollout_with_losses,
+    step_with_losses, rollout_with_losses, vay_kick, hc_kick, kick,
 )

@@ -32,6 +32,7 @@ class Params:
     dt: float
     mass: float         # packet mass weight M_j = N_j <m_s>
     naive: bool = False  # naive substitution of c by c_tilde (contrast mode, see naive_constants)
+    pusher: str = "boris"  # momentum update: "boris", "vay" or "hc" (Higuera-Cary)
 
     @property
     def n_cells(self):
@@ -159,6 +160,58 @@ def boris_kick(u, Ep, Bp, h, h_b=None):
     return uplus + h * Ep
 
 
+def _implicit_gamma(v, tau):
+    """Lorentz factor after the magnetic rotation of the Vay and Higuera-Cary schemes for
+    the vector v being rotated: the positive root of
+    gamma^4 - sigma gamma^2 - (tau.tau + (v.tau)^2) = 0, sigma = 1 + v.v - tau.tau."""
+    tt = tau[0] * tau[0] + tau[1] * tau[1] + tau[2] * tau[2]
+    vt = v[0] * tau[0] + v[1] * tau[1] + v[2] * tau[2]
+    sig = 1.0 + v[0] * v[0] + v[1] * v[1] + v[2] * v[2] - tt
+    return np.sqrt(0.5 * (sig + np.sqrt(sig * sig + 4.0 * (tt + vt * vt))))
+
+
+def vay_kick(u, Ep, Bp, h, h_b):
+    """The relativistic pusher of Vay (Phys. Plasmas 15, 056701, 2008) for
+    du/dt = (2h/dt) E + (2h_b/dt) beta x B: u' = u + 2h E + h_b (u/gamma) x B; tau = h_b B;
+    the new gamma solves the quartic of the implicit velocity average; t = tau/gamma,
+    s = 1/(1 + t.t), u_new = s [u' + (u'.t) t + u' x t].  A particle in the force-free
+    E x B drift keeps its momentum exactly."""
+    g = lorentz_gamma(u)
+    up = u + 2.0 * h * Ep + h_b * np.cross(u / g, Bp, axis=0)
+    tau = h_b * Bp
+    gn = _implicit_gamma(up, tau)
+    t = tau / gn
+    s = 1.0 / (1.0 + t[0] * t[0] + t[1] * t[1] + t[2] * t[2])
+    upt = up[0] * t[0] + up[1] * t[1] + up[2] * t[2]
+    return s * (up + upt * t + np.cross(up, t, axis=0))
+
+
+def hc_kick(u, Ep, Bp, h, h_b):
+    """The relativistic pusher of Higuera and Cary (Phys. Plasmas 24, 052104, 2017) for the
+    same equation: half electric kick u- = u + h E; the rotation uses the Lorentz factor of
+    the implicit velocity average (the quartic of the Vay scheme, applied to u-), t = tau/gamma,
+    s = 1/(1 + t.t), u+ = s [u- + (u-.t) t + u- x t]; then u_new = u+ + h E + u+ x t."""
+    um = u + h * Ep
+    tau = h_b * Bp
+    gn = _implicit_gamma(um, tau)
+    t = tau / gn
+    s = 1.0 / (1.0 + t[0] * t[0] + t[1] * t[1] + t[2] * t[2])
+    umt = um[0] * t[0] + um[1] * t[1] + um[2] * t[2]
+    uplus = s * (um + umt * t + np.cross(um, t, axis=0))
+    return uplus + h * Ep + np.cross(uplus, t, axis=0)
+
+
+def kick(u, Ep, Bp, h, h_b, pusher="boris"):
+    """The momentum update of one step with the chosen pusher."""
+    if pusher == "boris":
+        return boris_kick(u, Ep, Bp, h, h_b)
+    if pusher == "vay":
+        return vay_kick(u, Ep, Bp, h, h_b)
+    if pusher == "hc":
+        return hc_kick(u, Ep, Bp, h, h_b)
+    raise ValueError(f"unknown pusher {pusher}")
+
+
 def naive_constants(p: Params):
     """Constants of the naive substitution of c by c_tilde (the prior approach the
     paper contrasts with, Sec. 1 and Sec. 5): the Lorentz factor is formed with
@@ -235,7 +288,7 @@ def step_with_losses(x, u, w, E, B, nn, sigma, p: Params):
     Bp = gather(B, idx, wts)
     nn_p = gather(np.asarray(nn)[None], idx, wts)[0]
     h_e, h_b, _, _ = mode_constants(p)
-    u_new = boris_kick(u, Ep, Bp, h_e, h_b)
+    u_new = kick(u, Ep, Bp, h_e, h_b, p.pusher)
     w_new = w * loss_factor(u_new, nn_p, sigma, p)
     dP, dEn = exchange_weighted(u, w, u_new, w_new, p)
     dep = deposit(idx, wts, np.concatenate([dP, dEn[None]]), p.n_cells) / p.volume
@@ -296,7 +349,7 @@ def step(x, u, E, B, p: Params):
     Ep = gather(E, idx, w)
     Bp = gather(B, idx, w)
     h_e, h_b, _, _ = mode_constants(p)
-    u_new = boris_kick(u, Ep, Bp, h_e, h_b)
+    u_new = kick(u, Ep, Bp, h_e, h_b, p.pusher)
     dP, dEn = exchange(u, u_new, p)
     dep = deposit(idx, w, np.concatenate([dP, dEn[None]]), p.n_cells) / p.volume
     x_new = drift(x, u_new, p)

@@ -234,10 +234,8 @@ def _analytic_field(x, c):
     return E, Bv
 
 
-def test_second_order_convergence_to_continuous_rsol_equations():
-    """Kick + drift converge at second order to the continuous packet equations of Sec. 2:
-    dx/dt = c_tilde u/gamma and d(u)/dt = (c_tilde/c)(q/(m c))[E + beta x B] (Eq. (11)),
-    solved independently by scipy's DOP853 at tight tolerance."""
+def _convergence_ratios(pusher):
+    """Position errors at T against the DOP853 solution for 200, 400, 800 steps."""
     c, qomc, ratio = 1000.0, 4000.0, 10.0
     ct = c / ratio
 
@@ -263,12 +261,21 @@ def test_second_order_convergence_to_continuous_rsol_equations():
         h = 0.5 * (ct / c) * qomc * dt
         for _ in range(nsteps):
             E, Bv = _analytic_field(x[:, 0], c)
-            u = oracle.boris_kick(u, E[:, None], Bv[:, None], h)
+            u = oracle.pic.kick(u, E[:, None], Bv[:, None], h, h, pusher)
             x = oracle.drift(x, u, p)
         d = x[:, 0] - xT
         d -= 64.0 * np.round(d / 64.0)
         errs.append(np.linalg.norm(d))
-    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    return errs[0] / errs[1], errs[1] / errs[2], errs
+
+
+@pytest.mark.parametrize("pusher", ["boris", "vay", "hc"])
+def test_second_order_convergence_to_continuous_rsol_equations(pusher):
+    """Kick + drift converge at second order to the continuous packet equations of Sec. 2:
+    dx/dt = c_tilde u/gamma and d(u)/dt = (c_tilde/c)(q/(m c))[E + beta x B] (Eq. (11)),
+    solved independently by scipy's DOP853 at tight tolerance; for the Boris, Vay and
+    Higuera-Cary momentum updates alike."""
+    r1, r2, errs = _convergence_ratios(pusher)
     assert 3.7 < r1 < 4.3 and 3.7 < r2 < 4.3, errs
 
 
@@ -854,6 +861,106 @@ def test_planted_mistakes_fail_the_loss_pins(monkeypatch):
         # the removed packet totals not handed to the gas
         m.setattr(pic, "exchange_weighted", lambda u0, w0, u1, w1, p: tuple(w1 * v for v in pic.exchange(u0, u1, p)))
         assert _loss_conservation_residual()[0] > 100.0
+
+
+# ---------------------------------------------------------------- alternative pushers (Vay, Higuera-Cary)
+
+def _with_pusher(p, pusher):
+    return oracle.Params(p.nx, p.ny, p.nz, p.dx, p.shape, p.c, p.c_tilde, p.qomc, p.dt, p.mass, pusher=pusher)
+
+
+def _force_free_drift(pusher, ratio=10.0):
+    """Largest momentum change over 200 steps of a packet in the force-free E x B state
+    E + beta x B = 0 (beta = u_gas/c for E = -(u_gas/c) x B): the Vay and Higuera-Cary
+    schemes keep it exactly by construction, Boris only up to the gamma change over its
+    half kick.  Returned relative to |u|."""
+    n, U, c = 8, 1.0, 1000.0
+    E, B = _uniform_fields(n, B=(1.0, 0.0, 0.0), u_gas=(0.0, U, 0.0))
+    beta = U / c
+    u0 = np.array([[0.0], [beta / math.sqrt(1 - beta ** 2)], [0.0]])
+    p = _with_pusher(_uniform_params(n, "cic", ratio, dt=0.3 / (c / ratio)), pusher)
+    _, us = _run_single(np.array([[4.0], [4.0], [4.0]]), u0, E, B, p, 200)
+    return float(np.max(np.abs(us - us[0]))) / float(u0[1, 0])
+
+
+def test_vay_and_higuera_cary_keep_the_exb_drift_exactly():
+    for pusher in ("vay", "hc"):
+        assert _force_free_drift(pusher) < 1e-13, pusher
+    assert _force_free_drift("boris") > 1e-8
+
+
+def _pure_b_rotation_errors(pusher):
+    """In uniform B: |u| is kept (B does no work).  Vay rotates by Boris' angle
+    2 atan(h_b B/gamma).  Higuera-Cary rotates by 2 atan(h_b B/gamma_a), where gamma_a is the
+    Lorentz factor of the average of the momenta before and after the step (its implicit
+    velocity average), checked from the states themselves."""
+    n = 16
+    E, B = _uniform_fields(n)
+    u0 = np.array([[3.0], [8.0], [-2.0]])
+    p = _with_pusher(_uniform_params(n, "cic", 10.0, dt=2e-3), pusher)
+    _, us = _run_single(np.array([[8.0], [8.0], [8.0]]), u0, E, B, p, 40)
+    nrm = np.linalg.norm(us, axis=1)
+    hb = 0.5 * (p.c_tilde / p.c) * p.qomc * p.dt
+    ang = np.arctan2(us[:-1, 1] * us[1:, 2] - us[:-1, 2] * us[1:, 1], us[:-1, 1] * us[1:, 1] + us[:-1, 2] * us[1:, 2])
+    if pusher == "hc":
+        avg = 0.5 * (us[:-1] + us[1:])
+        ga = np.sqrt(1.0 + np.sum(avg * avg, axis=1))
+        want = -2.0 * np.arctan(hb * 1.0 / ga)
+    else:
+        want = -2.0 * np.arctan(hb * 1.0 / np.sqrt(1.0 + nrm[:-1] ** 2))
+    return max(float(np.max(np.abs(nrm - nrm[0]))) / nrm[0], float(np.max(np.abs(ang - want) / np.abs(want))))
+
+
+@pytest.mark.parametrize("pusher", ["vay", "hc"])
+def test_pusher_rotation_in_pure_b(pusher):
+    assert _pure_b_rotation_errors(pusher) < 1e-12
+
+
+@pytest.mark.parametrize("pusher", ["vay", "hc"])
+def test_pusher_step_space_invariance(pusher):
+    """The RSOL stays a rescaling of time with any pusher: the per-step maps depend on
+    c_tilde dt alone (the c_tilde/c of Eq. (11) enters only through h = (c_tilde/c) qomc dt/2)."""
+    base = None
+    for ratio in (1.0, 10.0, 100.0):
+        w = make_workload(2, n=8, ppc=2, ratio=ratio)
+        p = _with_pusher(oracle_params(w), pusher)
+        E, B = oracle_fields(w)
+        r = oracle.rollout(w.x, w.u, E, B, p, 30)
+        if base is None:
+            base = r
+            continue
+        assert np.max(np.abs(r["x"] - base["x"])) < 1e-11
+        assert np.max(np.abs(r["u"] - base["u"]) / np.linalg.norm(base["u"], axis=0)) < 1e-12
+
+
+def test_planted_mistakes_fail_the_pusher_pins(monkeypatch):
+    """Plausible mistakes in the Vay and Higuera-Cary updates each fail a pusher pin."""
+    pic = oracle.pic
+    good_gamma = pic._implicit_gamma
+    with monkeypatch.context() as m:
+        # Vay without the magnetic half of its first stage, u' = u + 2 h E
+        def vay_short(u, E, B, h, hb):
+            up = u + 2.0 * h * E
+            tau = hb * B
+            t = tau / good_gamma(up, tau)
+            sv = 1.0 / (1.0 + np.sum(t * t, axis=0))
+            return sv * (up + np.sum(up * t, axis=0) * t + np.cross(up, t, axis=0))
+        m.setattr(pic, "vay_kick", vay_short)
+        assert _pure_b_rotation_errors("vay") > 1e-6 and _force_free_drift("vay") > 1e-8
+    with monkeypatch.context() as m:
+        # rotation with gamma of the rotated vector itself (the Boris choice) instead of the implicit root
+        m.setattr(pic, "_implicit_gamma", lambda v, tau: np.sqrt(1.0 + v[0] ** 2 + v[1] ** 2 + v[2] ** 2))
+        assert _force_free_drift("hc") > 1e-8 and _force_free_drift("vay") > 1e-8
+    with monkeypatch.context() as m:
+        # Higuera-Cary without the final u+ x t
+        def hc_short(u, E, B, h, hb):
+            um = u + h * E
+            tau = hb * B
+            t = tau / good_gamma(um, tau)
+            sv = 1.0 / (1.0 + np.sum(t * t, axis=0))
+            return sv * (um + np.sum(um * t, axis=0) * t + np.cross(um, t, axis=0)) + h * E
+        m.setattr(pic, "hc_kick", hc_short)
+        assert _pure_b_rotation_errors("hc") > 1e-6
 
 
 # ---------------------------------------------------------------- reference gradients
