@@ -17,7 +17,8 @@ duration against the 8 TB/s HBM3E peak; "coupled" = the FP64 step coupled to the
 workload's gas (exchange into the gas momentum and energy, E rebuilt every step);
 "naive" = the FP64 step in the naive-substitution contrast mode (same kernels,
 naive constants); "losses" = the FP64 step with catastrophic losses (packet weights
-in the cell lists, nucleon density gathered by the step);
+in the cell lists, nucleon density gathered by the step); "pushers" = the FP64 step
+with the Vay and Higuera-Cary momentum updates;
 "backward" = the differentiation form;
 "cpu_baseline" = the CPU oracle timed on a bounded sample of the same workload.
 """
@@ -210,6 +211,7 @@ def main():
     ap.add_argument("--no-coupled", action="store_true", help="skip the run coupled to the gas")
     ap.add_argument("--no-naive", action="store_true", help="skip the naive-substitution contrast run")
     ap.add_argument("--no-losses", action="store_true", help="skip the run with catastrophic losses")
+    ap.add_argument("--no-pushers", action="store_true", help="skip the Vay and Higuera-Cary pusher runs")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="first run one plain device copy of BYTES bytes (a known-size reference for HBM counters)")
     args = ap.parse_args()
@@ -262,6 +264,14 @@ def main():
         rl = time_path(w, "fp64", args.steps, args.warmup, args.sort_every, losses=True)
         print(f"[bench] losses fp64 {rl['value']:.3e} upd/s, kernel {rl['kernel_ms']:.3f} ms", file=sys.stderr,
               flush=True)
+    rp = {}
+    if not args.no_pushers:
+        from paper_2111_14704_amd.rsol import RSOL_FLAG_PUSHER_HC, RSOL_FLAG_PUSHER_VAY
+        for name, fl in (("vay", RSOL_FLAG_PUSHER_VAY), ("hc", RSOL_FLAG_PUSHER_HC)):
+            r = time_path(w, "fp64", args.steps, args.warmup, args.sort_every, flags=fl)
+            rp[name] = dict(value=r["value"], ms_per_step=r["ms_per_step"], kernel_ms=r["kernel_ms"], dtype="f64")
+            print(f"[bench] {name} pusher fp64 {r['value']:.3e} upd/s, kernel {r['kernel_ms']:.3f} ms",
+                  file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w)
@@ -289,6 +299,8 @@ def main():
                                dtype="f64", overhead_vs_static=rc["ms_per_step"] / r64["ms_per_step"] - 1.0)
     if rn:
         line["naive"] = dict(value=rn["value"], ms_per_step=rn["ms_per_step"], kernel_ms=rn["kernel_ms"], dtype="f64")
+    if rp:
+        line["pushers"] = rp
     if rl:
         line["losses"] = dict(value=rl["value"], ms_per_step=rl["ms_per_step"], kernel_ms=rl["kernel_ms"], dtype="f64",
                               overhead_vs_static=rl["ms_per_step"] / r64["ms_per_step"] - 1.0)

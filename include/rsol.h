@@ -90,6 +90,13 @@ typedef struct rsol_params {
 #define RSOL_FLAG_LOSSES 8      /* set at rsol_init: the scratch layout carries a weight per
                                    packet so that rsol_set_losses can switch on catastrophic
                                    losses; fixed for the life of the handle                   */
+#define RSOL_FLAG_PUSHER_VAY 16 /* momentum update by the pusher of Vay (Phys. Plasmas 15,
+                                   056701, 2008) instead of Boris, for the same Eq. (11) and
+                                   the same half kicks; keeps the force-free E x B drift
+                                   exactly.  Cell-list and keep-order paths and rsol_push; the
+                                   tiled path and the differentiation form refuse it.        */
+#define RSOL_FLAG_PUSHER_HC 32  /* the same with the pusher of Higuera and Cary (Phys. Plasmas
+                                   24, 052104, 2017); at most one pusher flag.               */
 
 typedef struct rsol_ctx* rsol_handle;
 

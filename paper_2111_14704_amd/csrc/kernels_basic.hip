@@ -195,15 +195,15 @@ __global__ void gather_kernel(Packets<T> P, const T* __restrict__ E, const T* __
   }
 }
 
-// A5: kick u in place; payload = (du_x, du_y, du_z, dgamma)
-template <typename T>
+// A5: kick u in place with pusher PUSH; payload = (du_x, du_y, du_z, dgamma)
+template <typename T, int PUSH>
 __global__ void push_kernel(Packets<T> P, const T* __restrict__ Ep, const T* __restrict__ Bp,
                             T* __restrict__ payload, RunConsts k) {
   const T h = (T)k.h, hb = (T)k.hb;
   const int64_t np = P.np;
   for (int64_t i = gtid(); i < np; i += gstride()) {
     const T ux = P.u[i], uy = P.u[np + i], uz = P.u[2 * np + i];
-    const Kick<T> q = boris_kick<T>(ux, uy, uz, Ep[i], Ep[np + i], Ep[2 * np + i],
+    const Kick<T> q = kick<PUSH, T>(ux, uy, uz, Ep[i], Ep[np + i], Ep[2 * np + i],
                                     Bp[i], Bp[np + i], Bp[2 * np + i], h, hb);
     P.u[i] = ux + q.dux;
     P.u[np + i] = uy + q.duy;
@@ -341,7 +341,7 @@ __global__ void moments_kernel(Packets<T> P, double* __restrict__ rho, double* _
 // Fused step with global atomics: gather at x^n, kick, exchange deposit at x^n, drift.
 // LOSS: also gather the nucleon density NN, reduce the packet weight (catastrophic
 // losses) and deposit the change of the weighted packet totals.
-template <int M, typename T, bool LOSS>
+template <int M, typename T, bool LOSS, int PUSH>
 __global__ void __launch_bounds__(kBlock) step_global_kernel(Packets<T> P, const T* __restrict__ E,
                                                              const T* __restrict__ B, const T* __restrict__ NN,
                                                              double* __restrict__ dM, double* __restrict__ dE,
@@ -373,7 +373,7 @@ __global__ void __launch_bounds__(kBlock) step_global_kernel(Packets<T> P, const
       }
     }
     const T ux = P.u[i], uy = P.u[np + i], uz = P.u[2 * np + i];
-    const Kick<T> q = boris_kick<T>(ux, uy, uz, e[0], e[1], e[2], b[0], b[1], b[2], h, hb);
+    const Kick<T> q = kick<PUSH, T>(ux, uy, uz, e[0], e[1], e[2], b[0], b[1], b[2], h, hb);
     const T nux = ux + q.dux, nuy = uy + q.duy, nuz = uz + q.duz;
     P.u[i] = nux;
     P.u[np + i] = nuy;
@@ -480,7 +480,10 @@ hipError_t launch_gather(int shape, const Packets<T>& P, const T* E, const T* B,
 template <typename T>
 hipError_t launch_push(const Packets<T>& P, const T* Ep, const T* Bp, T* payload, const RunConsts& k,
                        hipStream_t s) {
-  hipLaunchKernelGGL(push_kernel<T>, dim3(grid_for(P.np)), dim3(kBlock), 0, s, P, Ep, Bp, payload, k);
+  const dim3 g(grid_for(P.np)), b(kBlock);
+  if (k.pusher == kPushVay) hipLaunchKernelGGL((push_kernel<T, kPushVay>), g, b, 0, s, P, Ep, Bp, payload, k);
+  else if (k.pusher == kPushHC) hipLaunchKernelGGL((push_kernel<T, kPushHC>), g, b, 0, s, P, Ep, Bp, payload, k);
+  else hipLaunchKernelGGL((push_kernel<T, kPushBoris>), g, b, 0, s, P, Ep, Bp, payload, k);
   return hipGetLastError();
 }
 
@@ -510,17 +513,28 @@ hipError_t launch_moments(int shape, const Packets<T>& P, double* rho, double* P
   return hipGetLastError();
 }
 
+template <int M, typename T, bool L>
+void step_global_variant(const Packets<T>& P, const T* E, const T* B, const T* NN, double* dM, double* dE,
+                         const RunConsts& k, hipStream_t s) {
+  const dim3 g(grid_for(P.np)), b(kBlock);
+  if (k.pusher == kPushVay)
+    hipLaunchKernelGGL((step_global_kernel<M, T, L, kPushVay>), g, b, 0, s, P, E, B, NN, dM, dE, k);
+  else if (k.pusher == kPushHC)
+    hipLaunchKernelGGL((step_global_kernel<M, T, L, kPushHC>), g, b, 0, s, P, E, B, NN, dM, dE, k);
+  else
+    hipLaunchKernelGGL((step_global_kernel<M, T, L, kPushBoris>), g, b, 0, s, P, E, B, NN, dM, dE, k);
+}
+
 template <typename T>
 hipError_t launch_step_global(int shape, const Packets<T>& P, const T* E, const T* B, const T* NN, double* dM,
                               double* dE, const RunConsts& k, hipStream_t s) {
   if (NN && !P.w) return hipErrorInvalidValue;
-  const dim3 g(grid_for(P.np)), b(kBlock);
   if (shape == kShapeCIC) {
-    if (NN) hipLaunchKernelGGL((step_global_kernel<2, T, true>), g, b, 0, s, P, E, B, NN, dM, dE, k);
-    else hipLaunchKernelGGL((step_global_kernel<2, T, false>), g, b, 0, s, P, E, B, NN, dM, dE, k);
+    if (NN) step_global_variant<2, T, true>(P, E, B, NN, dM, dE, k, s);
+    else step_global_variant<2, T, false>(P, E, B, NN, dM, dE, k, s);
   } else {
-    if (NN) hipLaunchKernelGGL((step_global_kernel<3, T, true>), g, b, 0, s, P, E, B, NN, dM, dE, k);
-    else hipLaunchKernelGGL((step_global_kernel<3, T, false>), g, b, 0, s, P, E, B, NN, dM, dE, k);
+    if (NN) step_global_variant<3, T, true>(P, E, B, NN, dM, dE, k, s);
+    else step_global_variant<3, T, false>(P, E, B, NN, dM, dE, k, s);
   }
   return hipGetLastError();
 }

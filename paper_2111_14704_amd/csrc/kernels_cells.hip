@@ -308,8 +308,9 @@ __device__ __forceinline__ uint32_t drift3(const RunConsts& k, const int home[3]
 
 // LOSS: catastrophic losses.  The tile stages the nucleon density NN as a seventh
 // field, the quad's lane 3 (idle in the field gather otherwise) gathers it, and the
-// packet weight travels with the packet through the slot stores.
-template <int M, typename T, bool DEP, bool LOSS>
+// packet weight travels with the packet through the slot stores.  PUSH: the momentum
+// update (Boris, Vay or Higuera-Cary).
+template <int M, typename T, bool DEP, bool LOSS, int PUSH>
 __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const T* __restrict__ E,
                                                               const T* __restrict__ B, const T* __restrict__ NN,
                                                               double* __restrict__ dM, double* __restrict__ dE,
@@ -564,7 +565,7 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
       }
 
       // kick (Eq. (11))
-      const Kick<T> kq = boris_kick<T>(u[0], u[1], u[2], eb[0], eb[1], eb[2], eb[3], eb[4], eb[5], h, hb);
+      const Kick<T> kq = kick<PUSH, T>(u[0], u[1], u[2], eb[0], eb[1], eb[2], eb[3], eb[4], eb[5], h, hb);
       const T un[3] = {u[0] + kq.dux, u[1] + kq.duy, u[2] + kq.duz};
       // losses: weight update; the exchange becomes the change of the weighted totals,
       // wn du - w lost u (momentum) and wn dgamma - w lost gamma (energy)
@@ -658,7 +659,7 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
         const int a = node % 3, b = (node / 3) % 3, c = node / 9;
         return Fs[d][(bx + a) + kRegionEdge * ((by + b) + kRegionEdge * (bz + c))];
       }, eb);
-      const Kick<T> kq = boris_kick<T>(u[0], u[1], u[2], eb[0], eb[1], eb[2], eb[3], eb[4], eb[5], h, hb);
+      const Kick<T> kq = kick<PUSH, T>(u[0], u[1], u[2], eb[0], eb[1], eb[2], eb[3], eb[4], eb[5], h, hb);
       const T un[3] = {u[0] + kq.dux, u[1] + kq.duy, u[2] + kq.duz};
       T wn = wv, lost = T(0);
       if constexpr (LOSS) loss_step<T>(un[0], un[1], un[2], eb[NF - 1], lrate, wv, &wn, &lost);
@@ -769,7 +770,7 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
       gather27<NF, T>(w, [&](int node, int d) {
         return d < 3 ? E[d * nc + nodes[node]] : (d < 6 ? B[(d - 3) * nc + nodes[node]] : NN[nodes[node]]);
       }, eb);
-      const Kick<T> kq = boris_kick<T>(u[0], u[1], u[2], eb[0], eb[1], eb[2], eb[3], eb[4], eb[5], h, hb);
+      const Kick<T> kq = kick<PUSH, T>(u[0], u[1], u[2], eb[0], eb[1], eb[2], eb[3], eb[4], eb[5], h, hb);
       const T un[3] = {u[0] + kq.dux, u[1] + kq.duy, u[2] + kq.duz};
       T wn = wv, lost = T(0);
       if constexpr (LOSS) loss_step<T>(un[0], un[1], un[2], eb[NF - 1], lrate, wv, &wn, &lost);
@@ -1149,6 +1150,19 @@ hipError_t launch_cells_build(const Packets<T>& P, CellLists& L, const RunConsts
   return hipGetLastError();
 }
 
+// One launch of the step kernel for the run's pusher.
+template <int M, typename T, bool D, bool L>
+void launch_cells_variant(const StepView& V, const T* E, const T* B, const T* NN, double* dM, double* dE,
+                          const RunConsts& k, hipStream_t s) {
+  const dim3 grid((unsigned)V.ntiles), block(kThreads);
+  if (k.pusher == kPushVay)
+    hipLaunchKernelGGL((cells_step_kernel<M, T, D, L, kPushVay>), grid, block, 0, s, V, E, B, NN, dM, dE, k);
+  else if (k.pusher == kPushHC)
+    hipLaunchKernelGGL((cells_step_kernel<M, T, D, L, kPushHC>), grid, block, 0, s, V, E, B, NN, dM, dE, k);
+  else
+    hipLaunchKernelGGL((cells_step_kernel<M, T, D, L, kPushBoris>), grid, block, 0, s, V, E, B, NN, dM, dE, k);
+}
+
 template <typename T>
 hipError_t launch_cells_step(int shape, CellLists& L, const T* E, const T* B, const T* NN, double* dM, double* dE,
                              const GasLink& gas, const RunConsts& k, hipStream_t s, hipEvent_t before,
@@ -1156,28 +1170,24 @@ hipError_t launch_cells_step(int shape, CellLists& L, const T* E, const T* B, co
   const StepView V = step_view(L);
   if (NN && !(L.buf[0].w && L.buf[1].w)) return hipErrorInvalidValue;
   if (before) (void)hipEventRecord(before, s);
-  const dim3 grid((unsigned)L.ntiles), block(kThreads);
   const bool dep = dM != nullptr, loss = NN != nullptr;
-#define RSOL_CELLS_LAUNCH(M_, D_, L_) \
-  hipLaunchKernelGGL((cells_step_kernel<M_, T, D_, L_>), grid, block, 0, s, V, E, B, NN, dM, dE, k)
   if (shape == kShapeCIC) {
     if (loss) {
-      if (dep) RSOL_CELLS_LAUNCH(2, true, true);
-      else RSOL_CELLS_LAUNCH(2, false, true);
+      if (dep) launch_cells_variant<2, T, true, true>(V, E, B, NN, dM, dE, k, s);
+      else launch_cells_variant<2, T, false, true>(V, E, B, NN, dM, dE, k, s);
     } else {
-      if (dep) RSOL_CELLS_LAUNCH(2, true, false);
-      else RSOL_CELLS_LAUNCH(2, false, false);
+      if (dep) launch_cells_variant<2, T, true, false>(V, E, B, NN, dM, dE, k, s);
+      else launch_cells_variant<2, T, false, false>(V, E, B, NN, dM, dE, k, s);
     }
   } else {
     if (loss) {
-      if (dep) RSOL_CELLS_LAUNCH(3, true, true);
-      else RSOL_CELLS_LAUNCH(3, false, true);
+      if (dep) launch_cells_variant<3, T, true, true>(V, E, B, NN, dM, dE, k, s);
+      else launch_cells_variant<3, T, false, true>(V, E, B, NN, dM, dE, k, s);
     } else {
-      if (dep) RSOL_CELLS_LAUNCH(3, true, false);
-      else RSOL_CELLS_LAUNCH(3, false, false);
+      if (dep) launch_cells_variant<3, T, true, false>(V, E, B, NN, dM, dE, k, s);
+      else launch_cells_variant<3, T, false, false>(V, E, B, NN, dM, dE, k, s);
     }
   }
-#undef RSOL_CELLS_LAUNCH
   if (after) (void)hipEventRecord(after, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

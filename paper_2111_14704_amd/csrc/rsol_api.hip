@@ -112,7 +112,18 @@ void timed_end(rsol_ctx* h, std::pair<hipEvent_t, hipEvent_t> pr, bool is_sort) 
 bool fp32(const rsol_params& p) { return p.precision == RSOL_FP32; }
 bool naive(const rsol_params& p) { return (p.flags & RSOL_FLAG_NAIVE) != 0; }
 bool loss_layout(const rsol_params& p) { return (p.flags & RSOL_FLAG_LOSSES) != 0; }
-constexpr int32_t kKnownFlags = RSOL_FLAG_KEEP_ORDER | RSOL_FLAG_TILED | RSOL_FLAG_NAIVE | RSOL_FLAG_LOSSES;
+constexpr int32_t kKnownFlags = RSOL_FLAG_KEEP_ORDER | RSOL_FLAG_TILED | RSOL_FLAG_NAIVE | RSOL_FLAG_LOSSES |
+                                RSOL_FLAG_PUSHER_VAY | RSOL_FLAG_PUSHER_HC;
+int pusher_of(int32_t flags) {
+  return (flags & RSOL_FLAG_PUSHER_VAY) ? kPushVay : (flags & RSOL_FLAG_PUSHER_HC) ? kPushHC : kPushBoris;
+}
+bool tiled_path(int32_t flags) { return (flags & RSOL_FLAG_TILED) && !(flags & RSOL_FLAG_KEEP_ORDER); }
+// Flag combinations no path serves; empty when the flags are usable.
+std::string flag_conflict(int32_t flags) {
+  if ((flags & RSOL_FLAG_PUSHER_VAY) && (flags & RSOL_FLAG_PUSHER_HC)) return "choose one pusher flag";
+  if (tiled_path(flags) && pusher_of(flags) != kPushBoris) return "the tiled path runs the Boris pusher only";
+  return "";
+}
 
 Tiling tiling_for(const rsol_params& p) {
   const StepPlan pl = plan_step(p.nx, p.ny, p.nz, p.shape, p.precision, p.sort_every, p.courant);
@@ -166,6 +177,7 @@ std::string validate(const rsol_params* p, int64_t np) {
   if (p->sort_every < 1 || p->sort_every > 8) return "sort_every must be in 1..8";
   if (p->reserved != 0) return "reserved must be 0";
   if (p->flags & ~kKnownFlags) return "unknown flag bits";
+  if (!flag_conflict(p->flags).empty()) return flag_conflict(p->flags);
   if (!(p->dx > 0)) return "dx must be > 0";
   if (!(p->c > 0) || !(p->c_tilde > 0) || p->c_tilde > p->c) return "need 0 < c_tilde <= c";
   if (!isfinite(p->qomc)) return "qomc must be finite";
@@ -219,6 +231,7 @@ RunConsts consts(const rsol_ctx* h) {
   // a packet may never cross more than one cell per step; the tiled kernel's halo
   // additionally relies on the Courant bound (at most C cells per step)
   k.lrate = h->have_losses ? (p.c_tilde / p.c) * h->sigma * p.c * p.dt : 0.0;
+  k.pusher = pusher_of(p.flags);
   k.max_step = h->plan.max_step;
   k.status = h->status;
   return k;
@@ -696,6 +709,7 @@ int rsol_moments(rsol_handle h, double* rho, double* P, double* e) {
 int rsol_set_flags(rsol_handle h, int32_t flags) {
   if (int rc = need(h, false, false)) return rc;
   if (flags & ~kKnownFlags) return fail(h, RSOL_EINVAL, "unknown flag bits");
+  if (!flag_conflict(flags).empty()) return fail(h, RSOL_EINVAL, flag_conflict(flags));
   if ((flags ^ h->p.flags) & RSOL_FLAG_LOSSES) return fail(h, RSOL_EINVAL, "RSOL_FLAG_LOSSES is fixed at rsol_init");
   if (h->have_losses && (flags & RSOL_FLAG_TILED) && !(flags & RSOL_FLAG_KEEP_ORDER))
     return fail(h, RSOL_EINVAL, "the tiled path does not carry losses");
@@ -711,6 +725,7 @@ size_t rsol_state_bytes(rsol_handle h) {
 int rsol_record_states(rsol_handle h, int32_t nsteps, void* states) {
   if (int rc = need(h, true, true)) return rc;
   if (naive(h->p)) return fail(h, RSOL_EINVAL, "the differentiation form covers the RSOL equations only");
+  if (pusher_of(h->p.flags) != kPushBoris) return fail(h, RSOL_EINVAL, "the differentiation form is the Boris pusher's");
   if (h->have_losses) return fail(h, RSOL_EINVAL, "the differentiation form carries no losses");
   if (nsteps < 0) return fail(h, RSOL_EINVAL, "nsteps < 0");
   if (!(h->p.dt > 0)) return fail(h, RSOL_ESTATE, "dt not set");
@@ -738,6 +753,7 @@ int rsol_step_backward(rsol_handle h, int32_t nsteps, const void* states, void* 
                        const double* lam_dM, const double* lam_dE, double* gE, double* gB) {
   if (int rc = need(h, true, true)) return rc;
   if (naive(h->p)) return fail(h, RSOL_EINVAL, "the differentiation form covers the RSOL equations only");
+  if (pusher_of(h->p.flags) != kPushBoris) return fail(h, RSOL_EINVAL, "the differentiation form is the Boris pusher's");
   if (h->have_losses) return fail(h, RSOL_EINVAL, "the differentiation form carries no losses");
   if (nsteps < 0) return fail(h, RSOL_EINVAL, "nsteps < 0");
   if (!(h->p.dt > 0)) return fail(h, RSOL_ESTATE, "dt not set");
@@ -798,6 +814,7 @@ int rsol_moments_backward(rsol_handle h, const double* lam_rho, const double* la
                           void* lam_x, void* lam_u) {
   if (int rc = need(h, false, true)) return rc;
   if (naive(h->p)) return fail(h, RSOL_EINVAL, "the differentiation form covers the RSOL equations only");
+  if (pusher_of(h->p.flags) != kPushBoris) return fail(h, RSOL_EINVAL, "the differentiation form is the Boris pusher's");
   if (h->have_losses) return fail(h, RSOL_EINVAL, "the differentiation form carries no losses");
   if (h->np == 0) return RSOL_OK;
   if (!lam_x || !lam_u) return fail(h, RSOL_EINVAL, "NULL adjoint array");

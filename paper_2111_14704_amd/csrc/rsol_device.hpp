@@ -38,6 +38,7 @@ struct RunConsts {
   double pfac;       // gas momentum per unit packet du: -(c/c_tilde) M c / V  [-M c_tilde / V]
   double efac;       // gas energy per unit packet dgamma: -(c/c_tilde) M c^2 / V  [-M c_tilde^2 / V]
   double lrate;      // catastrophic losses: (c_tilde/c) sigma c dt, the loss exponent per unit beta n_n
+  int pusher;        // momentum update: kPushBoris, kPushVay or kPushHC
   double max_step;   // largest allowed |dx| per step, in cells
   uint32_t* status;  // device status word
 };
@@ -184,6 +185,90 @@ __device__ __forceinline__ Kick<T> boris_kick(T ux, T uy, T uz, T ex, T ey, T ez
   o.dg = (o.dux * (nx + ux) + o.duy * (ny + uy) + o.duz * (nz + uz)) * rcp_nr<T>(g0 + g1);
   o.g0 = g0;
   return o;
+}
+
+// Momentum updates other than Boris, for the same equation du/dt = (2h/dt) E +
+// (2hb/dt) beta x B: the pushers of Vay (Phys. Plasmas 15, 056701, 2008) and of Higuera
+// and Cary (Phys. Plasmas 24, 052104, 2017).  Both rotate with the Lorentz factor of an
+// implicit velocity average, so a packet in the force-free E x B drift keeps its
+// momentum exactly.
+constexpr int kPushBoris = 0;
+constexpr int kPushVay = 1;
+constexpr int kPushHC = 2;
+
+// Lorentz factor of the rotation for the vector v and tau = hb B: the positive root of
+// g^4 - sigma g^2 - (tau.tau + (v.tau)^2) = 0 with sigma = 1 + v.v - tau.tau.
+template <typename T>
+__device__ __forceinline__ T implicit_gamma(T vx, T vy, T vz, T tx, T ty, T tz) {
+  const T tt = tx * tx + ty * ty + tz * tz;
+  const T vt = vx * tx + vy * ty + vz * tz;
+  const T sig = T(1) + (vx * vx + vy * vy + vz * vz) - tt;
+  return sqrt(T(0.5) * (sig + sqrt(sig * sig + T(4) * (tt + vt * vt))));
+}
+
+// s [v + (v.t) t + v x t] with s = 1/(1 + t.t): the rotation step of both schemes.
+template <typename T>
+__device__ __forceinline__ void implicit_rotate(T vx, T vy, T vz, T tx, T ty, T tz, T& ox, T& oy, T& oz) {
+  const T s = rcp_nr<T>(T(1) + (tx * tx + ty * ty + tz * tz));
+  const T vt = vx * tx + vy * ty + vz * tz;
+  ox = s * (vx + vt * tx + (vy * tz - vz * ty));
+  oy = s * (vy + vt * ty + (vz * tx - vx * tz));
+  oz = s * (vz + vt * tz + (vx * ty - vy * tx));
+}
+
+// du = u_new - u and dgamma = du . (u_new + u) / (gamma_new + gamma) of a finished update.
+template <typename T>
+__device__ __forceinline__ Kick<T> kick_from(T ux, T uy, T uz, T nx, T ny, T nz, T g0) {
+  Kick<T> o;
+  o.dux = nx - ux;
+  o.duy = ny - uy;
+  o.duz = nz - uz;
+  const T q1 = T(1) + (nx * nx + ny * ny + nz * nz);
+  const T g1 = q1 * rsqrt_nr<T>(q1);
+  o.dg = (o.dux * (nx + ux) + o.duy * (ny + uy) + o.duz * (nz + uz)) * rcp_nr<T>(g0 + g1);
+  o.g0 = g0;
+  return o;
+}
+
+// Vay: u' = u + 2h E + hb (u/gamma) x B, then the implicit rotation of u' about tau = hb B.
+template <typename T>
+__device__ __forceinline__ Kick<T> vay_kick(T ux, T uy, T uz, T ex, T ey, T ez, T bx, T by, T bz, T h, T hb) {
+  const T q0 = T(1) + (ux * ux + uy * uy + uz * uz);
+  const T ig0 = rsqrt_nr<T>(q0);
+  const T k = hb * ig0;
+  const T px = ux + (h + h) * ex + k * (uy * bz - uz * by);
+  const T py = uy + (h + h) * ey + k * (uz * bx - ux * bz);
+  const T pz = uz + (h + h) * ez + k * (ux * by - uy * bx);
+  const T tx0 = hb * bx, ty0 = hb * by, tz0 = hb * bz;
+  const T ign = rcp_nr<T>(implicit_gamma<T>(px, py, pz, tx0, ty0, tz0));
+  T nx, ny, nz;
+  implicit_rotate<T>(px, py, pz, tx0 * ign, ty0 * ign, tz0 * ign, nx, ny, nz);
+  return kick_from<T>(ux, uy, uz, nx, ny, nz, q0 * ig0);
+}
+
+// Higuera-Cary: u- = u + h E, implicit rotation of u- to u+, u_new = u+ + h E + u+ x t.
+template <typename T>
+__device__ __forceinline__ Kick<T> hc_kick(T ux, T uy, T uz, T ex, T ey, T ez, T bx, T by, T bz, T h, T hb) {
+  const T q0 = T(1) + (ux * ux + uy * uy + uz * uz);
+  const T g0 = q0 * rsqrt_nr<T>(q0);
+  const T mx = ux + h * ex, my = uy + h * ey, mz = uz + h * ez;
+  const T tx0 = hb * bx, ty0 = hb * by, tz0 = hb * bz;
+  const T ign = rcp_nr<T>(implicit_gamma<T>(mx, my, mz, tx0, ty0, tz0));
+  const T tx = tx0 * ign, ty = ty0 * ign, tz = tz0 * ign;
+  T px, py, pz;
+  implicit_rotate<T>(mx, my, mz, tx, ty, tz, px, py, pz);
+  const T nx = px + h * ex + (py * tz - pz * ty);
+  const T ny = py + h * ey + (pz * tx - px * tz);
+  const T nz = pz + h * ez + (px * ty - py * tx);
+  return kick_from<T>(ux, uy, uz, nx, ny, nz, g0);
+}
+
+// The momentum update of pusher P.
+template <int P, typename T>
+__device__ __forceinline__ Kick<T> kick(T ux, T uy, T uz, T ex, T ey, T ez, T bx, T by, T bz, T h, T hb) {
+  if constexpr (P == kPushVay) return vay_kick<T>(ux, uy, uz, ex, ey, ez, bx, by, bz, h, hb);
+  else if constexpr (P == kPushHC) return hc_kick<T>(ux, uy, uz, ex, ey, ez, bx, by, bz, h, hb);
+  else return boris_kick<T>(ux, uy, uz, ex, ey, ez, bx, by, bz, h, hb);
 }
 
 // Catastrophic losses over one step (Sec. 2, collisional terms): every packet total

@@ -28,6 +28,8 @@ RSOL_FLAG_KEEP_ORDER = 1
 RSOL_FLAG_TILED = 2
 RSOL_FLAG_NAIVE = 4
 RSOL_FLAG_LOSSES = 8
+RSOL_FLAG_PUSHER_VAY = 16
+RSOL_FLAG_PUSHER_HC = 32
 
 
 class RSOLError(RuntimeError):
