@@ -44,6 +44,14 @@ __device__ __host__ __forceinline__ int wrapm(int i, int n) {
   return i < 0 ? i + n : i;
 }
 
+// Index of a cell one step can reach, i in [-n, 2n), wrapped into [0, n) with selects
+// (no integer division); anything further out (a flagged runaway step) is clamped.
+__device__ __forceinline__ int wrap_near(int i, int n) {
+  i = i >= n ? i - n : i;
+  i = i < 0 ? i + n : i;
+  return min(max(i, 0), n - 1);
+}
+
 // Per-lane strides (elements) of the quad loop's LDS exchange areas: 12 weights + 4
 // exchange values, and 4 x 2 partial sums, padded so that the 16 quads of a wave
 // (and the lanes of a wave) start on distinct 16-byte bank groups.
@@ -232,14 +240,16 @@ __device__ __forceinline__ int tile_step(int t, int tt, int n) {
 // overflow slot).  *bucket tells whether the slot is a bucket slot.
 __device__ __forceinline__ int64_t place(const StepView& V, int ttx, int tty, int ttz, int* cntB, int* cntD,
                                          const int* sDcap, const int* sDoff, const int h[3], bool* bucket) {
-  const int tx = h[0] / kCellTile, ty = h[1] / kCellTile, tz = h[2] / kCellTile;
+  // h is a wrapped cell index (non-negative): tile and cell in tile by shifts and masks
+  const int tx = (int)((unsigned)h[0] / kCellTile), ty = (int)((unsigned)h[1] / kCellTile),
+            tz = (int)((unsigned)h[2] / kCellTile);
   const int sx = tile_step(tx, ttx, V.ntx), sy = tile_step(ty, tty, V.nty), sz = tile_step(tz, ttz, V.ntz);
   *bucket = false;
   if (sx > 1 || sy > 1 || sz > 1) return -1;
   const int dir = (sx + 1) + 3 * ((sy + 1) + 3 * (sz + 1));
   if (dir == kSelfDir) {
-    const int local =
-        (h[0] - tx * kCellTile) + kCellTile * ((h[1] - ty * kCellTile) + kCellTile * (h[2] - tz * kCellTile));
+    const int local = (int)((unsigned)h[0] % kCellTile) +
+                      kCellTile * ((int)((unsigned)h[1] % kCellTile) + kCellTile * (int)((unsigned)h[2] % kCellTile));
     const int slot = atomicAdd(&cntB[local], 1);
     if (slot < V.cap) {
       *bucket = true;
@@ -276,14 +286,26 @@ __device__ __forceinline__ uint32_t drift3(const RunConsts& k, const int home[3]
   const int n3[3] = {k.nx, k.ny, k.nz};
   if constexpr (is_fp64<T>()) {
     const double L3[3] = {k.Lx, k.Ly, k.Lz};
+    // periodic wrap with selects (a step moves less than one box length); one rare
+    // branch takes what is still outside [0, L) (a flagged runaway or non-finite step)
+    bool out = false;
     #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const double st = s * un[d];
       bad |= fabs(st) > k.max_step * k.dx;
-      xn[d] = wrap_coord(xa[d] + st, L3[d]);
-      h[d] = wrapm((int)floor(xn[d] * k.inv_dx), n3[d]);
+      double y = xa[d] + st;
+      y = y < 0.0 ? y + L3[d] : y;
+      y = y >= L3[d] ? y - L3[d] : y;
+      out |= !(y >= 0.0 && y < L3[d]);
+      xn[d] = y;
       fn[d] = 0;
     }
+    if (out) {
+      #pragma unroll
+      for (int d = 0; d < 3; ++d) xn[d] = wrap_coord(xn[d], L3[d]);
+    }
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) h[d] = wrap_near((int)floor(xn[d] * k.inv_dx), n3[d]);
   } else {
     #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -297,7 +319,7 @@ __device__ __forceinline__ uint32_t drift3(const RunConsts& k, const int home[3]
         fo = 0.0f;
         hd += 1;
       }
-      h[d] = wrapm(hd, n3[d]);
+      h[d] = wrap_near(hd, n3[d]);
       fn[d] = fo;
       xn[d] = 0.0;
     }
