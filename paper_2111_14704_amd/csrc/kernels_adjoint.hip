@@ -166,7 +166,7 @@ struct GlobalAccess {
   }
 };
 
-constexpr int kAdjRegion = 216;  // region cells of a 4x4x4 tile with a one-cell halo
+constexpr int kAdjRegion = 512;  // region cells: a 4x4x4 tile with a two-cell halo
 
 template <typename T>
 struct TileAccess {
@@ -376,14 +376,20 @@ __global__ void __launch_bounds__(kBlock) step_backward_kernel(const void* __res
   }
 }
 
-// Reverse of one step with the packets grouped by tile (the step's starting state
-// counting-sorted into `S`, S.id = the packets' indices in the recorded order): each
-// workgroup takes one part of one tile's packets, stages the fields of the tile and
-// its halo in LDS, accumulates dL/dE, dL/dB there, and adds the region to the grid
-// with one atomic per node and component.
+// Reverse of one step with the packets grouped by tile.  `order` lists the packets
+// (their indices in the recorded order) tile by tile, `offsets` the first entry of each
+// tile (a counting sort of a recorded state of this step or of a step up to a few steps
+// later).  Each workgroup takes one part of one tile's packets, stages the fields of the
+// tile plus a halo of `halo` cells in LDS, accumulates dL/dE, dL/dB there and adds the
+// region to the grid with one atomic per node and component.  A packet reads its state
+// from the step's slab through `order`; one whose stencil leaves the region (it moved
+// further than the halo allows since the sort) is appended to `spill` (count in
+// spill[0], packet indices after it) for step_backward_list_kernel.
 template <int M, typename T>
-__global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> S, const int32_t* __restrict__ offsets,
-                                                                     Tiling tl, int parts, T* __restrict__ lam_x,
+__global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> slab, const int32_t* __restrict__ order,
+                                                                     const int32_t* __restrict__ offsets, Tiling tl,
+                                                                     int halo, int parts, int32_t* __restrict__ spill,
+                                                                     T* __restrict__ lam_x,
                                                                      T* __restrict__ lam_u, const T* __restrict__ E,
                                                                      const T* __restrict__ B,
                                                                      const double* __restrict__ lam_dM,
@@ -396,10 +402,12 @@ __global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> 
   const int64_t tile = blockIdx.x / parts;
   const int part = blockIdx.x - (int)(tile * parts);
   const int ttx = (int)(tile % tl.ntx), tty = (int)((tile / tl.ntx) % tl.nty), ttz = (int)(tile / ((int64_t)tl.ntx * tl.nty));
-  const int ox = ttx * tl.tx - 1, oy = tty * tl.ty - 1, oz = ttz * tl.tz - 1;
-  const int rx = tl.tx + 2, ry = tl.ty + 2, rz = tl.tz + 2;
+  const int t0[3] = {ttx * tl.tx, tty * tl.ty, ttz * tl.tz};
+  const int ox = t0[0] - halo, oy = t0[1] - halo, oz = t0[2] - halo;
+  const int rx = tl.tx + 2 * halo, ry = tl.ty + 2 * halo, rz = tl.tz + 2 * halo;
+  const int rext[3] = {rx, ry, rz};
   const int rc = rx * ry * rz;
-  const int64_t nc = k.ncells, np = S.np;
+  const int64_t nc = k.ncells, np = slab.np;
   const bool ld = lam_dM != nullptr;
   for (int r = threadIdx.x; r < rc; r += blockDim.x) {
     const int ax = r % rx, ay = (r / rx) % ry, az = r / (rx * ry);
@@ -418,40 +426,38 @@ __global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> 
     for (int d = 0; d < 6; ++d) Gs[d * kAdjRegion + r] = 0.0;
   }
   __syncthreads();
-  TileAccess<T> acc{Fs, ld ? Ls : nullptr, Gs, ox, oy, oz, rx, ry};
+  const TileAccess<T> acc{Fs, ld ? Ls : nullptr, Gs, ox, oy, oz, rx, ry};
   const int64_t b0 = offsets[tile * tl.cells_per_tile], b1 = offsets[(tile + 1) * tl.cells_per_tile];
   const int64_t len = b1 - b0;
   const int64_t j0 = b0 + len * part / parts, j1 = b0 + len * (part + 1) / parts;
   const int n3[3] = {k.nx, k.ny, k.nz};
   for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+    const int64_t i = order[j];
     int home[3];
     T f[3], u0a[3];
-    if constexpr (is_fp64<T>()) {
-      #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const double q = S.x[d * np + j] * k.inv_dx;
-        const double fl = floor(q);
-        home[d] = wrapn((int)fl, n3[d]);  // the sort's home cell
-        f[d] = q - fl;
-        u0a[d] = S.u[d * np + j];
-      }
-    } else {
-      const int c = S.cell[j];
-      const int nxy = k.nx * k.ny;
-      home[2] = c / nxy;
-      const int rr = c - home[2] * nxy;
-      home[1] = rr / k.nx;
-      home[0] = rr - home[1] * k.nx;
-      #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        f[d] = S.off[d * np + j];
-        u0a[d] = S.u[d * np + j];
-      }
+    load_position(slab, i, k, home, f);
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) u0a[d] = slab.u[d * np + i];
+    // home in the tile's unwrapped frame; the stencil spans home-1 .. home+1
+    bool inside = true;
+    int hu[3];
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int hw = wrapn(home[d], n3[d]);
+      int delta = hw - t0[d];
+      if (2 * delta >= n3[d]) delta -= n3[d];
+      else if (2 * delta < -n3[d]) delta += n3[d];
+      hu[d] = t0[d] + delta;
+      const int rel = delta + halo;
+      inside &= rel >= 1 && rel <= rext[d] - 2;
     }
-    const int64_t i = S.id[j];
+    if (!inside) {
+      spill[1 + atomicAdd(&spill[0], 1)] = (int32_t)i;
+      continue;
+    }
     T lx[3] = {lam_x[i], lam_x[np + i], lam_x[2 * np + i]};
     T lu[3] = {lam_u[i], lam_u[np + i], lam_u[2 * np + i]};
-    packet_backward<M, T>(acc, home, f, u0a, lx, lu, k);
+    packet_backward<M, T>(acc, hu, f, u0a, lx, lu, k);
     #pragma unroll
     for (int d = 0; d < 3; ++d) {
       lam_x[d * np + i] = lx[d];
@@ -470,6 +476,39 @@ __global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> 
     }
   }
 }
+
+// The packets a tiled reverse step left out (spill[0] of them, indices after it), with
+// the global fields and atomics.
+template <int M, typename T>
+__global__ void __launch_bounds__(kBlock) step_backward_list_kernel(Packets<T> slab, const int32_t* __restrict__ spill,
+                                                                    T* __restrict__ lam_x, T* __restrict__ lam_u,
+                                                                    const T* __restrict__ E, const T* __restrict__ B,
+                                                                    const double* __restrict__ lam_dM,
+                                                                    const double* __restrict__ lam_dE,
+                                                                    double* __restrict__ gE, double* __restrict__ gB,
+                                                                    RunConsts k) {
+  const int64_t np = slab.np;
+  const int n = spill[0];
+  const GlobalAccess<T> gacc{E, B, lam_dM, lam_dE, gE, gB, (int64_t)k.ncells, k.nx, k.ny, k.nz};
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    const int64_t i = spill[1 + t];
+    int home[3];
+    T f[3], u0a[3];
+    load_position(slab, i, k, home, f);
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) u0a[d] = slab.u[d * np + i];
+    T lx[3] = {lam_x[i], lam_x[np + i], lam_x[2 * np + i]};
+    T lu[3] = {lam_u[i], lam_u[np + i], lam_u[2 * np + i]};
+    packet_backward<M, T>(gacc, home, f, u0a, lx, lu, k);
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      lam_x[d * np + i] = lx[d];
+      lam_u[d * np + i] = lu[d];
+    }
+  }
+}
+
+__global__ void clear_count_kernel(int32_t* c) { c[0] = 0; }
 
 __global__ void iota_kernel(int32_t* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -559,7 +598,9 @@ hipError_t launch_step_backward(int shape, const void* slab, int64_t np, T* lam_
   return hipGetLastError();
 }
 
-bool step_backward_tiled_fits(const Tiling& t) { return (t.tx + 2) * (t.ty + 2) * (t.tz + 2) <= kAdjRegion; }
+bool step_backward_tiled_fits(const Tiling& t, int halo) {
+  return halo >= 1 && (t.tx + 2 * halo) * (t.ty + 2 * halo) * (t.tz + 2 * halo) <= kAdjRegion;
+}
 
 hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(iota_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, p, n);
@@ -567,23 +608,30 @@ hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_step_backward_tiled(int shape, const Packets<T>& sorted, const int32_t* offsets, const Tiling& t,
-                                      T* lam_x, T* lam_u, const T* E, const T* B, const double* lam_dM,
-                                      const double* lam_dE, double* gE, double* gB, const RunConsts& k,
-                                      hipStream_t s) {
-  if (!step_backward_tiled_fits(t)) return hipErrorInvalidValue;
+hipError_t launch_step_backward_tiled(int shape, const Packets<T>& slab, const int32_t* order, const int32_t* offsets,
+                                      const Tiling& t, int halo, int32_t* spill, T* lam_x, T* lam_u, const T* E,
+                                      const T* B, const double* lam_dM, const double* lam_dE, double* gE, double* gB,
+                                      const RunConsts& k, hipStream_t s) {
+  if (!step_backward_tiled_fits(t, halo)) return hipErrorInvalidValue;
   // split a tile's packets over several workgroups when tiles are few and full
   const int64_t ntiles = t.ntiles();
-  const int64_t per_tile = (sorted.np + ntiles - 1) / (ntiles > 0 ? ntiles : 1);
+  const int64_t per_tile = (slab.np + ntiles - 1) / (ntiles > 0 ? ntiles : 1);
   int parts = (int)((per_tile + 1023) / 1024);
   parts = parts < 1 ? 1 : (parts > 4 ? 4 : parts);
   const dim3 grid((unsigned)(ntiles * parts));
-  if (shape == kShapeCIC)
-    hipLaunchKernelGGL((step_backward_tiled_kernel<2, T>), grid, dim3(kBlock), 0, s, sorted, offsets, t, parts, lam_x,
-                       lam_u, E, B, lam_dM, lam_dE, gE, gB, k);
-  else
-    hipLaunchKernelGGL((step_backward_tiled_kernel<3, T>), grid, dim3(kBlock), 0, s, sorted, offsets, t, parts, lam_x,
-                       lam_u, E, B, lam_dM, lam_dE, gE, gB, k);
+  hipLaunchKernelGGL(clear_count_kernel, dim3(1), dim3(1), 0, s, spill);
+  const dim3 lgrid((unsigned)(grid_for(slab.np) < 256 ? grid_for(slab.np) : 256));
+  if (shape == kShapeCIC) {
+    hipLaunchKernelGGL((step_backward_tiled_kernel<2, T>), grid, dim3(kBlock), 0, s, slab, order, offsets, t, halo,
+                       parts, spill, lam_x, lam_u, E, B, lam_dM, lam_dE, gE, gB, k);
+    hipLaunchKernelGGL((step_backward_list_kernel<2, T>), lgrid, dim3(kBlock), 0, s, slab, spill, lam_x, lam_u, E, B,
+                       lam_dM, lam_dE, gE, gB, k);
+  } else {
+    hipLaunchKernelGGL((step_backward_tiled_kernel<3, T>), grid, dim3(kBlock), 0, s, slab, order, offsets, t, halo,
+                       parts, spill, lam_x, lam_u, E, B, lam_dM, lam_dE, gE, gB, k);
+    hipLaunchKernelGGL((step_backward_list_kernel<3, T>), lgrid, dim3(kBlock), 0, s, slab, spill, lam_x, lam_u, E, B,
+                       lam_dM, lam_dE, gE, gB, k);
+  }
   return hipGetLastError();
 }
 
@@ -606,9 +654,10 @@ hipError_t launch_moments_backward(int shape, const Packets<T>& P, const double*
                                               hipStream_t);                                                    \
   template hipError_t launch_moments_backward<T>(int, const Packets<T>&, const double*, const double*,         \
                                                  const double*, T*, T*, const RunConsts&, hipStream_t);        \
-  template hipError_t launch_step_backward_tiled<T>(int, const Packets<T>&, const int32_t*, const Tiling&, T*, T*, \
-                                                    const T*, const T*, const double*, const double*, double*,    \
-                                                    double*, const RunConsts&, hipStream_t);
+  template hipError_t launch_step_backward_tiled<T>(int, const Packets<T>&, const int32_t*, const int32_t*,        \
+                                                    const Tiling&, int, int32_t*, T*, T*, const T*, const T*,      \
+                                                    const double*, const double*, double*, double*,                \
+                                                    const RunConsts&, hipStream_t);
 
 RSOL_ADJ_INSTANTIATE(double)
 RSOL_ADJ_INSTANTIATE(float)

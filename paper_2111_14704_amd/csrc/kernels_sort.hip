@@ -168,16 +168,18 @@ __global__ void __launch_bounds__(kBlock) scatter_kernel(Packets<T> src, Packets
       } else {
         j += e[(int64_t)kRankCap * tw] + atomicAdd(&ovf[tile], 1);
       }
-      if constexpr (is_fp64<T>()) {
+      if (dst.u) {  // NULL: only the permutation (ids) is wanted
+        if constexpr (is_fp64<T>()) {
+          #pragma unroll
+          for (int d = 0; d < 3; ++d) dst.x[d * np + j] = src.x[d * np + i];
+        } else {
+          dst.cell[j] = src.cell[i];
+          #pragma unroll
+          for (int d = 0; d < 3; ++d) dst.off[d * np + j] = src.off[d * np + i];
+        }
         #pragma unroll
-        for (int d = 0; d < 3; ++d) dst.x[d * np + j] = src.x[d * np + i];
-      } else {
-        dst.cell[j] = src.cell[i];
-        #pragma unroll
-        for (int d = 0; d < 3; ++d) dst.off[d * np + j] = src.off[d * np + i];
+        for (int d = 0; d < 3; ++d) dst.u[d * np + j] = src.u[d * np + i];
       }
-      #pragma unroll
-      for (int d = 0; d < 3; ++d) dst.u[d * np + j] = src.u[d * np + i];
       dst.id[j] = src.id[i];
     }
   }

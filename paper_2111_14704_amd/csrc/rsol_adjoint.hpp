@@ -24,17 +24,21 @@ hipError_t launch_step_backward(int shape, const void* slab, int64_t np, T* lam_
                                 const double* lam_dM, const double* lam_dE, double* gE, double* gB,
                                 const RunConsts& k, hipStream_t s);
 
-// Same reverse step with the starting state counting-sorted by tile (launch_sort of the
-// slab with id = the packets' recorded indices into `sorted`, offsets = the sort's bin
-// offsets): dL/dE, dL/dB accumulate per tile in LDS.  Needs a tiling whose tile plus a
-// one-cell halo fits the LDS region (step_backward_tiled_fits).
-bool step_backward_tiled_fits(const Tiling& t);
+// Same reverse step with the packets taken tile by tile: `order` (packet indices in the
+// recorded order, tile by tile) and `offsets` (first entry of each tile) come from a
+// counting sort (launch_sort with the packets' recorded indices as ids) of this step's
+// starting state or of one a few steps later; `slab` is this step's starting state in
+// the recorded order.  dL/dE, dL/dB accumulate per tile in LDS over the tile plus a halo
+// of `halo` cells; packets outside it are listed in `spill` (np + 1 int32 of scratch)
+// and reversed by a second kernel with global atomics.  Needs
+// step_backward_tiled_fits(t, halo).
+bool step_backward_tiled_fits(const Tiling& t, int halo);
 hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t s);
 template <typename T>
-hipError_t launch_step_backward_tiled(int shape, const Packets<T>& sorted, const int32_t* offsets, const Tiling& t,
-                                      T* lam_x, T* lam_u, const T* E, const T* B, const double* lam_dM,
-                                      const double* lam_dE, double* gE, double* gB, const RunConsts& k,
-                                      hipStream_t s);
+hipError_t launch_step_backward_tiled(int shape, const Packets<T>& slab, const int32_t* order, const int32_t* offsets,
+                                      const Tiling& t, int halo, int32_t* spill, T* lam_x, T* lam_u, const T* E,
+                                      const T* B, const double* lam_dM, const double* lam_dE, double* gE, double* gB,
+                                      const RunConsts& k, hipStream_t s);
 
 // Adjoint of the moment deposit at the current state, added into lam_x, lam_u.
 template <typename T>

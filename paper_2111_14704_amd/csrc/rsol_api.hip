@@ -31,6 +31,7 @@ struct rsol_ctx {
   float* B32;
   char* cells_base;     // cell-list buffers of the default step path
   int32_t* iota;        // 0..np-1: recorded packet indices for the adjoint's sort
+  int32_t* spill;       // packets a tiled reverse step leaves to the global kernel (count, then indices)
   float* nn32;          // FP32 copy of the nucleon density (FP32 form with RSOL_FLAG_LOSSES)
   // registered caller arrays
   const double* E;
@@ -152,6 +153,7 @@ size_t layout(const rsol_params& p, int64_t np, rsol_ctx* h) {
   }
   const size_t cl = take(cell_list_bytes(p.nx, p.ny, p.nz, np, p.precision, loss_layout(p)));
   const size_t io = take(sizeof(int32_t) * (size_t)np + 64);
+  const size_t sp = take(sizeof(int32_t) * (size_t)np + 64);
   const size_t n32 = (fp32(p) && loss_layout(p)) ? take(sizeof(float) * (size_t)n_cells(p)) : 0;
   if (h) {
     char* s = h->scratch;
@@ -163,6 +165,7 @@ size_t layout(const rsol_params& p, int64_t np, rsol_ctx* h) {
     h->B32 = fp32(p) ? (float*)(s + b32) : nullptr;
     h->cells_base = s + cl;
     h->iota = (int32_t*)(s + io);
+    h->spill = (int32_t*)(s + sp);
     h->nn32 = (fp32(p) && loss_layout(p)) ? (float*)(s + n32) : nullptr;
   }
   return off;
@@ -762,43 +765,62 @@ int rsol_step_backward(rsol_handle h, int32_t nsteps, const void* states, void* 
   if (!states || !lam_x || !lam_u || !gE || !gB) return fail(h, RSOL_EINVAL, "NULL pointer");
   const RunConsts k = consts(h);
   const size_t slab = rsol_state_bytes(h);
-  // group each step's starting state by tile (a counting sort of the slab whose ids are
-  // the recorded packet indices) so that dL/dE, dL/dB accumulate in LDS
-  const bool tiled = step_backward_tiled_fits(h->tiling);
+  // Take packets tile by tile so that dL/dE, dL/dB accumulate in LDS: a counting sort of
+  // the recorded packet indices by tile, computed from the starting state of every
+  // kAdjSortEvery-th reversed step and reused for the following ones (a two-cell halo
+  // covers what packets move in between; packets beyond it fall back to global atomics).
+  constexpr int kAdjSortEvery = 4;
+  int halo = 0, every = 1;
+  if (step_backward_tiled_fits(h->tiling, 2)) {
+    halo = 2;
+    every = kAdjSortEvery;
+  } else if (step_backward_tiled_fits(h->tiling, 1)) {
+    halo = 1;
+  }
+  const bool tiled = halo > 0;
   if (tiled) RSOL_HIP(h, launch_iota(h->iota, h->np, h->stream), "iota");
   for (int32_t n = nsteps - 1; n >= 0; --n) {
     const void* at = (const char*)states + (size_t)n * slab;
+    const bool resort = (nsteps - 1 - n) % every == 0;
     if (fp32(h->p)) {
+      Packets<float> src;
+      src.np = h->np;
+      src.x = nullptr;
+      src.cell = (int32_t*)at;
+      src.off = (float*)at + h->np;
+      src.u = (float*)at + 4 * h->np;
+      src.id = h->iota;
       if (tiled) {
-        Packets<float> src;
-        src.np = h->np;
-        src.x = nullptr;
-        src.cell = (int32_t*)at;
-        src.off = (float*)at + h->np;
-        src.u = (float*)at + 4 * h->np;
-        src.id = h->iota;
-        RSOL_HIP(h, launch_sort<float>(src, perm_packets<float>(h), k, h->tiling, h->sort_ints, h->stream),
-                 "adjoint sort");
-        RSOL_HIP(h, launch_step_backward_tiled<float>(h->p.shape, perm_packets<float>(h), h->sort_ints, h->tiling,
-                                                      (float*)lam_x, (float*)lam_u, h->E32, h->B32, lam_dM, lam_dE,
+        Packets<float> ord = perm_packets<float>(h);
+        ord.x = nullptr;
+        ord.cell = nullptr;
+        ord.off = nullptr;
+        ord.u = nullptr;
+        if (resort)
+          RSOL_HIP(h, launch_sort<float>(src, ord, k, h->tiling, h->sort_ints, h->stream), "adjoint sort");
+        RSOL_HIP(h, launch_step_backward_tiled<float>(h->p.shape, src, ord.id, h->sort_ints, h->tiling, halo,
+                                                      h->spill, (float*)lam_x, (float*)lam_u, h->E32, h->B32, lam_dM, lam_dE,
                                                       gE, gB, k, h->stream), "step backward");
       } else {
         RSOL_HIP(h, launch_step_backward<float>(h->p.shape, at, h->np, (float*)lam_x, (float*)lam_u, h->E32, h->B32,
                                                 lam_dM, lam_dE, gE, gB, k, h->stream), "step backward");
       }
     } else {
+      Packets<double> src;
+      src.np = h->np;
+      src.x = (double*)at;
+      src.cell = nullptr;
+      src.off = nullptr;
+      src.u = (double*)at + 3 * h->np;
+      src.id = h->iota;
       if (tiled) {
-        Packets<double> src;
-        src.np = h->np;
-        src.x = (double*)at;
-        src.cell = nullptr;
-        src.off = nullptr;
-        src.u = (double*)at + 3 * h->np;
-        src.id = h->iota;
-        RSOL_HIP(h, launch_sort<double>(src, perm_packets<double>(h), k, h->tiling, h->sort_ints, h->stream),
-                 "adjoint sort");
-        RSOL_HIP(h, launch_step_backward_tiled<double>(h->p.shape, perm_packets<double>(h), h->sort_ints, h->tiling,
-                                                       (double*)lam_x, (double*)lam_u, h->E, h->B, lam_dM, lam_dE,
+        Packets<double> ord = perm_packets<double>(h);
+        ord.x = nullptr;
+        ord.u = nullptr;
+        if (resort)
+          RSOL_HIP(h, launch_sort<double>(src, ord, k, h->tiling, h->sort_ints, h->stream), "adjoint sort");
+        RSOL_HIP(h, launch_step_backward_tiled<double>(h->p.shape, src, ord.id, h->sort_ints, h->tiling, halo,
+                                                       h->spill, (double*)lam_x, (double*)lam_u, h->E, h->B, lam_dM, lam_dE,
                                                        gE, gB, k, h->stream), "step backward");
       } else {
         RSOL_HIP(h, launch_step_backward<double>(h->p.shape, at, h->np, (double*)lam_x, (double*)lam_u, h->E, h->B,

@@ -41,7 +41,8 @@ int max_cells_per_tile();
 size_t exclusive_scan_tmp_ints(int64_t n);
 hipError_t launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, hipStream_t s);
 
-// Sort src into dst by tile, rank-major inside each tile.  ints = scratch of
+// Sort src into dst by tile, rank-major inside each tile (dst.u NULL: only dst.id, the
+// permutation, is written).  ints = scratch of
 // sort_scratch_ints words; on return ints[0..nbins] holds the exclusive bin offsets
 // (ints[nbins] = np), so tile t occupies [ints[t*cells_per_tile], ints[(t+1)*cells_per_tile]).
 template <typename T>
