@@ -230,6 +230,9 @@ size_t rsol_state_bytes(rsol_handle h);
 int rsol_record_states(rsol_handle h, int32_t nsteps, void* states);
 
 /* Reverse of the nsteps steps recorded in states (from step nsteps-1 down to 0).
+ * Internally the packets are taken tile by tile (a counting sort of the recorded packet
+ * indices every few reversed steps) so that dL/dE and dL/dB accumulate in on-chip
+ * memory; the caller's arrays keep their order.
  * lam_x, lam_u: [3][np] (precision type), on entry dL/d(x, u) after the last step, on
  * exit dL/d(x, u) before the first.  lam_dM [3][n_cells], lam_dE [n_cells]: cotangent of
  * the exchange summed over these steps (both may be NULL; lam_dE needs lam_dM).

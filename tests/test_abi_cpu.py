@@ -56,6 +56,7 @@ def test_scratch_bytes_positive_and_grows_with_packets():
     dict(nx=0), dict(nx=2000), dict(shape=3), dict(precision=2), dict(sort_every=0), dict(sort_every=9),
     dict(dx=0.0), dict(c_tilde=2000.0), dict(c_tilde=0.0), dict(courant=0.0), dict(courant=0.9),
     dict(mass=-1.0), dict(dt=float("nan")),
+    dict(flags=64), dict(flags=16 | 32), dict(flags=2 | 16), dict(flags=2 | 32),
 ])
 def test_invalid_parameters_are_rejected_before_any_device_work(bad):
     rsol, L = _lib()
@@ -67,6 +68,16 @@ def test_invalid_parameters_are_rejected_before_any_device_work(bad):
     assert rc == -1
     assert h.value is None
     assert L.rsol_last_error(None)
+
+
+def test_loss_layout_needs_more_scratch_and_pushers_do_not():
+    """RSOL_FLAG_LOSSES sizes the cell-list slot stores for packet weights; the pusher and
+    naive flags change only constants (same layout)."""
+    rsol, L = _lib()
+    base = rsol.rsol_scratch_bytes(_params(rsol), 100000)
+    assert rsol.rsol_scratch_bytes(_params(rsol, flags=8), 100000) > base
+    for fl in (4, 16, 32, 1 | 16):
+        assert rsol.rsol_scratch_bytes(_params(rsol, flags=fl), 100000) == base
 
 
 def test_small_or_misaligned_scratch_is_rejected():
