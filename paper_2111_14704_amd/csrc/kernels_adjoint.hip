@@ -104,36 +104,6 @@ __device__ __forceinline__ void slab_load(const void* slab, int64_t np, int64_t 
   }
 }
 
-template <typename T>
-__device__ __forceinline__ void slab_store(void* slab, const Packets<T>& P, int64_t i) {
-  const int64_t np = P.np;
-  if constexpr (is_fp64<T>()) {
-    double* s = (double*)slab;
-    #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      s[d * np + i] = P.x[d * np + i];
-      s[(3 + d) * np + i] = P.u[d * np + i];
-    }
-  } else {
-    int32_t* cw = (int32_t*)slab;
-    float* fw = (float*)slab;
-    cw[i] = P.cell[i];
-    #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      fw[(1 + d) * np + i] = P.off[d * np + i];
-      fw[(4 + d) * np + i] = P.u[d * np + i];
-    }
-  }
-}
-
-// Copy the state before the step into the slab; the step itself runs in step_global
-// (launched right after on the same stream).
-template <typename T>
-__global__ void record_kernel(Packets<T> P, void* slab) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.np; i += (int64_t)gridDim.x * blockDim.x)
-    slab_store<T>(slab, P, i);
-}
-
 // Node access of the backward step.  GlobalAccess: the grid itself (wrapped indices,
 // device-scope atomics for dL/dE, dL/dB).  TileAccess: a workgroup's LDS copy of the
 // fields (and exchange cotangents) on its tile plus a one-cell halo, with the field
@@ -580,12 +550,6 @@ __global__ void __launch_bounds__(kBlock) moments_backward_kernel(Packets<T> P, 
 }  // namespace
 
 template <typename T>
-hipError_t launch_record(const Packets<T>& P, void* slab, hipStream_t s) {
-  hipLaunchKernelGGL(record_kernel<T>, dim3(grid_for(P.np)), dim3(kBlock), 0, s, P, slab);
-  return hipGetLastError();
-}
-
-template <typename T>
 hipError_t launch_step_backward(int shape, const void* slab, int64_t np, T* lam_x, T* lam_u, const T* E, const T* B,
                                 const double* lam_dM, const double* lam_dE, double* gE, double* gB,
                                 const RunConsts& k, hipStream_t s) {
@@ -648,7 +612,6 @@ hipError_t launch_moments_backward(int shape, const Packets<T>& P, const double*
 }
 
 #define RSOL_ADJ_INSTANTIATE(T)                                                                                 \
-  template hipError_t launch_record<T>(const Packets<T>&, void*, hipStream_t);                                 \
   template hipError_t launch_step_backward<T>(int, const void*, int64_t, T*, T*, const T*, const T*,          \
                                               const double*, const double*, double*, double*, const RunConsts&, \
                                               hipStream_t);                                                    \

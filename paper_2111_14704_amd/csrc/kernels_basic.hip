@@ -340,12 +340,13 @@ __global__ void moments_kernel(Packets<T> P, double* __restrict__ rho, double* _
 
 // Fused step with global atomics: gather at x^n, kick, exchange deposit at x^n, drift.
 // LOSS: also gather the nucleon density NN, reduce the packet weight (catastrophic
-// losses) and deposit the change of the weighted packet totals.
-template <int M, typename T, bool LOSS, int PUSH>
+// losses) and deposit the change of the weighted packet totals.  REC: write the starting
+// state of each packet into the state slab `rec` (the differentiation form's recording).
+template <int M, typename T, bool LOSS, int PUSH, bool REC = false>
 __global__ void __launch_bounds__(kBlock) step_global_kernel(Packets<T> P, const T* __restrict__ E,
                                                              const T* __restrict__ B, const T* __restrict__ NN,
                                                              double* __restrict__ dM, double* __restrict__ dE,
-                                                             RunConsts k) {
+                                                             RunConsts k, void* __restrict__ rec = nullptr) {
   const int64_t nc = k.ncells, np = P.np;
   const T h = (T)k.h, hb = (T)k.hb;
   for (int64_t i = gtid(); i < np; i += gstride()) {
@@ -373,6 +374,7 @@ __global__ void __launch_bounds__(kBlock) step_global_kernel(Packets<T> P, const
       }
     }
     const T ux = P.u[i], uy = P.u[np + i], uz = P.u[2 * np + i];
+    if constexpr (REC) store_state<T>(rec, P, i);
     const Kick<T> q = kick<PUSH, T>(ux, uy, uz, e[0], e[1], e[2], b[0], b[1], b[2], h, hb);
     const T nux = ux + q.dux, nuy = uy + q.duy, nuz = uz + q.duz;
     P.u[i] = nux;
@@ -539,6 +541,20 @@ hipError_t launch_step_global(int shape, const Packets<T>& P, const T* E, const 
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_step_record(int shape, const Packets<T>& P, const T* E, const T* B, void* slab, const RunConsts& k,
+                              hipStream_t s) {
+  if (!slab) return hipErrorInvalidValue;
+  const dim3 g(grid_for(P.np)), b(kBlock);
+  if (shape == kShapeCIC)
+    hipLaunchKernelGGL((step_global_kernel<2, T, false, kPushBoris, true>), g, b, 0, s, P, E, B, nullptr, nullptr,
+                       nullptr, k, slab);
+  else
+    hipLaunchKernelGGL((step_global_kernel<3, T, false, kPushBoris, true>), g, b, 0, s, P, E, B, nullptr, nullptr,
+                       nullptr, k, slab);
+  return hipGetLastError();
+}
+
 #define RSOL_INSTANTIATE(T)                                                                                    \
   template hipError_t launch_dt_inputs<T>(const Packets<T>&, const double*, const double*, int,               \
                                           unsigned long long*, hipStream_t);                                   \
@@ -551,7 +567,9 @@ hipError_t launch_step_global(int shape, const Packets<T>& P, const T* E, const 
   template hipError_t launch_moments<T>(int, const Packets<T>&, double*, double*, double*, const RunConsts&,  \
                                         hipStream_t);                                                          \
   template hipError_t launch_step_global<T>(int, const Packets<T>&, const T*, const T*, const T*, double*,     \
-                                            double*, const RunConsts&, hipStream_t);
+                                            double*, const RunConsts&, hipStream_t);                           \
+  template hipError_t launch_step_record<T>(int, const Packets<T>&, const T*, const T*, void*, const RunConsts&, \
+                                            hipStream_t);
 
 RSOL_INSTANTIATE(double)
 RSOL_INSTANTIATE(float)

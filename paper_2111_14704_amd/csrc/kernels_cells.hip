@@ -53,7 +53,7 @@ __device__ __forceinline__ int wrap_near(int i, int n) {
 }
 
 // Per-lane strides (elements) of the quad loop's LDS exchange areas: 12 weights + 4
-// exchange values, and 4 x 2 partial sums, padded so that the 16 quads of a wave
+// exchange values, and up to 8 partial sums, padded so that the 16 quads of a wave
 // (and the lanes of a wave) start on distinct 16-byte bank groups.
 template <typename T>
 constexpr int kPkStride = sizeof(T) == 8 ? 18 : 20;
@@ -97,6 +97,23 @@ __device__ __forceinline__ void weights3(T f, T* w) {
 // packet from the 27 nodes around its home cell, fetch(node, comp) giving the node
 // values; the summation order (x first, then y-z pairs) is the one the quad path
 // uses, so a packet's arithmetic does not depend on the store it was read from.
+// One component of the field at a packet from the component's 27 node values: w[0..2]
+// are the packet's x weights and w[3 + b + 3c] the products of its y and z weights.
+template <typename T>
+__device__ __forceinline__ T stencil_sum(const T w[12], const T F[27]) {
+  T s = T(0);
+  #pragma unroll
+  for (int c = 0; c < 3; ++c)
+    #pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      T t = T(0);
+      #pragma unroll
+      for (int a = 0; a < 3; ++a) t += w[a] * F[a + 3 * (b + 3 * c)];
+      s += w[3 + b + 3 * c] * t;
+    }
+  return s;
+}
+
 template <int NC, typename T, typename F>
 __device__ __forceinline__ void gather27(const T* w, F fetch, T out[NC]) {
   #pragma unroll
@@ -488,7 +505,11 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
     n = n < V.cap ? n : V.cap;
     n = n < 4 * sR ? n : 4 * sR;  // packets past the round cap go to the per-packet phase
 
-    // this lane's field components on the 27 nodes around the cell
+    // this lane's field components on the 27 nodes around the cell.  Without losses
+    // the quad holds E_x, E_y, E_z, B_x in F0 (lane q: component q) and B_y, B_z, B_y,
+    // B_z in F1, so the six components of its four packets take six passes: four over
+    // F0 and two over F1, where lanes 0, 1 serve packets 0, 2 and lanes 2, 3 packets
+    // 1, 3.  With losses lane q < 3 holds E_q, B_q and lane 3 the nucleon density.
     T F0[27], F1[27], D[27];
     #pragma unroll
     for (int c = 0; c < 3; ++c)
@@ -498,9 +519,13 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
         for (int a = 0; a < 3; ++a) {
           const int node = a + 3 * (b + 3 * c);
           const int r = (lx + a) + kRegionEdge * ((ly + b) + kRegionEdge * (lz + c));
-          if constexpr (LOSS) F0[node] = q < 3 ? Fs[q][r] : Fs[6][r];
-          else F0[node] = q < 3 ? Fs[q][r] : T(0);
-          F1[node] = q < 3 ? Fs[3 + q][r] : T(0);
+          if constexpr (LOSS) {
+            F0[node] = q < 3 ? Fs[q][r] : Fs[6][r];
+            F1[node] = q < 3 ? Fs[3 + q][r] : T(0);
+          } else {
+            F0[node] = Fs[q][r];
+            F1[node] = Fs[4 + (q & 1)][r];
+          }
           D[node] = T(0);
         }
 
@@ -552,38 +577,48 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
       }
       wave_sync();
 
-      // gather: lane q sums its two components for each packet J of the quad and
-      // leaves the partial sums in LDS for the owner lane
-      #pragma unroll
-      for (int J = 0; J < 4; ++J) {
-        const T* wj = pkw + (qbase + J) * kPkStride<T>;
-        T w[12];
-        #pragma unroll
-        for (int i = 0; i < 12; ++i) w[i] = wj[i];
-        T s0 = T(0), s1 = T(0);
-        #pragma unroll
-        for (int c = 0; c < 3; ++c)
-          #pragma unroll
-          for (int b = 0; b < 3; ++b) {
-            T t0 = T(0), t1 = T(0);
-            #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              const int node = a + 3 * (b + 3 * c);
-              t0 += w[a] * F0[node];
-              t1 += w[a] * F1[node];
-            }
-            s0 += w[3 + b + 3 * c] * t0;
-            s1 += w[3 + b + 3 * c] * t1;
-          }
-        rsw[lane * kRsStride<T> + 2 * J] = s0;
-        rsw[lane * kRsStride<T> + 2 * J + 1] = s1;
-      }
-      wave_sync();
+      // gather: each lane sums its components over the 27 nodes for the packets it
+      // serves and leaves the sums in LDS for the owner lanes
       T eb[6];
-      #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        eb[c] = rsw[(qbase + c) * kRsStride<T> + 2 * q];
-        eb[3 + c] = rsw[(qbase + c) * kRsStride<T> + 2 * q + 1];
+      if constexpr (LOSS) {
+        #pragma unroll
+        for (int J = 0; J < 4; ++J) {
+          const T* wj = pkw + (qbase + J) * kPkStride<T>;
+          T w[12];
+          #pragma unroll
+          for (int i = 0; i < 12; ++i) w[i] = wj[i];
+          rsw[lane * kRsStride<T> + 2 * J] = stencil_sum<T>(w, F0);
+          rsw[lane * kRsStride<T> + 2 * J + 1] = stencil_sum<T>(w, F1);
+        }
+        wave_sync();
+        #pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          eb[c] = rsw[(qbase + c) * kRsStride<T> + 2 * q];
+          eb[3 + c] = rsw[(qbase + c) * kRsStride<T> + 2 * q + 1];
+        }
+      } else {
+        #pragma unroll
+        for (int J = 0; J < 4; ++J) {
+          const T* wj = pkw + (qbase + J) * kPkStride<T>;
+          T w[12];
+          #pragma unroll
+          for (int i = 0; i < 12; ++i) w[i] = wj[i];
+          rsw[lane * kRsStride<T> + J] = stencil_sum<T>(w, F0);
+        }
+        #pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          const T* wj = pkw + (qbase + 2 * p + (q >> 1)) * kPkStride<T>;
+          T w[12];
+          #pragma unroll
+          for (int i = 0; i < 12; ++i) w[i] = wj[i];
+          rsw[lane * kRsStride<T> + 4 + p] = stencil_sum<T>(w, F1);
+        }
+        wave_sync();
+        #pragma unroll
+        for (int c = 0; c < 4; ++c) eb[c] = rsw[(qbase + c) * kRsStride<T> + q];
+        const int hy = qbase + 2 * (q & 1);  // lane holding B_y for this lane's packet
+        eb[4] = rsw[hy * kRsStride<T> + 4 + (q >> 1)];
+        eb[5] = rsw[(hy + 1) * kRsStride<T> + 4 + (q >> 1)];
       }
 
       // kick (Eq. (11))

@@ -1,5 +1,5 @@
-// Launchers of the differentiation-form kernels (forward state recording, step
-// adjoint, moment adjoint).
+// Launchers of the differentiation-form kernels (step adjoint, moment adjoint); the
+// recording forward step is declared beside the other step launchers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,11 +9,6 @@
 #include "rsol_sort.hpp"
 
 namespace rsol {
-
-// Copy the current packet state into a state slab: FP64 form [6][np] doubles
-// (x0, x1, x2, u0, u1, u2); FP32 form [7][np] 4-byte words (cell, off0..2, u0..2).
-template <typename T>
-hipError_t launch_record(const Packets<T>& P, void* slab, hipStream_t s);
 
 // Reverse of one step whose starting state is in `slab`: lam_x, lam_u [3][np] hold
 // dL/d(state after) on entry and dL/d(state before) on exit; gE, gB [3][n_cells] and

@@ -738,15 +738,12 @@ int rsol_record_states(rsol_handle h, int32_t nsteps, void* states) {
   const size_t slab = rsol_state_bytes(h);
   for (int32_t n = 0; n < nsteps; ++n) {
     void* at = (char*)states + (size_t)n * slab;
-    if (fp32(h->p)) {
-      RSOL_HIP(h, launch_record<float>(caller_packets<float>(h), at, h->stream), "record");
-      RSOL_HIP(h, launch_step_global<float>(h->p.shape, caller_packets<float>(h), h->E32, h->B32, nullptr, nullptr, nullptr, k,
-                                            h->stream), "record step");
-    } else {
-      RSOL_HIP(h, launch_record<double>(caller_packets<double>(h), at, h->stream), "record");
-      RSOL_HIP(h, launch_step_global<double>(h->p.shape, caller_packets<double>(h), h->E, h->B, nullptr, nullptr, nullptr, k,
-                                             h->stream), "record step");
-    }
+    if (fp32(h->p))
+      RSOL_HIP(h, launch_step_record<float>(h->p.shape, caller_packets<float>(h), h->E32, h->B32, at, k, h->stream),
+               "record step");
+    else
+      RSOL_HIP(h, launch_step_record<double>(h->p.shape, caller_packets<double>(h), h->E, h->B, at, k, h->stream),
+               "record step");
   }
   h->sorted_valid = false;
   return RSOL_OK;

@@ -84,4 +84,11 @@ template <typename T>
 hipError_t launch_step_global(int shape, const Packets<T>& P, const T* E, const T* B, const T* NN, double* dM,
                               double* dE, const RunConsts& k, hipStream_t s);
 
+// One step of the packets in their own order (Boris, no exchange deposit) that first
+// writes each packet's starting state into `slab`: FP64 form [6][np] doubles (x0, x1,
+// x2, u0, u1, u2); FP32 form [7][np] 4-byte words (cell, off0..2, u0..2).
+template <typename T>
+hipError_t launch_step_record(int shape, const Packets<T>& P, const T* E, const T* B, void* slab,
+                              const RunConsts& k, hipStream_t s);
+
 }  // namespace rsol

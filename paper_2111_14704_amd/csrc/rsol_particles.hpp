@@ -53,4 +53,28 @@ __device__ __forceinline__ void load_position(const Packets<T>& P, int64_t i, co
   }
 }
 
+// Copy packet i's state into a state slab: FP64 [6][np] doubles (x, u); FP32 [7][np]
+// 4-byte words (cell, off, u).
+template <typename T>
+__device__ __forceinline__ void store_state(void* slab, const Packets<T>& P, int64_t i) {
+  const int64_t np = P.np;
+  if constexpr (is_fp64<T>()) {
+    double* s = (double*)slab;
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      s[d * np + i] = P.x[d * np + i];
+      s[(3 + d) * np + i] = P.u[d * np + i];
+    }
+  } else {
+    int32_t* cw = (int32_t*)slab;
+    float* fw = (float*)slab;
+    cw[i] = P.cell[i];
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      fw[(1 + d) * np + i] = P.off[d * np + i];
+      fw[(4 + d) * np + i] = P.u[d * np + i];
+    }
+  }
+}
+
 }  // namespace rsol
