@@ -218,21 +218,28 @@ int rsol_set_flags(rsol_handle h, int32_t flags);
 /* ---- Differentiation form (reverse mode through gather -> push -> drift) ----
  * The adjoint of the deposit is a gather and the adjoint of the gather is a scatter.
  * Gradients flow to the grid fields E, B (as independent inputs) and to the initial
- * packet state; dt is a fixed parameter.  Packet order must stay fixed between the
- * recorded states and the adjoint arrays (rsol_record_states never re-bins). */
+ * packet state; dt is a fixed parameter.  The adjoint arrays are in the order of the
+ * caller's packet arrays at the time of recording (rsol_record_states leaves that order
+ * as it found it). */
 
-/* Bytes of one stored packet state: np * 48 (FP64 form: x[3], u[3] doubles) or np * 28
- * (FP32 form: cell, off[3], u[3] as 4-byte words). */
+/* Bytes of one recorded step: the packet state (np * 48 in the FP64 form: x[3], u[3]
+ * doubles; np * 28 in the FP32 form: cell, off[3], u[3] as 4-byte words) followed by the
+ * tile ordering of its block of steps (np * 8 bytes plus 4 bytes per cell and one,
+ * each part rounded up to 256 bytes).  The contents are internal to the library. */
 size_t rsol_state_bytes(rsol_handle h);
 
-/* Advance nsteps steps without exchange deposit and without re-binning, writing the
- * state BEFORE each step into states[n] (device buffer of nsteps * rsol_state_bytes). */
+/* Advance nsteps steps without exchange deposit, writing the state BEFORE each step
+ * into states[n] (device buffer of nsteps * rsol_state_bytes).  The caller's packet
+ * arrays end advanced by nsteps steps, in their own order.  Internally the packets are
+ * counting-sorted by tile every few steps into a scratch copy, which the steps advance
+ * with each tile's E and B staged in on-chip memory; the recorded states are kept in
+ * those orders, so that the reverse sweep reads them contiguously. */
 int rsol_record_states(rsol_handle h, int32_t nsteps, void* states);
 
-/* Reverse of the nsteps steps recorded in states (from step nsteps-1 down to 0).
- * Internally the packets are taken tile by tile (a counting sort of the recorded packet
- * indices every few reversed steps) so that dL/dE and dL/dB accumulate in on-chip
- * memory; the caller's arrays keep their order.
+/* Reverse of the nsteps steps recorded in states by one rsol_record_states call (its
+ * first nsteps steps), from step nsteps-1 down to 0.  Internally the adjoints are held
+ * in the recorded tile orders, so that dL/dE and dL/dB accumulate in on-chip memory;
+ * the caller's arrays keep their order.
  * lam_x, lam_u: [3][np] (precision type), on entry dL/d(x, u) after the last step, on
  * exit dL/d(x, u) before the first.  lam_dM [3][n_cells], lam_dE [n_cells]: cotangent of
  * the exchange summed over these steps (both may be NULL; lam_dE needs lam_dM).

@@ -136,8 +136,6 @@ struct GlobalAccess {
   }
 };
 
-constexpr int kAdjRegion = 512;  // region cells: a 4x4x4 tile with a two-cell halo
-
 template <typename T>
 struct TileAccess {
   const T* F;        // [6][kAdjRegion] E then B
@@ -356,7 +354,7 @@ __global__ void __launch_bounds__(kBlock) step_backward_kernel(const void* __res
 // further than the halo allows since the sort) is appended to `spill` (count in
 // spill[0], packet indices after it) for step_backward_list_kernel.
 template <int M, typename T>
-__global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> slab, const int32_t* __restrict__ order,
+__global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> slab,
                                                                      const int32_t* __restrict__ offsets, Tiling tl,
                                                                      int halo, int parts, int32_t* __restrict__ spill,
                                                                      T* __restrict__ lam_x,
@@ -381,7 +379,7 @@ __global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> 
   const bool ld = lam_dM != nullptr;
   for (int r = threadIdx.x; r < rc; r += blockDim.x) {
     const int ax = r % rx, ay = (r / rx) % ry, az = r / (rx * ry);
-    const int64_t g = wrapn(ox + ax, k.nx) + (int64_t)k.nx * (wrapn(oy + ay, k.ny) + (int64_t)k.ny * wrapn(oz + az, k.nz));
+    const int64_t g = wrap_mod(ox + ax, k.nx) + (int64_t)k.nx * (wrap_mod(oy + ay, k.ny) + (int64_t)k.ny * wrap_mod(oz + az, k.nz));
     #pragma unroll
     for (int d = 0; d < 3; ++d) {
       Fs[d * kAdjRegion + r] = E[d * nc + g];
@@ -397,12 +395,14 @@ __global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> 
   }
   __syncthreads();
   const TileAccess<T> acc{Fs, ld ? Ls : nullptr, Gs, ox, oy, oz, rx, ry};
-  const int64_t b0 = offsets[tile * tl.cells_per_tile], b1 = offsets[(tile + 1) * tl.cells_per_tile];
+  // offsets come from a recorded slab: keep the range inside the arrays whatever they hold
+  int64_t b0 = offsets[tile * tl.cells_per_tile], b1 = offsets[(tile + 1) * tl.cells_per_tile];
+  b0 = b0 < 0 ? 0 : (b0 > np ? np : b0);
+  b1 = b1 < b0 ? b0 : (b1 > np ? np : b1);
   const int64_t len = b1 - b0;
   const int64_t j0 = b0 + len * part / parts, j1 = b0 + len * (part + 1) / parts;
   const int n3[3] = {k.nx, k.ny, k.nz};
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
-    const int64_t i = order[j];
+  for (int64_t i = j0 + threadIdx.x; i < j1; i += blockDim.x) {
     int home[3];
     T f[3], u0a[3];
     load_position(slab, i, k, home, f);
@@ -437,7 +437,7 @@ __global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> 
   __syncthreads();
   for (int r = threadIdx.x; r < rc; r += blockDim.x) {
     const int ax = r % rx, ay = (r / rx) % ry, az = r / (rx * ry);
-    const int64_t g = wrapn(ox + ax, k.nx) + (int64_t)k.nx * (wrapn(oy + ay, k.ny) + (int64_t)k.ny * wrapn(oz + az, k.nz));
+    const int64_t g = wrap_mod(ox + ax, k.nx) + (int64_t)k.nx * (wrap_mod(oy + ay, k.ny) + (int64_t)k.ny * wrap_mod(oz + az, k.nz));
     #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const double ge = Gs[d * kAdjRegion + r], gb = Gs[(3 + d) * kAdjRegion + r];
@@ -547,7 +547,54 @@ __global__ void __launch_bounds__(kBlock) moments_backward_kernel(Packets<T> P, 
   }
 }
 
+// rows x np arrays: dst[r][j] = src[r][idx[j]] (gather) or dst[r][idx[j]] = src[r][j]
+// (scatter); idx is a permutation of 0..np-1.
+template <typename T>
+__global__ void permute_rows_kernel(const T* __restrict__ src, T* __restrict__ dst, const int32_t* __restrict__ idx,
+                                    int64_t np, int rows, bool scatter) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < np; j += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx[j];
+    if (i < 0 || i >= np) continue;  // not a permutation entry (the arrays are left alone there)
+    for (int r = 0; r < rows; ++r) {
+      if (scatter) dst[r * np + i] = src[r * np + j];
+      else dst[r * np + j] = src[r * np + i];
+    }
+  }
+}
+
+// Packets in tile order back to the caller's order: P[S.id[j]] = S[j] (positions and
+// momenta; the caller's ids stay).
+template <typename T>
+__global__ void unsort_kernel(Packets<T> S, Packets<T> P) {
+  const int64_t np = P.np;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < np; j += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = S.id[j];
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if constexpr (is_fp64<T>()) P.x[d * np + i] = S.x[d * np + j];
+      else P.off[d * np + i] = S.off[d * np + j];
+      P.u[d * np + i] = S.u[d * np + j];
+    }
+    if constexpr (!is_fp64<T>()) P.cell[i] = S.cell[j];
+  }
+}
+
 }  // namespace
+
+template <typename T>
+hipError_t launch_permute_rows(const T* src, T* dst, const int32_t* idx, int64_t np, int rows, bool scatter,
+                               hipStream_t s) {
+  if (np > 0)
+    hipLaunchKernelGGL(permute_rows_kernel<T>, dim3(grid_for(np)), dim3(kBlock), 0, s, src, dst, idx, np, rows,
+                       scatter);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_unsort(const Packets<T>& S, const Packets<T>& P, hipStream_t s) {
+  if (P.np > 0) hipLaunchKernelGGL(unsort_kernel<T>, dim3(grid_for(P.np)), dim3(kBlock), 0, s, S, P);
+  return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_step_backward(int shape, const void* slab, int64_t np, T* lam_x, T* lam_u, const T* E, const T* B,
@@ -572,7 +619,7 @@ hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_step_backward_tiled(int shape, const Packets<T>& slab, const int32_t* order, const int32_t* offsets,
+hipError_t launch_step_backward_tiled(int shape, const Packets<T>& slab, const int32_t* offsets,
                                       const Tiling& t, int halo, int32_t* spill, T* lam_x, T* lam_u, const T* E,
                                       const T* B, const double* lam_dM, const double* lam_dE, double* gE, double* gB,
                                       const RunConsts& k, hipStream_t s) {
@@ -586,12 +633,12 @@ hipError_t launch_step_backward_tiled(int shape, const Packets<T>& slab, const i
   hipLaunchKernelGGL(clear_count_kernel, dim3(1), dim3(1), 0, s, spill);
   const dim3 lgrid((unsigned)(grid_for(slab.np) < 256 ? grid_for(slab.np) : 256));
   if (shape == kShapeCIC) {
-    hipLaunchKernelGGL((step_backward_tiled_kernel<2, T>), grid, dim3(kBlock), 0, s, slab, order, offsets, t, halo,
+    hipLaunchKernelGGL((step_backward_tiled_kernel<2, T>), grid, dim3(kBlock), 0, s, slab, offsets, t, halo,
                        parts, spill, lam_x, lam_u, E, B, lam_dM, lam_dE, gE, gB, k);
     hipLaunchKernelGGL((step_backward_list_kernel<2, T>), lgrid, dim3(kBlock), 0, s, slab, spill, lam_x, lam_u, E, B,
                        lam_dM, lam_dE, gE, gB, k);
   } else {
-    hipLaunchKernelGGL((step_backward_tiled_kernel<3, T>), grid, dim3(kBlock), 0, s, slab, order, offsets, t, halo,
+    hipLaunchKernelGGL((step_backward_tiled_kernel<3, T>), grid, dim3(kBlock), 0, s, slab, offsets, t, halo,
                        parts, spill, lam_x, lam_u, E, B, lam_dM, lam_dE, gE, gB, k);
     hipLaunchKernelGGL((step_backward_list_kernel<3, T>), lgrid, dim3(kBlock), 0, s, slab, spill, lam_x, lam_u, E, B,
                        lam_dM, lam_dE, gE, gB, k);
@@ -617,7 +664,9 @@ hipError_t launch_moments_backward(int shape, const Packets<T>& P, const double*
                                               hipStream_t);                                                    \
   template hipError_t launch_moments_backward<T>(int, const Packets<T>&, const double*, const double*,         \
                                                  const double*, T*, T*, const RunConsts&, hipStream_t);        \
-  template hipError_t launch_step_backward_tiled<T>(int, const Packets<T>&, const int32_t*, const int32_t*,        \
+  template hipError_t launch_permute_rows<T>(const T*, T*, const int32_t*, int64_t, int, bool, hipStream_t);   \
+  template hipError_t launch_unsort<T>(const Packets<T>&, const Packets<T>&, hipStream_t);                      \
+  template hipError_t launch_step_backward_tiled<T>(int, const Packets<T>&, const int32_t*,                        \
                                                     const Tiling&, int, int32_t*, T*, T*, const T*, const T*,      \
                                                     const double*, const double*, double*, double*,                \
                                                     const RunConsts&, hipStream_t);

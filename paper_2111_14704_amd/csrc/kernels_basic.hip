@@ -5,6 +5,7 @@
 // reference beside the tiled fused step.
 #include <math.h>
 
+#include "rsol_adjoint.hpp"
 #include "rsol_launch.hpp"
 
 namespace rsol {
@@ -416,6 +417,117 @@ __global__ void __launch_bounds__(kBlock) step_global_kernel(Packets<T> P, const
   }
 }
 
+// Recording step of the differentiation form on packets held in tile order (positions
+// [offsets[t*cells_per_tile], offsets[(t+1)*cells_per_tile]) belong to tile t): one
+// workgroup per part of a tile stages E and B of the tile plus a `halo`-cell border in
+// LDS; each packet's starting state goes to the state slab `rec` at its own position,
+// then the gather (the weights and summation order of step_global_kernel, so the
+// trajectory is the same to the bit), the Boris kick and the drift.  A packet whose
+// stencil has left the staged region since the sort gathers from the grid instead.
+template <int M, typename T>
+__global__ void __launch_bounds__(kBlock) step_record_tiled_kernel(Packets<T> P, void* __restrict__ rec,
+                                                                   const int32_t* __restrict__ offsets, Tiling tl,
+                                                                   int halo, int parts, const T* __restrict__ E,
+                                                                   const T* __restrict__ B, RunConsts k) {
+  __shared__ T Fs[6 * kAdjRegion];
+  const int64_t tile = blockIdx.x / parts;
+  const int part = blockIdx.x - (int)(tile * parts);
+  const int ttx = (int)(tile % tl.ntx), tty = (int)((tile / tl.ntx) % tl.nty), ttz = (int)(tile / ((int64_t)tl.ntx * tl.nty));
+  const int t0[3] = {ttx * tl.tx, tty * tl.ty, ttz * tl.tz};
+  const int o[3] = {t0[0] - halo, t0[1] - halo, t0[2] - halo};
+  const int rext[3] = {tl.tx + 2 * halo, tl.ty + 2 * halo, tl.tz + 2 * halo};
+  const int rc = rext[0] * rext[1] * rext[2];
+  const int64_t nc = k.ncells, np = P.np;
+  for (int r = threadIdx.x; r < rc; r += blockDim.x) {
+    const int ax = r % rext[0], ay = (r / rext[0]) % rext[1], az = r / (rext[0] * rext[1]);
+    const int64_t g = wrap_mod(o[0] + ax, k.nx) +
+                      (int64_t)k.nx * (wrap_mod(o[1] + ay, k.ny) + (int64_t)k.ny * wrap_mod(o[2] + az, k.nz));
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      Fs[d * kAdjRegion + r] = E[d * nc + g];
+      Fs[(3 + d) * kAdjRegion + r] = B[d * nc + g];
+    }
+  }
+  __syncthreads();
+  int64_t b0 = offsets[tile * tl.cells_per_tile], b1 = offsets[(tile + 1) * tl.cells_per_tile];
+  b0 = b0 < 0 ? 0 : (b0 > np ? np : b0);
+  b1 = b1 < b0 ? b0 : (b1 > np ? np : b1);
+  const int64_t len = b1 - b0;
+  const int64_t j0 = b0 + len * part / parts, j1 = b0 + len * (part + 1) / parts;
+  const int n3[3] = {k.nx, k.ny, k.nz};
+  const T h = (T)k.h, hb = (T)k.hb;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+    int home[3];
+    T f[3];
+    load_position(P, j, k, home, f);
+    const T ux = P.u[j], uy = P.u[np + j], uz = P.u[2 * np + j];
+    store_state<T>(rec, P, j);
+    // home in the tile's unwrapped frame; the stencil spans home-1 .. home+1
+    bool inside = true;
+    int hu[3];
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int hw = wrap_index(home[d], n3[d]);
+      int delta = hw - t0[d];
+      if (2 * delta >= n3[d]) delta -= n3[d];
+      else if (2 * delta < -n3[d]) delta += n3[d];
+      hu[d] = t0[d] + delta;
+      const int rel = delta + halo;
+      inside &= rel >= 1 && rel <= rext[d] - 2;
+    }
+    T e[3] = {0, 0, 0}, b[3] = {0, 0, 0};
+    if (inside) {
+      const AxisWeights<M, T> ax = axis_weights<M, T>(hu[0], f[0]), ay = axis_weights<M, T>(hu[1], f[1]),
+                              az = axis_weights<M, T>(hu[2], f[2]);
+      #pragma unroll
+      for (int cz = 0; cz < M; ++cz) {
+        #pragma unroll
+        for (int cy = 0; cy < M; ++cy) {
+          const T wyz = ay.w[cy] * az.w[cz];
+          #pragma unroll
+          for (int cx = 0; cx < M; ++cx) {
+            const int node = (ax.base + cx - o[0]) + rext[0] * ((ay.base + cy - o[1]) + rext[1] * (az.base + cz - o[2]));
+            const T w = ax.w[cx] * wyz;
+            #pragma unroll
+            for (int d = 0; d < 3; ++d) {
+              e[d] += w * Fs[d * kAdjRegion + node];
+              b[d] += w * Fs[(3 + d) * kAdjRegion + node];
+            }
+          }
+        }
+      }
+    } else {
+      const Stencil<M, T> s = stencil_of<M, T>(P, j, k);
+      #pragma unroll
+      for (int cz = 0; cz < M; ++cz) {
+        const int iz = wrap_index(s.az.base + cz, k.nz);
+        #pragma unroll
+        for (int cy = 0; cy < M; ++cy) {
+          const int iy = wrap_index(s.ay.base + cy, k.ny);
+          const T wyz = s.ay.w[cy] * s.az.w[cz];
+          #pragma unroll
+          for (int cx = 0; cx < M; ++cx) {
+            const int ix = wrap_index(s.ax.base + cx, k.nx);
+            const int64_t node = ix + (int64_t)k.nx * (iy + (int64_t)k.ny * iz);
+            const T w = s.ax.w[cx] * wyz;
+            #pragma unroll
+            for (int d = 0; d < 3; ++d) {
+              e[d] += w * E[d * nc + node];
+              b[d] += w * B[d * nc + node];
+            }
+          }
+        }
+      }
+    }
+    const Kick<T> q = kick<kPushBoris, T>(ux, uy, uz, e[0], e[1], e[2], b[0], b[1], b[2], h, hb);
+    const T nux = ux + q.dux, nuy = uy + q.duy, nuz = uz + q.duz;
+    P.u[j] = nux;
+    P.u[np + j] = nuy;
+    P.u[2 * np + j] = nuz;
+    drift_one<T>(P, j, nux, nuy, nuz, k);
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
@@ -555,6 +667,29 @@ hipError_t launch_step_record(int shape, const Packets<T>& P, const T* E, const 
   return hipGetLastError();
 }
 
+bool step_record_tiled_fits(const Tiling& t, int halo) {
+  return halo >= 1 && (t.tx + 2 * halo) * (t.ty + 2 * halo) * (t.tz + 2 * halo) <= kAdjRegion;
+}
+
+template <typename T>
+hipError_t launch_step_record_tiled(int shape, const Packets<T>& P, void* slab, const int32_t* offsets,
+                                    const Tiling& t, int halo, const T* E, const T* B, const RunConsts& k,
+                                    hipStream_t s) {
+  if (!slab || !step_record_tiled_fits(t, halo)) return hipErrorInvalidValue;
+  const int64_t ntiles = t.ntiles();
+  const int64_t per_tile = (P.np + ntiles - 1) / (ntiles > 0 ? ntiles : 1);
+  int parts = (int)((per_tile + 1023) / 1024);
+  parts = parts < 1 ? 1 : (parts > 4 ? 4 : parts);
+  const dim3 grid((unsigned)(ntiles * parts));
+  if (shape == kShapeCIC)
+    hipLaunchKernelGGL((step_record_tiled_kernel<2, T>), grid, dim3(kBlock), 0, s, P, slab, offsets, t, halo, parts,
+                       E, B, k);
+  else
+    hipLaunchKernelGGL((step_record_tiled_kernel<3, T>), grid, dim3(kBlock), 0, s, P, slab, offsets, t, halo, parts,
+                       E, B, k);
+  return hipGetLastError();
+}
+
 #define RSOL_INSTANTIATE(T)                                                                                    \
   template hipError_t launch_dt_inputs<T>(const Packets<T>&, const double*, const double*, int,               \
                                           unsigned long long*, hipStream_t);                                   \
@@ -569,7 +704,9 @@ hipError_t launch_step_record(int shape, const Packets<T>& P, const T* E, const 
   template hipError_t launch_step_global<T>(int, const Packets<T>&, const T*, const T*, const T*, double*,     \
                                             double*, const RunConsts&, hipStream_t);                           \
   template hipError_t launch_step_record<T>(int, const Packets<T>&, const T*, const T*, void*, const RunConsts&, \
-                                            hipStream_t);
+                                            hipStream_t);                                                      \
+  template hipError_t launch_step_record_tiled<T>(int, const Packets<T>&, void*, const int32_t*, const Tiling&, \
+                                                  int, const T*, const T*, const RunConsts&, hipStream_t);
 
 RSOL_INSTANTIATE(double)
 RSOL_INSTANTIATE(float)

@@ -144,7 +144,8 @@ __global__ void __launch_bounds__(kBlock) scatter_kernel(Packets<T> src, Packets
                                                          const int32_t* __restrict__ keys,
                                                          const int32_t* __restrict__ ranks,
                                                          const int32_t* __restrict__ offsets,
-                                                         const int32_t* __restrict__ tables, int32_t* ovf) {
+                                                         const int32_t* __restrict__ tables, int32_t* ovf,
+                                                         int32_t* __restrict__ pos_out) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t np = src.np;
   const int cpt = t.cells_per_tile;
@@ -181,6 +182,7 @@ __global__ void __launch_bounds__(kBlock) scatter_kernel(Packets<T> src, Packets
         for (int d = 0; d < 3; ++d) dst.u[d * np + j] = src.u[d * np + i];
       }
       dst.id[j] = src.id[i];
+      if (pos_out) pos_out[i] = (int32_t)j;
     }
   }
 }
@@ -264,7 +266,7 @@ int max_cells_per_tile() { return 32 * kMaskWords; }
 
 template <typename T>
 hipError_t launch_sort(const Packets<T>& src, const Packets<T>& dst, const RunConsts& k, const Tiling& t,
-                       int32_t* ints, hipStream_t s) {
+                       int32_t* ints, hipStream_t s, int32_t* pos_out) {
   const int64_t nbins = t.nbins();
   const int64_t nblk = (nbins + kScanChunk - 1) / kScanChunk;
   int32_t* offsets = ints;                 // nbins + 1
@@ -286,7 +288,7 @@ hipError_t launch_sort(const Packets<T>& src, const Packets<T>& dst, const RunCo
   hipLaunchKernelGGL(set_last_kernel, dim3(1), dim3(1), 0, s, offsets, nbins, (int32_t)src.np);
   hipLaunchKernelGGL(tile_tables_kernel, dim3((unsigned)t.ntiles()), dim3(256), 0, s, offsets, t, tables, ovf);
   hipLaunchKernelGGL(scatter_kernel<T>, dim3(grid_for(src.np)), dim3(kBlock), 0, s, src, dst, t, keys, ranks,
-                     offsets, tables, ovf);
+                     offsets, tables, ovf, pos_out);
   return hipGetLastError();
 }
 
@@ -305,8 +307,8 @@ hipError_t launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int
 }
 
 template hipError_t launch_sort<double>(const Packets<double>&, const Packets<double>&, const RunConsts&,
-                                        const Tiling&, int32_t*, hipStream_t);
+                                        const Tiling&, int32_t*, hipStream_t, int32_t*);
 template hipError_t launch_sort<float>(const Packets<float>&, const Packets<float>&, const RunConsts&,
-                                       const Tiling&, int32_t*, hipStream_t);
+                                       const Tiling&, int32_t*, hipStream_t, int32_t*);
 
 }  // namespace rsol

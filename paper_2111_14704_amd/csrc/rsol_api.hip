@@ -131,6 +131,23 @@ Tiling tiling_for(const rsol_params& p) {
   return make_tiling(p.nx, p.ny, p.nz, pl.tx, pl.ty, pl.tz);
 }
 
+// Bytes of one sorted packet copy (state and id) for np packets.
+size_t packet_copy_bytes(const rsol_params& p, int64_t np) {
+  const size_t per = fp32(p) ? (sizeof(int32_t) + 6 * sizeof(float) + sizeof(int32_t))
+                             : (6 * sizeof(double) + sizeof(int32_t));
+  return per * (size_t)np + 64;
+}
+
+// Work buffers of the differentiation form, carved from the cell-list region (which
+// holds nothing between rsol_step calls): a second sorted packet copy and two adjoint
+// arrays [6][np] (dL/dx rows, then dL/du rows) in tile order.
+size_t adj_lam_bytes(const rsol_params& p, int64_t np) {
+  return 6 * (size_t)np * (fp32(p) ? sizeof(float) : sizeof(double));
+}
+size_t adj_work_bytes(const rsol_params& p, int64_t np) {
+  return align_up(packet_copy_bytes(p, np)) + 2 * align_up(adj_lam_bytes(p, np));
+}
+
 // Scratch layout; returns total bytes and fills offsets when h is given.
 size_t layout(const rsol_params& p, int64_t np, rsol_ctx* h) {
   size_t off = 0;
@@ -143,15 +160,14 @@ size_t layout(const rsol_params& p, int64_t np, rsol_ctx* h) {
   const size_t rd = take(sizeof(unsigned long long) * 4);
   const Tiling t = tiling_for(p);
   const size_t si = take(sizeof(int32_t) * sort_scratch_ints(t, np));
-  const size_t per = fp32(p) ? (sizeof(int32_t) + 6 * sizeof(float) + sizeof(int32_t))
-                             : (6 * sizeof(double) + sizeof(int32_t));
-  const size_t pm = take(per * (size_t)np + 64);
+  const size_t pm = take(packet_copy_bytes(p, np));
   size_t e32 = 0, b32 = 0;
   if (fp32(p)) {
     e32 = take(sizeof(float) * 3 * (size_t)n_cells(p));
     b32 = take(sizeof(float) * 3 * (size_t)n_cells(p));
   }
-  const size_t cl = take(cell_list_bytes(p.nx, p.ny, p.nz, np, p.precision, loss_layout(p)));
+  const size_t cl_bytes = cell_list_bytes(p.nx, p.ny, p.nz, np, p.precision, loss_layout(p));
+  const size_t cl = take(cl_bytes > adj_work_bytes(p, np) ? cl_bytes : adj_work_bytes(p, np));
   const size_t io = take(sizeof(int32_t) * (size_t)np + 64);
   const size_t sp = take(sizeof(int32_t) * (size_t)np + 64);
   const size_t n32 = (fp32(p) && loss_layout(p)) ? take(sizeof(float) * (size_t)n_cells(p)) : 0;
@@ -259,11 +275,11 @@ Packets<T> caller_packets(const rsol_ctx* h) {
   return P;
 }
 
+// A sorted packet copy (the layout packet_copy_bytes sizes) starting at b.
 template <typename T>
-Packets<T> perm_packets(const rsol_ctx* h) {
+Packets<T> packets_at(const rsol_ctx* h, char* b) {
   Packets<T> P;
   P.np = h->np;
-  char* b = (char*)h->perm;
   const size_t n = (size_t)h->np;
   if constexpr (is_fp64<T>()) {
     P.x = (double*)b;
@@ -279,6 +295,17 @@ Packets<T> perm_packets(const rsol_ctx* h) {
     P.id = (int32_t*)(b + n * sizeof(int32_t) + 6 * n * sizeof(float));
   }
   return P;
+}
+
+template <typename T>
+Packets<T> perm_packets(const rsol_ctx* h) { return packets_at<T>(h, (char*)h->perm); }
+
+// The differentiation form's second sorted copy and its adjoint arrays (which = 0, 1).
+template <typename T>
+Packets<T> adj_packets2(const rsol_ctx* h) { return packets_at<T>(h, h->cells_base); }
+template <typename T>
+T* adj_lam(const rsol_ctx* h, int which) {
+  return (T*)(h->cells_base + align_up(packet_copy_bytes(h->p, h->np)) + which * align_up(adj_lam_bytes(h->p, h->np)));
 }
 
 int need(rsol_ctx* h, bool fields, bool packets) {
@@ -404,6 +431,155 @@ int do_step(rsol_ctx* h, int32_t nsteps, double* dM, double* dE, const GasLink& 
     h->steps_since_sort += 1;
     if (gas.rho) RSOL_HIP(h, launch_gas_field(gas, n_cells(h->p), h->stream), "gas field");
   }
+  return RSOL_OK;
+}
+
+// ---------------------------------------------------------------- differentiation form
+// Recorded steps come in blocks of kAdjBlock.  At the start of each block the packets are
+// counting-sorted by tile (the first block from the caller's arrays, later ones from the
+// previous block's sorted copy, which is nearly in order already) and the block's steps
+// run on that sorted copy with each tile's fields staged in LDS.  A step's slab holds
+// the starting state in its block's order; the first slab of a block also holds the
+// block's order (caller index of each position), its bin offsets and, once the next
+// block is sorted, the position of each of its packets in the next block's order.  The
+// reverse sweep keeps the adjoints in the same orders, so no per-packet access in
+// either direction goes through a permutation except at block boundaries.
+constexpr int kAdjBlock = 4;
+constexpr int kAdjHalo = 2;
+
+struct SlabLayout {
+  size_t state, order, next, offsets, total;
+};
+
+SlabLayout slab_layout(const rsol_ctx* h) {
+  SlabLayout L;
+  const size_t n = (size_t)h->np;
+  L.state = 0;
+  size_t off = align_up(n * (fp32(h->p) ? 7 * sizeof(float) : 6 * sizeof(double)));
+  L.order = off;
+  off = align_up(off + n * sizeof(int32_t));
+  L.next = off;
+  off = align_up(off + n * sizeof(int32_t));
+  L.offsets = off;
+  off = align_up(off + ((size_t)h->tiling.nbins() + 1) * sizeof(int32_t));
+  L.total = off;
+  return L;
+}
+
+bool adj_tiled(const rsol_ctx* h) {
+  return step_backward_tiled_fits(h->tiling, kAdjHalo) && step_record_tiled_fits(h->tiling, kAdjHalo);
+}
+
+// View of the packet state stored in a slab (ids unused).
+template <typename T>
+Packets<T> slab_packets(const rsol_ctx* h, const char* at) {
+  Packets<T> P;
+  P.np = h->np;
+  P.id = nullptr;
+  if constexpr (is_fp64<T>()) {
+    P.x = (double*)at;
+    P.cell = nullptr;
+    P.off = nullptr;
+    P.u = (T*)at + 3 * h->np;
+  } else {
+    P.x = nullptr;
+    P.cell = (int32_t*)at;
+    P.off = (float*)at + h->np;
+    P.u = (T*)at + 4 * h->np;
+  }
+  return P;
+}
+
+template <typename T>
+const T* adj_E(const rsol_ctx* h) { if constexpr (is_fp64<T>()) return h->E; else return h->E32; }
+template <typename T>
+const T* adj_B(const rsol_ctx* h) { if constexpr (is_fp64<T>()) return h->B; else return h->B32; }
+
+template <typename T>
+int record_global(rsol_ctx* h, int32_t nsteps, char* states, const RunConsts& k) {
+  const SlabLayout sl = slab_layout(h);
+  for (int32_t n = 0; n < nsteps; ++n)
+    RSOL_HIP(h, launch_step_record<T>(h->p.shape, caller_packets<T>(h), adj_E<T>(h), adj_B<T>(h),
+                                      states + (size_t)n * sl.total + sl.state, k, h->stream), "record step");
+  return RSOL_OK;
+}
+
+template <typename T>
+int record_tiled(rsol_ctx* h, int32_t nsteps, char* states, const RunConsts& k) {
+  const SlabLayout sl = slab_layout(h);
+  const size_t n_words = (size_t)h->np * sizeof(int32_t);
+  const size_t bin_words = ((size_t)h->tiling.nbins() + 1) * sizeof(int32_t);
+  Packets<T> cur = perm_packets<T>(h), nxt = adj_packets2<T>(h);
+  RSOL_HIP(h, launch_iota(h->iota, h->np, h->stream), "iota");
+  for (int32_t n = 0; n < nsteps; ++n) {
+    char* slab = states + (size_t)n * sl.total;
+    if (n % kAdjBlock == 0) {
+      if (n == 0) {
+        Packets<T> src = caller_packets<T>(h);
+        src.id = h->iota;
+        src.w = nullptr;
+        RSOL_HIP(h, launch_sort<T>(src, cur, k, h->tiling, h->sort_ints, h->stream), "record sort");
+      } else {
+        int32_t* pos = (int32_t*)(states + (size_t)(n - kAdjBlock) * sl.total + sl.next);
+        RSOL_HIP(h, launch_sort<T>(cur, nxt, k, h->tiling, h->sort_ints, h->stream, pos), "record sort");
+        const Packets<T> t = cur;
+        cur = nxt;
+        nxt = t;
+      }
+      RSOL_HIP(h, hipMemcpyAsync(slab + sl.order, cur.id, n_words, hipMemcpyDeviceToDevice, h->stream), "record order");
+      RSOL_HIP(h, hipMemcpyAsync(slab + sl.offsets, h->sort_ints, bin_words, hipMemcpyDeviceToDevice, h->stream),
+               "record offsets");
+    }
+    RSOL_HIP(h, launch_step_record_tiled<T>(h->p.shape, cur, slab + sl.state, h->sort_ints, h->tiling, kAdjHalo,
+                                            adj_E<T>(h), adj_B<T>(h), k, h->stream), "record step");
+  }
+  RSOL_HIP(h, launch_unsort<T>(cur, caller_packets<T>(h), h->stream), "record unsort");
+  return RSOL_OK;
+}
+
+template <typename T>
+int backward_global(rsol_ctx* h, int32_t nsteps, const char* states, T* lam_x, T* lam_u, const double* lam_dM,
+                    const double* lam_dE, double* gE, double* gB, const RunConsts& k) {
+  const SlabLayout sl = slab_layout(h);
+  for (int32_t n = nsteps - 1; n >= 0; --n)
+    RSOL_HIP(h, launch_step_backward<T>(h->p.shape, states + (size_t)n * sl.total + sl.state, h->np, lam_x, lam_u,
+                                        adj_E<T>(h), adj_B<T>(h), lam_dM, lam_dE, gE, gB, k, h->stream),
+             "step backward");
+  return RSOL_OK;
+}
+
+template <typename T>
+int backward_tiled(rsol_ctx* h, int32_t nsteps, const char* states, T* lam_x, T* lam_u, const double* lam_dM,
+                   const double* lam_dE, double* gE, double* gB, const RunConsts& k) {
+  const SlabLayout sl = slab_layout(h);
+  const int64_t np = h->np;
+  T* L0 = adj_lam<T>(h, 0);
+  T* L1 = adj_lam<T>(h, 1);
+  auto first_slab = [&](int b) { return states + (size_t)b * kAdjBlock * sl.total; };
+  int block = (nsteps - 1) / kAdjBlock;
+  // the caller's adjoints into the last block's order
+  const int32_t* order = (const int32_t*)(first_slab(block) + sl.order);
+  RSOL_HIP(h, launch_permute_rows<T>(lam_x, L0, order, np, 3, false, h->stream), "adjoint gather");
+  RSOL_HIP(h, launch_permute_rows<T>(lam_u, L0 + 3 * np, order, np, 3, false, h->stream), "adjoint gather");
+  for (int32_t n = nsteps - 1; n >= 0; --n) {
+    const int b = n / kAdjBlock;
+    if (b != block) {
+      // from block b+1's order into block b's: position j of block b sits at next[j]
+      const int32_t* next = (const int32_t*)(first_slab(b) + sl.next);
+      RSOL_HIP(h, launch_permute_rows<T>(L0, L1, next, np, 6, false, h->stream), "adjoint reorder");
+      T* t = L0;
+      L0 = L1;
+      L1 = t;
+      block = b;
+    }
+    const int32_t* offsets = (const int32_t*)(first_slab(b) + sl.offsets);
+    RSOL_HIP(h, launch_step_backward_tiled<T>(h->p.shape, slab_packets<T>(h, states + (size_t)n * sl.total + sl.state),
+                                              offsets, h->tiling, kAdjHalo, h->spill, L0, L0 + 3 * np, adj_E<T>(h),
+                                              adj_B<T>(h), lam_dM, lam_dE, gE, gB, k, h->stream), "step backward");
+  }
+  const int32_t* order0 = (const int32_t*)(states + sl.order);
+  RSOL_HIP(h, launch_permute_rows<T>(L0, lam_x, order0, np, 3, true, h->stream), "adjoint scatter");
+  RSOL_HIP(h, launch_permute_rows<T>(L0 + 3 * np, lam_u, order0, np, 3, true, h->stream), "adjoint scatter");
   return RSOL_OK;
 }
 
@@ -722,7 +898,7 @@ int rsol_set_flags(rsol_handle h, int32_t flags) {
 
 size_t rsol_state_bytes(rsol_handle h) {
   if (!h) return 0;
-  return (size_t)h->np * (fp32(h->p) ? 7 * sizeof(float) : 6 * sizeof(double));
+  return slab_layout(h).total;
 }
 
 int rsol_record_states(rsol_handle h, int32_t nsteps, void* states) {
@@ -735,18 +911,11 @@ int rsol_record_states(rsol_handle h, int32_t nsteps, void* states) {
   if (h->np == 0 || nsteps == 0) return RSOL_OK;
   if (!states) return fail(h, RSOL_EINVAL, "states is NULL");
   const RunConsts k = consts(h);
-  const size_t slab = rsol_state_bytes(h);
-  for (int32_t n = 0; n < nsteps; ++n) {
-    void* at = (char*)states + (size_t)n * slab;
-    if (fp32(h->p))
-      RSOL_HIP(h, launch_step_record<float>(h->p.shape, caller_packets<float>(h), h->E32, h->B32, at, k, h->stream),
-               "record step");
-    else
-      RSOL_HIP(h, launch_step_record<double>(h->p.shape, caller_packets<double>(h), h->E, h->B, at, k, h->stream),
-               "record step");
-  }
   h->sorted_valid = false;
-  return RSOL_OK;
+  if (fp32(h->p)) return adj_tiled(h) ? record_tiled<float>(h, nsteps, (char*)states, k)
+                                      : record_global<float>(h, nsteps, (char*)states, k);
+  return adj_tiled(h) ? record_tiled<double>(h, nsteps, (char*)states, k)
+                      : record_global<double>(h, nsteps, (char*)states, k);
 }
 
 int rsol_step_backward(rsol_handle h, int32_t nsteps, const void* states, void* lam_x, void* lam_u,
@@ -761,72 +930,16 @@ int rsol_step_backward(rsol_handle h, int32_t nsteps, const void* states, void* 
   if (h->np == 0 || nsteps == 0) return RSOL_OK;
   if (!states || !lam_x || !lam_u || !gE || !gB) return fail(h, RSOL_EINVAL, "NULL pointer");
   const RunConsts k = consts(h);
-  const size_t slab = rsol_state_bytes(h);
-  // Take packets tile by tile so that dL/dE, dL/dB accumulate in LDS: a counting sort of
-  // the recorded packet indices by tile, computed from the starting state of every
-  // kAdjSortEvery-th reversed step and reused for the following ones (a two-cell halo
-  // covers what packets move in between; packets beyond it fall back to global atomics).
-  constexpr int kAdjSortEvery = 4;
-  int halo = 0, every = 1;
-  if (step_backward_tiled_fits(h->tiling, 2)) {
-    halo = 2;
-    every = kAdjSortEvery;
-  } else if (step_backward_tiled_fits(h->tiling, 1)) {
-    halo = 1;
-  }
-  const bool tiled = halo > 0;
-  if (tiled) RSOL_HIP(h, launch_iota(h->iota, h->np, h->stream), "iota");
-  for (int32_t n = nsteps - 1; n >= 0; --n) {
-    const void* at = (const char*)states + (size_t)n * slab;
-    const bool resort = (nsteps - 1 - n) % every == 0;
-    if (fp32(h->p)) {
-      Packets<float> src;
-      src.np = h->np;
-      src.x = nullptr;
-      src.cell = (int32_t*)at;
-      src.off = (float*)at + h->np;
-      src.u = (float*)at + 4 * h->np;
-      src.id = h->iota;
-      if (tiled) {
-        Packets<float> ord = perm_packets<float>(h);
-        ord.x = nullptr;
-        ord.cell = nullptr;
-        ord.off = nullptr;
-        ord.u = nullptr;
-        if (resort)
-          RSOL_HIP(h, launch_sort<float>(src, ord, k, h->tiling, h->sort_ints, h->stream), "adjoint sort");
-        RSOL_HIP(h, launch_step_backward_tiled<float>(h->p.shape, src, ord.id, h->sort_ints, h->tiling, halo,
-                                                      h->spill, (float*)lam_x, (float*)lam_u, h->E32, h->B32, lam_dM, lam_dE,
-                                                      gE, gB, k, h->stream), "step backward");
-      } else {
-        RSOL_HIP(h, launch_step_backward<float>(h->p.shape, at, h->np, (float*)lam_x, (float*)lam_u, h->E32, h->B32,
-                                                lam_dM, lam_dE, gE, gB, k, h->stream), "step backward");
-      }
-    } else {
-      Packets<double> src;
-      src.np = h->np;
-      src.x = (double*)at;
-      src.cell = nullptr;
-      src.off = nullptr;
-      src.u = (double*)at + 3 * h->np;
-      src.id = h->iota;
-      if (tiled) {
-        Packets<double> ord = perm_packets<double>(h);
-        ord.x = nullptr;
-        ord.u = nullptr;
-        if (resort)
-          RSOL_HIP(h, launch_sort<double>(src, ord, k, h->tiling, h->sort_ints, h->stream), "adjoint sort");
-        RSOL_HIP(h, launch_step_backward_tiled<double>(h->p.shape, src, ord.id, h->sort_ints, h->tiling, halo,
-                                                       h->spill, (double*)lam_x, (double*)lam_u, h->E, h->B, lam_dM, lam_dE,
-                                                       gE, gB, k, h->stream), "step backward");
-      } else {
-        RSOL_HIP(h, launch_step_backward<double>(h->p.shape, at, h->np, (double*)lam_x, (double*)lam_u, h->E, h->B,
-                                                 lam_dM, lam_dE, gE, gB, k, h->stream), "step backward");
-      }
-    }
-  }
   h->sorted_valid = false;
-  return RSOL_OK;
+  if (fp32(h->p))
+    return adj_tiled(h) ? backward_tiled<float>(h, nsteps, (const char*)states, (float*)lam_x, (float*)lam_u, lam_dM,
+                                                lam_dE, gE, gB, k)
+                        : backward_global<float>(h, nsteps, (const char*)states, (float*)lam_x, (float*)lam_u, lam_dM,
+                                                 lam_dE, gE, gB, k);
+  return adj_tiled(h) ? backward_tiled<double>(h, nsteps, (const char*)states, (double*)lam_x, (double*)lam_u, lam_dM,
+                                               lam_dE, gE, gB, k)
+                      : backward_global<double>(h, nsteps, (const char*)states, (double*)lam_x, (double*)lam_u, lam_dM,
+                                                lam_dE, gE, gB, k);
 }
 
 int rsol_moments_backward(rsol_handle h, const double* lam_rho, const double* lam_P, const double* lam_e,

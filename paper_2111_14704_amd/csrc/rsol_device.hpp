@@ -47,6 +47,13 @@ __device__ __forceinline__ int wrap_index(int i, int n) {
   return i < 0 ? i + n : (i >= n ? i - n : i);
 }
 
+// Periodic index for any offset (a staged region's border can reach past one period
+// of a grid only a cell or two wide).
+__device__ __forceinline__ int wrap_mod(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
 // Axis weights from a home cell and the in-cell offset f = x/dx - home in [0, 1).
 // CIC: nodes base, base+1 with base = floor(x/dx - 1/2).
 // TSC: nodes home-1, home, home+1 with d = f - 1/2.
