@@ -77,7 +77,11 @@ typedef struct rsol_params {
                                    differentiation form runs so                               */
 #define RSOL_FLAG_TILED 2       /* rsol_step runs the tiled LDS kernel over packets re-sorted
                                    every sort_every steps instead of the default cell-list
-                                   kernel (ignored under RSOL_FLAG_KEEP_ORDER)                */
+                                   kernel (ignored under RSOL_FLAG_KEEP_ORDER).  The tiles of
+                                   this path and of the differentiation form are 4x4x4 cells;
+                                   the environment variable RSOL_TILE="tx,ty,tz" (read when a
+                                   handle is created or sized) sets another shape, with
+                                   tx*ty*tz <= 256                                           */
 #define RSOL_FLAG_NAIVE 4       /* contrast mode: the naive substitution of c by c_tilde that
                                    the RSOL formulation replaces (Sec. 1; Sec. 5, items (1)-(4)).
                                    u = gamma v / c_tilde with du/dt = (q/(m c)) [(c/c_tilde) E +

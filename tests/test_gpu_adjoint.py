@@ -78,10 +78,11 @@ def test_adjoint_matches_oracle_small(precision, tol):
 
 def test_adjoint_with_packets_outrunning_the_halo():
     """Three times the Courant timestep (0.9 cells per step) on a 16^3 grid: between the
-    tile re-sorts of the reverse sweep (every fourth step) packets move further than the
-    two-cell halo of the tiled reverse kernel, so many take the global stray path; the
-    gradients still match the oracle's complex step (64 sampled coordinates, 12 steps,
-    checkpoints every 4)."""
+    tile sorts of the recorded blocks (every fourth step) packets move further than the
+    two-cell halo of the tiled kernels, so many gather from the grid while recording and
+    take the global stray path in the reverse sweep; the gradients still match the
+    oracle's complex step (64 sampled coordinates, 12 steps, checkpoints every 6: a full
+    block and a partial one per segment)."""
     w = make_workload(5, n=16, ppc=2, nsteps=12)
     p = oracle_params(w)
     p.dt *= 3.0
@@ -92,9 +93,30 @@ def test_adjoint_with_packets_outrunning_the_halo():
     touch = adjoint.packets_touching(w.x, w.u, E, B, p, 12, cells)
     g_cs, L0 = adjoint.complex_step_grad(w.x, w.u, E, B, p, 12, T, coords, touch)
     _say("adjoint with strays (3x Courant dt)")
-    g = _gpu_grads(w, p.dt, 12, 4)
+    g = _gpu_grads(w, p.dt, 12, 6)
     err = _errors(_pick(g, coords), g_cs)
     _say(f"adjoint strays: L rel {abs(g['L'] - L0) / L0:.2e}, max grad err {err.max():.2e}")
+    assert abs(g["L"] - L0) <= 1e-12 * L0
+    assert err.max() <= 1e-6
+
+
+def test_adjoint_in_caller_order_when_the_tile_region_does_not_fit(monkeypatch):
+    """With 8^3 tiles (RSOL_TILE) a tile and its two-cell halo exceed the LDS region, so
+    recording and reverse sweep run in the caller's order with global gathers and
+    atomics; the gradients match the oracle's complex step as in the tiled case."""
+    w = make_workload(5, n=8, ppc=4, nsteps=12)
+    p = oracle_params(w)
+    E, B = oracle_fields(w)
+    T = w.target.reshape(3, -1)
+    coords = w.grad_coords
+    cells = [c for k, _, c in coords if k != "u"]
+    touch = adjoint.packets_touching(w.x, w.u, E, B, p, 12, cells)
+    g_cs, L0 = adjoint.complex_step_grad(w.x, w.u, E, B, p, 12, T, coords, touch)
+    monkeypatch.setenv("RSOL_TILE", "8,8,8")
+    _say("adjoint in caller order (8^3 tiles)")
+    g = _gpu_grads(w, p.dt, 12, 6)
+    err = _errors(_pick(g, coords), g_cs)
+    _say(f"adjoint caller order: L rel {abs(g['L'] - L0) / L0:.2e}, max grad err {err.max():.2e}")
     assert abs(g["L"] - L0) <= 1e-12 * L0
     assert err.max() <= 1e-6
 
