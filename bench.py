@@ -19,7 +19,10 @@ workload's gas (exchange into the gas momentum and energy, E rebuilt every step)
 naive constants); "losses" = the FP64 step with catastrophic losses (packet weights
 in the cell lists, nucleon density gathered by the step); "pushers" = the FP64 step
 with the Vay and Higuera-Cary momentum updates;
-"backward" = the differentiation form;
+"backward" = the differentiation form, with a roofline over the whole backward pass
+(algorithmic bytes of the recompute and the reverse step per packet-step);
+"copy_gbs" in each roofline = a plain device-to-device copy's measured bandwidth on
+the same GPU, "frac_of_copy" the achieved bandwidth against it;
 "cpu_baseline" = the CPU oracle timed on a bounded sample of the same workload.
 """
 
@@ -59,6 +62,41 @@ def algorithmic_bytes_per_packet_step(precision, ppc):
         packet = 2 * (4 + 3 * 4 + 3 * 4)       # cell, offset, u read + write
         cell = 6 * 4 + 2 * 4 * 8               # FP32 E, B read; FP64 exchange read + write
     return packet + cell / ppc
+
+
+def algorithmic_bytes_backward(precision, ppc):
+    """Bytes one packet-step of the backward pass must move at minimum (checkpoints every
+    16 steps): the recompute reads and writes the state and stores it, the reverse step
+    reads the stored state and reads and writes the adjoint; per cell both passes read
+    the fields and the reverse step read-modify-writes dL/dE, dL/dB (FP64)."""
+    if precision == "fp64":
+        packet = 3 * 48 + 3 * 48
+        cell = 2 * 48 + 2 * 48
+    else:
+        packet = 3 * 28 + 28 + 2 * 24         # state read, written, stored, read back; FP32 adjoint read + write
+        cell = 2 * 24 + 2 * 48
+    return packet + cell / ppc
+
+
+def copy_bandwidth(nbytes=1 << 31, reps=5):
+    """Achieved bandwidth of a plain device-to-device copy (torch copy_) of nbytes, in GB/s
+    counting the bytes read and written; median of reps timed copies."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    times = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b) / 1e3)
+    del src, dst
+    torch.cuda.empty_cache()
+    times.sort()
+    return 2 * nbytes / times[len(times) // 2] / 1e9
 
 
 def measured_traffic(precision, workload):
@@ -171,8 +209,14 @@ def time_backward(precision, nsteps=256, ckpt=16):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     npk = w.n_particles
-    return dict(workload=w.name, dtype="f64" if precision == "fp64" else "f32", value=npk * nsteps / (t2 - t1),
-                unit="particle-updates/s", backward_s=t2 - t1, forward_s=t1 - t0, steps=nsteps, ckpt=ckpt)
+    value = npk * nsteps / (t2 - t1)
+    balg = algorithmic_bytes_backward(precision, w.ppc)
+    achieved = balg * value / 1e9
+    return dict(workload=w.name, dtype="f64" if precision == "fp64" else "f32", value=value,
+                unit="particle-updates/s", backward_s=t2 - t1, forward_s=t1 - t0, steps=nsteps, ckpt=ckpt,
+                roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                              frac=achieved / HBM_PEAK_GBS, traffic=None, bytes_per_packet_step=balg,
+                              scope="whole backward pass"))
 
 
 def cpu_baseline(w, sample=131072, steps=6):
@@ -252,7 +296,7 @@ def main():
         bwd = time_backward("fp64")
         print(f"[bench] backward fp64 {bwd['value']:.3e} upd/s", file=sys.stderr, flush=True)
         b32 = time_backward("fp32")
-        bwd["fp32"] = dict(value=b32["value"], backward_s=b32["backward_s"])
+        bwd["fp32"] = dict(value=b32["value"], backward_s=b32["backward_s"], roofline=b32["roofline"])
         print(f"[bench] backward fp32 {b32['value']:.3e} upd/s", file=sys.stderr, flush=True)
     rc = None
     if not args.no_coupled:
@@ -278,6 +322,12 @@ def main():
             rp[name] = dict(value=r["value"], ms_per_step=r["ms_per_step"], kernel_ms=r["kernel_ms"], dtype="f64")
             print(f"[bench] {name} pusher fp64 {r['value']:.3e} upd/s, kernel {r['kernel_ms']:.3f} ms",
                   file=sys.stderr, flush=True)
+    copy_gbs = copy_bandwidth()
+    print(f"[bench] device copy {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    for r in (r64, r32, bwd, bwd and bwd.get("fp32")):
+        if r:
+            r["roofline"]["copy_gbs"] = copy_gbs
+            r["roofline"]["frac_of_copy"] = r["roofline"]["achieved"] / copy_gbs
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w)
