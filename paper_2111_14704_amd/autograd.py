@@ -12,7 +12,8 @@ gather, whose adjoint is a scatter into dL/dE and dL/dB).  Checkpoints are taken
 Packet order: the packets are re-binned once (rank-major cell order, so neighbouring
 lanes sit in different cells) and then kept in that order for the whole rollout so
 checkpoints, stored states and adjoint arrays stay aligned; gradients are returned in
-the caller's packet order.
+the caller's packet order.  (Inside the library the recompute and the reverse sweep
+work on copies sorted by tile every four steps; the arrays seen here keep their order.)
 """
 
 from __future__ import annotations
