@@ -142,9 +142,9 @@ struct TileAccess {
   const double* L;   // [4][kAdjRegion] exchange cotangents, or NULL
   double* G;         // [6][kAdjRegion] dL/dE then dL/dB accumulators
   int ox, oy, oz;    // grid coordinates of region cell 0
-  int rx, ry;        // region extents along x and y
+  int rx, pz;        // region extent along x (the row pitch) and plane pitch
   __device__ __forceinline__ int64_t node(const int base[3], int cx, int cy, int cz) const {
-    return (base[0] + cx - ox) + rx * ((base[1] + cy - oy) + ry * (base[2] + cz - oz));
+    return region_index(base[0] + cx - ox, base[1] + cy - oy, base[2] + cz - oz, rx, pz);
   }
   __device__ __forceinline__ T e(int64_t n, int c) const { return F[c * kAdjRegion + n]; }
   __device__ __forceinline__ T b(int64_t n, int c) const { return F[(3 + c) * kAdjRegion + n]; }
@@ -344,15 +344,15 @@ __global__ void __launch_bounds__(kBlock) step_backward_kernel(const void* __res
   }
 }
 
-// Reverse of one step with the packets grouped by tile.  `order` lists the packets
-// (their indices in the recorded order) tile by tile, `offsets` the first entry of each
-// tile (a counting sort of a recorded state of this step or of a step up to a few steps
-// later).  Each workgroup takes one part of one tile's packets, stages the fields of the
-// tile plus a halo of `halo` cells in LDS, accumulates dL/dE, dL/dB there and adds the
-// region to the grid with one atomic per node and component.  A packet reads its state
-// from the step's slab through `order`; one whose stencil leaves the region (it moved
-// further than the halo allows since the sort) is appended to `spill` (count in
-// spill[0], packet indices after it) for step_backward_list_kernel.
+// Reverse of one step with the packets held in tile order: tile t's packets are entries
+// [offsets[t*cells_per_tile], offsets[(t+1)*cells_per_tile]) of the slab and of lam_x,
+// lam_u (a counting sort of a recorded state of this step or of one up to a few steps
+// earlier).  Each workgroup takes one part of one tile's packets, stages the fields of
+// the tile plus a halo of `halo` cells in LDS, accumulates dL/dE, dL/dB there and adds
+// the region to the grid with one atomic per node and component.  A packet whose
+// stencil leaves the region (it moved further than the halo allows since the sort) is
+// appended to `spill` (count in spill[0], packet indices after it) for
+// step_backward_list_kernel.
 template <int M, typename T>
 __global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> slab,
                                                                      const int32_t* __restrict__ offsets, Tiling tl,
@@ -375,26 +375,28 @@ __global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> 
   const int rx = tl.tx + 2 * halo, ry = tl.ty + 2 * halo, rz = tl.tz + 2 * halo;
   const int rext[3] = {rx, ry, rz};
   const int rc = rx * ry * rz;
+  const int pz = region_plane_pitch(rx, ry);
   const int64_t nc = k.ncells, np = slab.np;
   const bool ld = lam_dM != nullptr;
   for (int r = threadIdx.x; r < rc; r += blockDim.x) {
     const int ax = r % rx, ay = (r / rx) % ry, az = r / (rx * ry);
     const int64_t g = wrap_mod(ox + ax, k.nx) + (int64_t)k.nx * (wrap_mod(oy + ay, k.ny) + (int64_t)k.ny * wrap_mod(oz + az, k.nz));
+    const int s = region_index(ax, ay, az, rx, pz);
     #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      Fs[d * kAdjRegion + r] = E[d * nc + g];
-      Fs[(3 + d) * kAdjRegion + r] = B[d * nc + g];
+      Fs[d * kAdjRegion + s] = E[d * nc + g];
+      Fs[(3 + d) * kAdjRegion + s] = B[d * nc + g];
     }
     if (ld) {
       #pragma unroll
-      for (int d = 0; d < 3; ++d) Ls[d * kAdjRegion + r] = lam_dM[d * nc + g];
-      Ls[3 * kAdjRegion + r] = lam_dE ? lam_dE[g] : 0.0;
+      for (int d = 0; d < 3; ++d) Ls[d * kAdjRegion + s] = lam_dM[d * nc + g];
+      Ls[3 * kAdjRegion + s] = lam_dE ? lam_dE[g] : 0.0;
     }
     #pragma unroll
-    for (int d = 0; d < 6; ++d) Gs[d * kAdjRegion + r] = 0.0;
+    for (int d = 0; d < 6; ++d) Gs[d * kAdjRegion + s] = 0.0;
   }
   __syncthreads();
-  const TileAccess<T> acc{Fs, ld ? Ls : nullptr, Gs, ox, oy, oz, rx, ry};
+  const TileAccess<T> acc{Fs, ld ? Ls : nullptr, Gs, ox, oy, oz, rx, pz};
   // offsets come from a recorded slab: keep the range inside the arrays whatever they hold
   int64_t b0 = offsets[tile * tl.cells_per_tile], b1 = offsets[(tile + 1) * tl.cells_per_tile];
   b0 = b0 < 0 ? 0 : (b0 > np ? np : b0);
@@ -438,9 +440,10 @@ __global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> 
   for (int r = threadIdx.x; r < rc; r += blockDim.x) {
     const int ax = r % rx, ay = (r / rx) % ry, az = r / (rx * ry);
     const int64_t g = wrap_mod(ox + ax, k.nx) + (int64_t)k.nx * (wrap_mod(oy + ay, k.ny) + (int64_t)k.ny * wrap_mod(oz + az, k.nz));
+    const int s = region_index(ax, ay, az, rx, pz);
     #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const double ge = Gs[d * kAdjRegion + r], gb = Gs[(3 + d) * kAdjRegion + r];
+      const double ge = Gs[d * kAdjRegion + s], gb = Gs[(3 + d) * kAdjRegion + s];
       if (ge != 0.0) atomicAdd(&gE[d * nc + g], ge);
       if (gb != 0.0) atomicAdd(&gB[d * nc + g], gb);
     }
@@ -610,7 +613,7 @@ hipError_t launch_step_backward(int shape, const void* slab, int64_t np, T* lam_
 }
 
 bool step_backward_tiled_fits(const Tiling& t, int halo) {
-  return halo >= 1 && (t.tx + 2 * halo) * (t.ty + 2 * halo) * (t.tz + 2 * halo) <= kAdjRegion;
+  return halo >= 1 && region_span(t.tx + 2 * halo, t.ty + 2 * halo, t.tz + 2 * halo) <= kAdjRegion;
 }
 
 hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t s) {

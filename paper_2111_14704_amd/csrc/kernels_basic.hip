@@ -437,15 +437,17 @@ __global__ void __launch_bounds__(kBlock) step_record_tiled_kernel(Packets<T> P,
   const int o[3] = {t0[0] - halo, t0[1] - halo, t0[2] - halo};
   const int rext[3] = {tl.tx + 2 * halo, tl.ty + 2 * halo, tl.tz + 2 * halo};
   const int rc = rext[0] * rext[1] * rext[2];
+  const int pz = region_plane_pitch(rext[0], rext[1]);
   const int64_t nc = k.ncells, np = P.np;
   for (int r = threadIdx.x; r < rc; r += blockDim.x) {
     const int ax = r % rext[0], ay = (r / rext[0]) % rext[1], az = r / (rext[0] * rext[1]);
     const int64_t g = wrap_mod(o[0] + ax, k.nx) +
                       (int64_t)k.nx * (wrap_mod(o[1] + ay, k.ny) + (int64_t)k.ny * wrap_mod(o[2] + az, k.nz));
+    const int s = region_index(ax, ay, az, rext[0], pz);
     #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      Fs[d * kAdjRegion + r] = E[d * nc + g];
-      Fs[(3 + d) * kAdjRegion + r] = B[d * nc + g];
+      Fs[d * kAdjRegion + s] = E[d * nc + g];
+      Fs[(3 + d) * kAdjRegion + s] = B[d * nc + g];
     }
   }
   __syncthreads();
@@ -486,7 +488,7 @@ __global__ void __launch_bounds__(kBlock) step_record_tiled_kernel(Packets<T> P,
           const T wyz = ay.w[cy] * az.w[cz];
           #pragma unroll
           for (int cx = 0; cx < M; ++cx) {
-            const int node = (ax.base + cx - o[0]) + rext[0] * ((ay.base + cy - o[1]) + rext[1] * (az.base + cz - o[2]));
+            const int node = region_index(ax.base + cx - o[0], ay.base + cy - o[1], az.base + cz - o[2], rext[0], pz);
             const T w = ax.w[cx] * wyz;
             #pragma unroll
             for (int d = 0; d < 3; ++d) {
@@ -668,7 +670,7 @@ hipError_t launch_step_record(int shape, const Packets<T>& P, const T* E, const 
 }
 
 bool step_record_tiled_fits(const Tiling& t, int halo) {
-  return halo >= 1 && (t.tx + 2 * halo) * (t.ty + 2 * halo) * (t.tz + 2 * halo) <= kAdjRegion;
+  return halo >= 1 && region_span(t.tx + 2 * halo, t.ty + 2 * halo, t.tz + 2 * halo) <= kAdjRegion;
 }
 
 template <typename T>

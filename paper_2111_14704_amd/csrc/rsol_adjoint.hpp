@@ -10,9 +10,23 @@
 
 namespace rsol {
 
-// Cells of the LDS region the tiled kernels of the differentiation form stage: a 4x4x4
-// tile with a two-cell halo.
-constexpr int kAdjRegion = 512;
+// LDS slots per field component of the region the tiled kernels of the differentiation
+// form stage (a 4x4x4 tile with a two-cell halo, laid out by region_index).
+constexpr int kAdjRegion = 600;
+
+// Layout of a staged region of rx x ry x rz cells: x fastest, rows of rx, planes padded
+// to a pitch of 12 (mod 32) elements.  A wave's 64 lanes hold packets of the 64 cells of
+// one tile (the sort orders a tile rank-major); with planes of 64 elements the four
+// z-layers of the tile would fall on the same LDS banks.
+__host__ __device__ inline int region_plane_pitch(int rx, int ry) {
+  const int p = rx * ry;
+  return p + ((12 - p % 32) % 32 + 32) % 32;
+}
+__host__ __device__ inline int region_index(int ax, int ay, int az, int rx, int pz) { return ax + rx * ay + pz * az; }
+// Slots a region of rx x ry x rz cells spans.
+__host__ __device__ inline int region_span(int rx, int ry, int rz) {
+  return region_plane_pitch(rx, ry) * (rz - 1) + rx * ry;
+}
 
 // Reverse of one step whose starting state is in `slab`: lam_x, lam_u [3][np] hold
 // dL/d(state after) on entry and dL/d(state before) on exit; gE, gB [3][n_cells] and
