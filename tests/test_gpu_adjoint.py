@@ -272,3 +272,45 @@ def test_workload5_full_size_matches_oracle_golden():
     assert abs(g["L"] - gold["loss"]) <= 1e-10 * gold["loss"]
     assert e_cs.max() <= 1e-6
     assert ok_fd.sum() >= 16 and e_fd.max() <= 1e-6
+
+
+def test_reverse_sweep_over_a_prefix_of_the_recorded_steps():
+    """rsol_step_backward over the first 6 of 9 recorded steps (a block of four and part of
+    the next) gives the gradients of recording and reversing those 6 steps alone; and
+    recording leaves the caller's packets advanced by all its steps in their own order
+    (the states of 9 keep-order steps)."""
+    import torch
+    from paper_2111_14704_amd.sim import Simulation
+    w = make_workload(5, n=8, ppc=4, nsteps=9)
+    p = oracle_params(w)
+    rng = np.random.default_rng(11)
+    lam_x0 = rng.standard_normal((3, w.n_particles))
+    lam_u0 = rng.standard_normal((3, w.n_particles))
+    lam_dM = rng.standard_normal((3, w.n_cells))
+
+    def run(nrec, nrev):
+        sim = Simulation.from_workload(w, dt=p.dt, flags=1)
+        h = sim.handle
+        states = torch.empty(h.rsol_state_bytes() * nrec, dtype=torch.uint8, device="cuda")
+        h.rsol_record_states(nrec, states)
+        lx = torch.tensor(lam_x0, device="cuda")
+        lu = torch.tensor(lam_u0, device="cuda")
+        gE, gB = sim.zeros_grid(3), sim.zeros_grid(3)
+        h.rsol_step_backward(nrev, states, lx, lu, gE, gB, torch.tensor(lam_dM, device="cuda"))
+        h.rsol_check()
+        torch.cuda.synchronize()
+        x, u = sim.state_by_id()
+        return dict(lx=lx.cpu().numpy(), lu=lu.cpu().numpy(), gE=gE.cpu().numpy(), gB=gB.cpu().numpy(), x=x, u=u)
+
+    _say("adjoint over a prefix of the recorded steps")
+    a, b = run(9, 6), run(6, 6)
+    for key in ("lx", "lu", "gE", "gB"):
+        err = float(np.max(np.abs(a[key] - b[key])) / np.max(np.abs(b[key])))
+        _say(f"prefix {key}: {err:.2e}")
+        assert err <= 1e-12, (key, err)
+    ref = Simulation.from_workload(w, dt=p.dt, flags=1)
+    ref.step(9)
+    torch.cuda.synchronize()
+    xr, ur = ref.state_by_id()
+    assert float(np.max(np.abs(a["x"] - xr))) <= 1e-12 * max(w.box)
+    assert float(np.max(np.abs(a["u"] - ur) / np.abs(ur).max())) <= 1e-13
