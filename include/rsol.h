@@ -73,8 +73,13 @@ typedef struct rsol_params {
 
 /* flags */
 #define RSOL_FLAG_KEEP_ORDER 1  /* rsol_step keeps the packet order (never re-bins) and runs the
-                                   one-thread-per-packet kernel with global atomics; the
-                                   differentiation form runs so                               */
+                                   one-thread-per-packet kernel with global atomics.  When
+                                   dM and dE are both NULL (the differentiation form's forward
+                                   pass), with the Boris pusher and no losses, the steps run
+                                   instead on a scratch copy sorted by tile every four steps,
+                                   with each tile's E and B staged on chip (the same
+                                   arithmetic in the same order); the caller's arrays end in
+                                   their own order either way                                 */
 #define RSOL_FLAG_TILED 2       /* rsol_step runs the tiled LDS kernel over packets re-sorted
                                    every sort_every steps instead of the default cell-list
                                    kernel (ignored under RSOL_FLAG_KEEP_ORDER).  The tiles of

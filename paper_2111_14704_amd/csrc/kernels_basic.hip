@@ -420,8 +420,8 @@ __global__ void __launch_bounds__(kBlock) step_global_kernel(Packets<T> P, const
 // Recording step of the differentiation form on packets held in tile order (positions
 // [offsets[t*cells_per_tile], offsets[(t+1)*cells_per_tile]) belong to tile t): one
 // workgroup per part of a tile stages E and B of the tile plus a `halo`-cell border in
-// LDS; each packet's starting state goes to the state slab `rec` at its own position,
-// then the gather (the weights and summation order of step_global_kernel, so the
+// LDS; each packet's starting state goes to the state slab `rec` (when given) at its own
+// position, then the gather (the weights and summation order of step_global_kernel, so the
 // trajectory is the same to the bit), the Boris kick and the drift.  A packet whose
 // stencil has left the staged region since the sort gathers from the grid instead.
 template <int M, typename T>
@@ -463,7 +463,7 @@ __global__ void __launch_bounds__(kBlock) step_record_tiled_kernel(Packets<T> P,
     T f[3];
     load_position(P, j, k, home, f);
     const T ux = P.u[j], uy = P.u[np + j], uz = P.u[2 * np + j];
-    store_state<T>(rec, P, j);
+    if (rec) store_state<T>(rec, P, j);
     // home in the tile's unwrapped frame; the stencil spans home-1 .. home+1
     bool inside = true;
     int hu[3];
@@ -677,7 +677,7 @@ template <typename T>
 hipError_t launch_step_record_tiled(int shape, const Packets<T>& P, void* slab, const int32_t* offsets,
                                     const Tiling& t, int halo, const T* E, const T* B, const RunConsts& k,
                                     hipStream_t s) {
-  if (!slab || !step_record_tiled_fits(t, halo)) return hipErrorInvalidValue;
+  if (!step_record_tiled_fits(t, halo)) return hipErrorInvalidValue;
   const int64_t ntiles = t.ntiles();
   const int64_t per_tile = (P.np + ntiles - 1) / (ntiles > 0 ? ntiles : 1);
   int parts = (int)((per_tile + 1023) / 1024);

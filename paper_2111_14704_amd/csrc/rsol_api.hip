@@ -399,11 +399,22 @@ int do_step_cells(rsol_ctx* h, int32_t nsteps, double* dM, double* dE, const Gas
   return RSOL_OK;
 }
 
+bool adj_tiled(const rsol_ctx* h);
+template <typename T>
+int record_tiled(rsol_ctx* h, int32_t nsteps, char* states, const RunConsts& k);
+
 template <typename T>
 int do_step(rsol_ctx* h, int32_t nsteps, double* dM, double* dE, const GasLink& gas) {
   if ((h->p.flags & (RSOL_FLAG_KEEP_ORDER | RSOL_FLAG_TILED)) == 0)
     return do_step_cells<T>(h, nsteps, dM, dE, gas);
   const RunConsts k = consts(h);
+  // keep-order steps that deposit nothing (the differentiation form's forward pass) run
+  // on tile-sorted copies with the fields staged per tile, as its recording does
+  if ((h->p.flags & RSOL_FLAG_KEEP_ORDER) && !dM && !dE && !gas.rho && pusher_of(h->p.flags) == kPushBoris &&
+      !h->have_losses && h->np > 0 && adj_tiled(h)) {
+    h->sorted_valid = false;
+    return record_tiled<T>(h, nsteps, nullptr, k);
+  }
   const bool global = (h->p.flags & RSOL_FLAG_KEEP_ORDER) != 0 || !h->plan.tiled;
   for (int32_t s = 0; s < nsteps; ++s) {
     if (global) {
@@ -504,6 +515,9 @@ int record_global(rsol_ctx* h, int32_t nsteps, char* states, const RunConsts& k)
   return RSOL_OK;
 }
 
+// Advance nsteps steps on tile-sorted copies (sorted every kAdjBlock steps) and return
+// the packets to the caller's arrays in their order; with states, record every step's
+// starting state and each block's ordering there.
 template <typename T>
 int record_tiled(rsol_ctx* h, int32_t nsteps, char* states, const RunConsts& k) {
   const SlabLayout sl = slab_layout(h);
@@ -512,7 +526,7 @@ int record_tiled(rsol_ctx* h, int32_t nsteps, char* states, const RunConsts& k) 
   Packets<T> cur = perm_packets<T>(h), nxt = adj_packets2<T>(h);
   RSOL_HIP(h, launch_iota(h->iota, h->np, h->stream), "iota");
   for (int32_t n = 0; n < nsteps; ++n) {
-    char* slab = states + (size_t)n * sl.total;
+    char* slab = states ? states + (size_t)n * sl.total : nullptr;
     if (n % kAdjBlock == 0) {
       if (n == 0) {
         Packets<T> src = caller_packets<T>(h);
@@ -520,18 +534,24 @@ int record_tiled(rsol_ctx* h, int32_t nsteps, char* states, const RunConsts& k) 
         src.w = nullptr;
         RSOL_HIP(h, launch_sort<T>(src, cur, k, h->tiling, h->sort_ints, h->stream), "record sort");
       } else {
-        int32_t* pos = (int32_t*)(states + (size_t)(n - kAdjBlock) * sl.total + sl.next);
+        int32_t* pos = states ? (int32_t*)(states + (size_t)(n - kAdjBlock) * sl.total + sl.next) : nullptr;
         RSOL_HIP(h, launch_sort<T>(cur, nxt, k, h->tiling, h->sort_ints, h->stream, pos), "record sort");
         const Packets<T> t = cur;
         cur = nxt;
         nxt = t;
       }
-      RSOL_HIP(h, hipMemcpyAsync(slab + sl.order, cur.id, n_words, hipMemcpyDeviceToDevice, h->stream), "record order");
-      RSOL_HIP(h, hipMemcpyAsync(slab + sl.offsets, h->sort_ints, bin_words, hipMemcpyDeviceToDevice, h->stream),
-               "record offsets");
+      if (slab) {
+        RSOL_HIP(h, hipMemcpyAsync(slab + sl.order, cur.id, n_words, hipMemcpyDeviceToDevice, h->stream),
+                 "record order");
+        RSOL_HIP(h, hipMemcpyAsync(slab + sl.offsets, h->sort_ints, bin_words, hipMemcpyDeviceToDevice, h->stream),
+                 "record offsets");
+      }
     }
-    RSOL_HIP(h, launch_step_record_tiled<T>(h->p.shape, cur, slab + sl.state, h->sort_ints, h->tiling, kAdjHalo,
-                                            adj_E<T>(h), adj_B<T>(h), k, h->stream), "record step");
+    auto ev = timed_begin(h);
+    RSOL_HIP(h, launch_step_record_tiled<T>(h->p.shape, cur, slab ? slab + sl.state : nullptr, h->sort_ints,
+                                            h->tiling, kAdjHalo, adj_E<T>(h), adj_B<T>(h), k, h->stream),
+             "record step");
+    timed_end(h, ev, false);
   }
   RSOL_HIP(h, launch_unsort<T>(cur, caller_packets<T>(h), h->stream), "record unsort");
   return RSOL_OK;

@@ -94,7 +94,8 @@ hipError_t launch_step_record(int shape, const Packets<T>& P, const T* E, const 
 // The same recording step with the packets held in tile order (tile t's packets at
 // [offsets[t*cells_per_tile], offsets[(t+1)*cells_per_tile]) of P, from a counting sort
 // at most a few steps old): E and B of each tile plus a `halo`-cell border are staged
-// in LDS, so gathers do not touch the grid.  Needs step_record_tiled_fits(t, halo).
+// in LDS, so gathers do not touch the grid; slab may be NULL (the step without
+// recording).  Needs step_record_tiled_fits(t, halo).
 struct Tiling;
 bool step_record_tiled_fits(const Tiling& t, int halo);
 template <typename T>
