@@ -339,6 +339,112 @@ __global__ void moments_kernel(Packets<T> P, double* __restrict__ rho, double* _
   }
 }
 
+// The same moments with the packets taken tile by tile through `order` (a counting
+// sort's permutation of the current state: tile t's packets are order[offsets[t*cpt]
+// .. offsets[(t+1)*cpt])).  Each workgroup accumulates one part of a tile's packets into
+// its tile plus a one-cell halo in FP64 LDS and adds the region to the grid with one
+// atomic per node and component.  A packet whose stencil the region does not hold (its
+// sort key and its home cell disagreeing by a rounding) deposits to the grid directly.
+template <int M, typename T>
+__global__ void __launch_bounds__(kBlock) moments_tiled_kernel(Packets<T> P, const int32_t* __restrict__ order,
+                                                               const int32_t* __restrict__ offsets, Tiling tl,
+                                                               int parts, double* __restrict__ rho,
+                                                               double* __restrict__ Pm, double* __restrict__ e,
+                                                               RunConsts k) {
+  __shared__ double Ms[5 * kAdjRegion];
+  const int64_t tile = blockIdx.x / parts;
+  const int part = blockIdx.x - (int)(tile * parts);
+  const int ttx = (int)(tile % tl.ntx), tty = (int)((tile / tl.ntx) % tl.nty), ttz = (int)(tile / ((int64_t)tl.ntx * tl.nty));
+  const int t0[3] = {ttx * tl.tx, tty * tl.ty, ttz * tl.tz};
+  const int o[3] = {t0[0] - 1, t0[1] - 1, t0[2] - 1};
+  const int rext[3] = {tl.tx + 2, tl.ty + 2, tl.tz + 2};
+  const int rc = rext[0] * rext[1] * rext[2];
+  const int pz = region_plane_pitch(rext[0], rext[1]);
+  const int64_t nc = k.ncells, np = P.np;
+  const double inv_v = 1.0 / (k.dx * k.dx * k.dx);
+  const double m = k.mass * inv_v, mc = k.mass * k.pc * inv_v, mcc = k.mass * k.pc * k.pc * inv_v;
+  for (int r = threadIdx.x; r < rc; r += blockDim.x) {
+    const int s = region_index(r % rext[0], (r / rext[0]) % rext[1], r / (rext[0] * rext[1]), rext[0], pz);
+    #pragma unroll
+    for (int c = 0; c < 5; ++c) Ms[c * kAdjRegion + s] = 0.0;
+  }
+  __syncthreads();
+  int64_t b0 = offsets[tile * tl.cells_per_tile], b1 = offsets[(tile + 1) * tl.cells_per_tile];
+  b0 = b0 < 0 ? 0 : (b0 > np ? np : b0);
+  b1 = b1 < b0 ? b0 : (b1 > np ? np : b1);
+  const int64_t len = b1 - b0;
+  const int64_t j0 = b0 + len * part / parts, j1 = b0 + len * (part + 1) / parts;
+  const int n3[3] = {k.nx, k.ny, k.nz};
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+    const int64_t i = order[j];
+    if (i < 0 || i >= np) continue;
+    int home[3];
+    T f[3];
+    load_position(P, i, k, home, f);
+    const double ux = (double)P.u[i], uy = (double)P.u[np + i], uz = (double)P.u[2 * np + i];
+    const double g = sqrt(1.0 + (ux * ux + uy * uy + uz * uz));
+    const double pw = P.w ? (double)P.w[i] : 1.0;
+    bool inside = true;
+    int hu[3];
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int hw = wrap_index(home[d], n3[d]);
+      int delta = hw - t0[d];
+      if (2 * delta >= n3[d]) delta -= n3[d];
+      else if (2 * delta < -n3[d]) delta += n3[d];
+      hu[d] = t0[d] + delta;
+      inside &= delta + 1 >= 1 && delta + 1 <= rext[d] - 2;
+    }
+    const AxisWeights<M, T> ax = axis_weights<M, T>(hu[0], f[0]), ay = axis_weights<M, T>(hu[1], f[1]),
+                            az = axis_weights<M, T>(hu[2], f[2]);
+    #pragma unroll
+    for (int cz = 0; cz < M; ++cz) {
+      #pragma unroll
+      for (int cy = 0; cy < M; ++cy) {
+        const double wyz = (double)ay.w[cy] * (double)az.w[cz];
+        #pragma unroll
+        for (int cx = 0; cx < M; ++cx) {
+          const double w = (double)ax.w[cx] * wyz * pw;
+          const double v[5] = {w * m, w * mc * ux, w * mc * uy, w * mc * uz, w * mcc * g};
+          if (inside) {
+            const int s = region_index(ax.base + cx - o[0], ay.base + cy - o[1], az.base + cz - o[2], rext[0], pz);
+            if (rho) atomicAdd(&Ms[s], v[0]);
+            if (Pm) {
+              atomicAdd(&Ms[kAdjRegion + s], v[1]);
+              atomicAdd(&Ms[2 * kAdjRegion + s], v[2]);
+              atomicAdd(&Ms[3 * kAdjRegion + s], v[3]);
+            }
+            if (e) atomicAdd(&Ms[4 * kAdjRegion + s], v[4]);
+          } else {
+            const int64_t node = wrap_mod(ax.base + cx, k.nx) +
+                                 (int64_t)k.nx * (wrap_mod(ay.base + cy, k.ny) + (int64_t)k.ny * wrap_mod(az.base + cz, k.nz));
+            if (rho) atomicAdd(&rho[node], v[0]);
+            if (Pm) {
+              atomicAdd(&Pm[node], v[1]);
+              atomicAdd(&Pm[nc + node], v[2]);
+              atomicAdd(&Pm[2 * nc + node], v[3]);
+            }
+            if (e) atomicAdd(&e[node], v[4]);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < rc; r += blockDim.x) {
+    const int ax = r % rext[0], ay = (r / rext[0]) % rext[1], az = r / (rext[0] * rext[1]);
+    const int s = region_index(ax, ay, az, rext[0], pz);
+    const int64_t node = wrap_mod(o[0] + ax, k.nx) +
+                         (int64_t)k.nx * (wrap_mod(o[1] + ay, k.ny) + (int64_t)k.ny * wrap_mod(o[2] + az, k.nz));
+    double* dst[5] = {rho, Pm, Pm ? Pm + nc : nullptr, Pm ? Pm + 2 * nc : nullptr, e};
+    #pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      const double v = Ms[c * kAdjRegion + s];
+      if (dst[c] && v != 0.0) atomicAdd(&dst[c][node], v);
+    }
+  }
+}
+
 // Fused step with global atomics: gather at x^n, kick, exchange deposit at x^n, drift.
 // LOSS: also gather the nucleon density NN, reduce the packet weight (catastrophic
 // losses) and deposit the change of the weighted packet totals.  REC: write the starting
@@ -669,6 +775,27 @@ hipError_t launch_step_record(int shape, const Packets<T>& P, const T* E, const 
   return hipGetLastError();
 }
 
+bool moments_tiled_fits(const Tiling& t) { return region_span(t.tx + 2, t.ty + 2, t.tz + 2) <= kAdjRegion; }
+
+template <typename T>
+hipError_t launch_moments_tiled(int shape, const Packets<T>& P, const int32_t* order, const int32_t* offsets,
+                                const Tiling& t, double* rho, double* Pm, double* e, const RunConsts& k,
+                                hipStream_t s) {
+  if (!moments_tiled_fits(t)) return hipErrorInvalidValue;
+  const int64_t ntiles = t.ntiles();
+  const int64_t per_tile = (P.np + ntiles - 1) / (ntiles > 0 ? ntiles : 1);
+  int parts = (int)((per_tile + 1023) / 1024);
+  parts = parts < 1 ? 1 : (parts > 4 ? 4 : parts);
+  const dim3 grid((unsigned)(ntiles * parts));
+  if (shape == kShapeCIC)
+    hipLaunchKernelGGL((moments_tiled_kernel<2, T>), grid, dim3(kBlock), 0, s, P, order, offsets, t, parts, rho, Pm,
+                       e, k);
+  else
+    hipLaunchKernelGGL((moments_tiled_kernel<3, T>), grid, dim3(kBlock), 0, s, P, order, offsets, t, parts, rho, Pm,
+                       e, k);
+  return hipGetLastError();
+}
+
 bool step_record_tiled_fits(const Tiling& t, int halo) {
   return halo >= 1 && region_span(t.tx + 2 * halo, t.ty + 2 * halo, t.tz + 2 * halo) <= kAdjRegion;
 }
@@ -708,7 +835,10 @@ hipError_t launch_step_record_tiled(int shape, const Packets<T>& P, void* slab, 
   template hipError_t launch_step_record<T>(int, const Packets<T>&, const T*, const T*, void*, const RunConsts&, \
                                             hipStream_t);                                                      \
   template hipError_t launch_step_record_tiled<T>(int, const Packets<T>&, void*, const int32_t*, const Tiling&, \
-                                                  int, const T*, const T*, const RunConsts&, hipStream_t);
+                                                  int, const T*, const T*, const RunConsts&, hipStream_t);     \
+  template hipError_t launch_moments_tiled<T>(int, const Packets<T>&, const int32_t*, const int32_t*,          \
+                                              const Tiling&, double*, double*, double*, const RunConsts&,      \
+                                              hipStream_t);
 
 RSOL_INSTANTIATE(double)
 RSOL_INSTANTIATE(float)

@@ -603,6 +603,31 @@ int backward_tiled(rsol_ctx* h, int32_t nsteps, const char* states, T* lam_x, T*
   return RSOL_OK;
 }
 
+// Moments of the caller's packets: sorted by tile (the permutation only) and accumulated
+// per tile in LDS, or with global atomics where the tile region does not fit.
+template <typename T>
+int moments(rsol_ctx* h, double* rho, double* P, double* e) {
+  const RunConsts k = consts(h);
+  Packets<T> src = caller_packets<T>(h);
+  if (!moments_tiled_fits(h->tiling)) {
+    RSOL_HIP(h, launch_moments<T>(h->p.shape, src, rho, P, e, k, h->stream), "moments");
+    return RSOL_OK;
+  }
+  Packets<T> ord = perm_packets<T>(h);
+  ord.x = nullptr;
+  ord.cell = nullptr;
+  ord.off = nullptr;
+  ord.u = nullptr;
+  ord.w = nullptr;
+  src.id = h->iota;
+  RSOL_HIP(h, launch_iota(h->iota, h->np, h->stream), "iota");
+  RSOL_HIP(h, launch_sort<T>(src, ord, k, h->tiling, h->sort_ints, h->stream), "moments sort");
+  h->sorted_valid = false;
+  RSOL_HIP(h, launch_moments_tiled<T>(h->p.shape, caller_packets<T>(h), ord.id, h->sort_ints, h->tiling, rho, P, e,
+                                      k, h->stream), "moments");
+  return RSOL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -896,13 +921,8 @@ int rsol_moments(rsol_handle h, double* rho, double* P, double* e) {
   if (P) RSOL_HIP(h, launch_fill_f64(P, 0.0, 3 * nc, h->stream), "zero P");
   if (e) RSOL_HIP(h, launch_fill_f64(e, 0.0, nc, h->stream), "zero e");
   if (h->np == 0) return RSOL_OK;
-  if (fp32(h->p))
-    RSOL_HIP(h, launch_moments<float>(h->p.shape, caller_packets<float>(h), rho, P, e, consts(h), h->stream),
-             "moments");
-  else
-    RSOL_HIP(h, launch_moments<double>(h->p.shape, caller_packets<double>(h), rho, P, e, consts(h), h->stream),
-             "moments");
-  return RSOL_OK;
+  if (fp32(h->p)) return moments<float>(h, rho, P, e);
+  return moments<double>(h, rho, P, e);
 }
 
 int rsol_set_flags(rsol_handle h, int32_t flags) {

@@ -98,6 +98,15 @@ hipError_t launch_step_record(int shape, const Packets<T>& P, const T* E, const 
 // recording).  Needs step_record_tiled_fits(t, halo).
 struct Tiling;
 bool step_record_tiled_fits(const Tiling& t, int halo);
+
+// The moments with the packets taken tile by tile through `order` and `offsets` (a
+// counting sort of the current state), accumulated per tile plus a one-cell halo in LDS.
+// Outputs as launch_moments (accumulated: zero them first).  Needs moments_tiled_fits(t).
+bool moments_tiled_fits(const Tiling& t);
+template <typename T>
+hipError_t launch_moments_tiled(int shape, const Packets<T>& P, const int32_t* order, const int32_t* offsets,
+                                const Tiling& t, double* rho, double* Pm, double* e, const RunConsts& k,
+                                hipStream_t s);
 template <typename T>
 hipError_t launch_step_record_tiled(int shape, const Packets<T>& P, void* slab, const int32_t* offsets,
                                     const Tiling& t, int halo, const T* E, const T* B, const RunConsts& k,
