@@ -217,8 +217,11 @@ int rsol_step(rsol_handle h, int32_t nsteps, double* dM, double* dE);
 int rsol_step_coupled(rsol_handle h, int32_t nsteps, const double* rho, double* mom, double* egas, double* E);
 
 /* CR moments of the current state (Sec. 2 packet totals): rho[n_cells] = sum M W / V,
- * P[3][n_cells] = sum M c u W / V, e[n_cells] = sum M c^2 gamma W / V.  Outputs are
- * overwritten; any may be NULL. */
+ * P[3][n_cells] = sum M c u W / V, e[n_cells] = sum M c^2 gamma W / V (times the packet
+ * weight under losses).  Outputs are overwritten; any may be NULL.  The packets are
+ * taken tile by tile (a sort of their indices in scratch; the registered arrays are not
+ * touched) and summed per tile on chip, so the order of the additions into each cell
+ * is not fixed: results agree to rounding from call to call. */
 int rsol_moments(rsol_handle h, double* rho, double* P, double* e);
 
 /* Set the RSOL_FLAG_* bits of the handle (RSOL_FLAG_LOSSES cannot change). */
