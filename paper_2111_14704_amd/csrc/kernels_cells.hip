@@ -898,15 +898,42 @@ __global__ void cells_post_kernel(StepView V, double* dM, double* dE, GasLink ga
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   if (blockIdx.x == 0 && threadIdx.x == 0) V.icnt_in[V.ntiles * kDirs] = 0;
   if (!dM) return;
+  const int n3[3] = {k.nx, k.ny, k.nz};
+  const int nt[3] = {V.ntx, V.nty, V.ntz};
+  // whole tiles and at least three of them along every axis: a cell's slots are its own
+  // tile's and, on a tile face, the neighbour's across it (no wrap folds two together)
+  bool whole = true;
+  #pragma unroll
+  for (int d = 0; d < 3; ++d) whole &= n3[d] % kCellTile == 0 && nt[d] >= 3;
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += stride) {
     const int g[3] = {(int)(c % k.nx), (int)((c / k.nx) % k.ny), (int)(c / ((int64_t)k.nx * k.ny))};
-    const int n3[3] = {k.nx, k.ny, k.nz};
-    const int nt[3] = {V.ntx, V.nty, V.ntz};
-    // per axis: (tile, region index) pairs whose region slot is this cell
+    // per axis: (tile, region index) pairs whose region slot is this cell, in the order
+    // of the tiles before, at and after the cell's own
     int tl[3][8], rl[3][8], cnt[3] = {0, 0, 0};
     #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const int t0 = g[d] / kCellTile;
+      if (whole) {
+        const int l = g[d] - t0 * kCellTile;
+        if (l == 0) {
+          tl[d][0] = t0 == 0 ? nt[d] - 1 : t0 - 1;
+          rl[d][0] = kRegionEdge - 1;
+          tl[d][1] = t0;
+          rl[d][1] = 1;
+          cnt[d] = 2;
+        } else if (l == kCellTile - 1) {
+          tl[d][0] = t0;
+          rl[d][0] = l + 1;
+          tl[d][1] = t0 == nt[d] - 1 ? 0 : t0 + 1;
+          rl[d][1] = 0;
+          cnt[d] = 2;
+        } else {
+          tl[d][0] = t0;
+          rl[d][0] = l + 1;
+          cnt[d] = 1;
+        }
+        continue;
+      }
       for (int dt = -1; dt <= 1; ++dt) {
         const int t = wrapm(t0 + dt, nt[d]);
         bool dup = false;
