@@ -106,6 +106,19 @@ typedef struct rsol_params {
                                    tiled path and the differentiation form refuse it.        */
 #define RSOL_FLAG_PUSHER_HC 32  /* the same with the pusher of Higuera and Cary (Phys. Plasmas
                                    24, 052104, 2017); at most one pusher flag.               */
+#define RSOL_FLAG_RESIDENT 64   /* default (cell-list) path: the packets stay in the
+                                   library's cell lists between rsol_step / rsol_step_coupled
+                                   calls, which then neither file the registered arrays nor
+                                   copy the packets back.  The arrays are brought up to date
+                                   by rsol_sync_particles, and by every other entry point
+                                   that reads or writes them, before it does; entry points
+                                   that change the packets (rsol_set_particles,
+                                   rsol_set_losses, rsol_set_flags, rsol_sort, rsol_push,
+                                   rsol_drift, the other step paths, the differentiation
+                                   form, the position conversions) also drop the lists, and
+                                   the next call files again.  While the flag is set the
+                                   caller reads the arrays only after rsol_sync_particles
+                                   and writes them only followed by rsol_set_particles     */
 
 typedef struct rsol_ctx* rsol_handle;
 
@@ -215,6 +228,11 @@ int rsol_step(rsol_handle h, int32_t nsteps, double* dM, double* dE);
  * Errors: RSOL_EINVAL for NULL rho/mom/E or arrays that alias each other or B,
  * RSOL_ESTATE before fields, packets and dt are set; step errors as rsol_step. */
 int rsol_step_coupled(rsol_handle h, int32_t nsteps, const double* rho, double* mom, double* egas, double* E);
+
+/* Copy the packets held in resident cell lists (RSOL_FLAG_RESIDENT) back to the
+ * registered arrays (cell-major order, ids permuted with them); a no-op when the arrays
+ * are current.  Enqueued on the handle's stream. */
+int rsol_sync_particles(rsol_handle h);
 
 /* CR moments of the current state (Sec. 2 packet totals): rho[n_cells] = sum M W / V,
  * P[3][n_cells] = sum M c u W / V, e[n_cells] = sum M c^2 gamma W / V (times the packet

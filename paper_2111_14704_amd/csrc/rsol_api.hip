@@ -44,6 +44,8 @@ struct rsol_ctx {
   void* w;
   double sigma;
   bool have_fields, have_packets, sorted_valid, have_losses;
+  bool cells_valid;     // the cell lists hold the packets (as of the last rsol_step return)
+  bool arrays_stale;    // resident lists hold newer packets than the registered arrays
   int steps_since_sort;
   Tiling tiling;
   StepPlan plan;
@@ -114,7 +116,7 @@ bool fp32(const rsol_params& p) { return p.precision == RSOL_FP32; }
 bool naive(const rsol_params& p) { return (p.flags & RSOL_FLAG_NAIVE) != 0; }
 bool loss_layout(const rsol_params& p) { return (p.flags & RSOL_FLAG_LOSSES) != 0; }
 constexpr int32_t kKnownFlags = RSOL_FLAG_KEEP_ORDER | RSOL_FLAG_TILED | RSOL_FLAG_NAIVE | RSOL_FLAG_LOSSES |
-                                RSOL_FLAG_PUSHER_VAY | RSOL_FLAG_PUSHER_HC;
+                                RSOL_FLAG_PUSHER_VAY | RSOL_FLAG_PUSHER_HC | RSOL_FLAG_RESIDENT;
 int pusher_of(int32_t flags) {
   return (flags & RSOL_FLAG_PUSHER_VAY) ? kPushVay : (flags & RSOL_FLAG_PUSHER_HC) ? kPushHC : kPushBoris;
 }
@@ -375,12 +377,14 @@ int do_sort(rsol_ctx* h, bool copy) {
 // Default path: caller arrays -> cell buckets, nsteps cell-list steps, buckets ->
 // caller arrays (cell-major).
 template <typename T>
-int do_step_cells(rsol_ctx* h, int32_t nsteps, double* dM, double* dE, const GasLink& gas) {
+int do_step_cells(rsol_ctx* h, int32_t nsteps, double* dM, double* dE, const GasLink& gas, bool reuse) {
   const RunConsts k = consts(h);
   const Packets<T> P = caller_packets<T>(h);
   auto ev = timed_begin(h);
-  RSOL_HIP(h, launch_cells_build<T>(P, h->cells, k, h->stream), "cell lists (build)");
-  timed_end(h, ev, true);
+  if (!reuse) {
+    RSOL_HIP(h, launch_cells_build<T>(P, h->cells, k, h->stream), "cell lists (build)");
+    timed_end(h, ev, true);
+  }
   for (int32_t s = 0; s < nsteps; ++s) {
     std::pair<hipEvent_t, hipEvent_t> pr(nullptr, nullptr);
     if (h->timing) {
@@ -392,10 +396,30 @@ int do_step_cells(rsol_ctx* h, int32_t nsteps, double* dM, double* dE, const Gas
              "step (cells)");
     if (pr.first && pr.second) h->ev_step.push_back(pr);
   }
+  h->sorted_valid = false;
+  if (h->p.flags & RSOL_FLAG_RESIDENT) {
+    // the packets stay in the lists; the arrays catch up on the next sync
+    h->cells_valid = true;
+    h->arrays_stale = true;
+    return RSOL_OK;
+  }
   ev = timed_begin(h);
   RSOL_HIP(h, launch_cells_compact<T>(P, h->cells, k, h->stream), "cell lists (compact)");
   timed_end(h, ev, true);
-  h->sorted_valid = false;
+  return RSOL_OK;
+}
+
+// Copy the packets of resident cell lists back to the registered arrays.
+int sync_arrays(rsol_ctx* h) {
+  if (!h->arrays_stale) return RSOL_OK;
+  const RunConsts k = consts(h);
+  auto ev = timed_begin(h);
+  if (fp32(h->p))
+    RSOL_HIP(h, launch_cells_compact<float>(caller_packets<float>(h), h->cells, k, h->stream), "cell lists (sync)");
+  else
+    RSOL_HIP(h, launch_cells_compact<double>(caller_packets<double>(h), h->cells, k, h->stream), "cell lists (sync)");
+  timed_end(h, ev, true);
+  h->arrays_stale = false;
   return RSOL_OK;
 }
 
@@ -405,8 +429,12 @@ int record_tiled(rsol_ctx* h, int32_t nsteps, char* states, const RunConsts& k);
 
 template <typename T>
 int do_step(rsol_ctx* h, int32_t nsteps, double* dM, double* dE, const GasLink& gas) {
+  const bool reuse = (h->p.flags & RSOL_FLAG_RESIDENT) && h->cells_valid;
+  if (!reuse)
+    if (int rc = sync_arrays(h)) return rc;
+  h->cells_valid = false;
   if ((h->p.flags & (RSOL_FLAG_KEEP_ORDER | RSOL_FLAG_TILED)) == 0)
-    return do_step_cells<T>(h, nsteps, dM, dE, gas);
+    return do_step_cells<T>(h, nsteps, dM, dE, gas, reuse);
   const RunConsts k = consts(h);
   // keep-order steps that deposit nothing (the differentiation form's forward pass) run
   // on tile-sorted copies with the fields staged per tile, as its recording does
@@ -735,6 +763,8 @@ int rsol_set_fields(rsol_handle h, const double* E, const double* B) {
 
 int rsol_set_losses(rsol_handle h, double sigma, const double* nn, void* w) {
   if (int rc = need(h, false, false)) return rc;
+  if (int rc = sync_arrays(h)) return rc;
+  h->cells_valid = false;  // the packets change (or the cell-list scratch is reused)
   if (!loss_layout(h->p)) return fail(h, RSOL_ESTATE, "handle created without RSOL_FLAG_LOSSES");
   if (!(sigma >= 0) || !isfinite(sigma)) return fail(h, RSOL_EINVAL, "sigma must be finite and >= 0");
   if (!nn || (!w && h->np > 0)) return fail(h, RSOL_EINVAL, "NULL loss array");
@@ -750,6 +780,8 @@ int rsol_set_losses(rsol_handle h, double sigma, const double* nn, void* w) {
 
 int rsol_set_particles(rsol_handle h, void* pos, float* off, void* u, int32_t* id) {
   if (int rc = need(h, false, false)) return rc;
+  h->cells_valid = false;  // new arrays: the lists and any packets they held are dropped
+  h->arrays_stale = false;
   if (h->np > 0 && (!pos || !u || !id)) return fail(h, RSOL_EINVAL, "NULL packet pointer");
   if (fp32(h->p) && h->np > 0 && !off) return fail(h, RSOL_EINVAL, "FP32 form needs off");
   if (!fp32(h->p) && off) return fail(h, RSOL_EINVAL, "FP64 form takes no off array");
@@ -765,6 +797,8 @@ int rsol_set_particles(rsol_handle h, void* pos, float* off, void* u, int32_t* i
 
 int rsol_positions_to_cells(rsol_handle h, const double* x, int32_t* cell, float* off) {
   if (int rc = need(h, false, false)) return rc;
+  if (int rc = sync_arrays(h)) return rc;
+  h->cells_valid = false;  // the packets change (or the cell-list scratch is reused)
   if (h->np == 0) return RSOL_OK;
   if (!x || !cell || !off) return fail(h, RSOL_EINVAL, "NULL pointer");
   RSOL_HIP(h, launch_positions_to_cells(x, cell, off, h->np, consts(h), h->stream), "positions_to_cells");
@@ -773,6 +807,8 @@ int rsol_positions_to_cells(rsol_handle h, const double* x, int32_t* cell, float
 
 int rsol_cells_to_positions(rsol_handle h, const int32_t* cell, const float* off, double* x) {
   if (int rc = need(h, false, false)) return rc;
+  if (int rc = sync_arrays(h)) return rc;
+  h->cells_valid = false;  // the packets change (or the cell-list scratch is reused)
   if (h->np == 0) return RSOL_OK;
   if (!x || !cell || !off) return fail(h, RSOL_EINVAL, "NULL pointer");
   RSOL_HIP(h, launch_cells_to_positions(cell, off, x, h->np, consts(h), h->stream), "cells_to_positions");
@@ -781,6 +817,7 @@ int rsol_cells_to_positions(rsol_handle h, const int32_t* cell, const float* off
 
 int rsol_courant_dt(rsol_handle h, double* dt) {
   if (int rc = need(h, true, true)) return rc;
+  if (int rc = sync_arrays(h)) return rc;  // reads the registered packets
   if (!dt) return fail(h, RSOL_EINVAL, "dt is NULL");
   if (h->np == 0) return fail(h, RSOL_EINVAL, "no packets");
   if (fp32(h->p)) {
@@ -820,6 +857,7 @@ int rsol_set_dt(rsol_handle h, double dt) {
 
 int rsol_gather(rsol_handle h, void* Ep, void* Bp) {
   if (int rc = need(h, true, true)) return rc;
+  if (int rc = sync_arrays(h)) return rc;  // reads the registered packets
   if (h->have_losses) return fail(h, RSOL_EINVAL, "losses registered: the separate phases carry no losses (use rsol_step)");
   if (h->np == 0) return RSOL_OK;
   if (!Ep || !Bp) return fail(h, RSOL_EINVAL, "NULL output");
@@ -834,6 +872,8 @@ int rsol_gather(rsol_handle h, void* Ep, void* Bp) {
 
 int rsol_push(rsol_handle h, const void* Ep, const void* Bp, void* payload) {
   if (int rc = need(h, false, true)) return rc;
+  if (int rc = sync_arrays(h)) return rc;
+  h->cells_valid = false;  // the packets change (or the cell-list scratch is reused)
   if (h->have_losses) return fail(h, RSOL_EINVAL, "losses registered: the separate phases carry no losses (use rsol_step)");
   if (h->np == 0) return RSOL_OK;
   if (!Ep || !Bp || !payload) return fail(h, RSOL_EINVAL, "NULL pointer");
@@ -849,6 +889,7 @@ int rsol_push(rsol_handle h, const void* Ep, const void* Bp, void* payload) {
 
 int rsol_deposit(rsol_handle h, const void* payload, double* dM, double* dE) {
   if (int rc = need(h, false, true)) return rc;
+  if (int rc = sync_arrays(h)) return rc;  // reads the registered packets
   if (h->have_losses) return fail(h, RSOL_EINVAL, "losses registered: the separate phases carry no losses (use rsol_step)");
   if (h->np == 0) return RSOL_OK;
   if (!payload || !dM) return fail(h, RSOL_EINVAL, "NULL pointer");
@@ -863,6 +904,8 @@ int rsol_deposit(rsol_handle h, const void* payload, double* dM, double* dE) {
 
 int rsol_drift(rsol_handle h) {
   if (int rc = need(h, false, true)) return rc;
+  if (int rc = sync_arrays(h)) return rc;
+  h->cells_valid = false;  // the packets change (or the cell-list scratch is reused)
   if (h->have_losses) return fail(h, RSOL_EINVAL, "losses registered: the separate phases carry no losses (use rsol_step)");
   if (h->np == 0) return RSOL_OK;
   if (!(h->p.dt > 0)) return fail(h, RSOL_ESTATE, "dt not set");
@@ -876,6 +919,8 @@ int rsol_drift(rsol_handle h) {
 
 int rsol_sort(rsol_handle h) {
   if (int rc = need(h, false, true)) return rc;
+  if (int rc = sync_arrays(h)) return rc;
+  h->cells_valid = false;  // the packets change (or the cell-list scratch is reused)
   if (h->have_losses) return fail(h, RSOL_EINVAL, "losses registered: packets are re-binned by rsol_step only");
   return fp32(h->p) ? do_sort<float>(h, true) : do_sort<double>(h, true);
 }
@@ -914,8 +959,14 @@ int rsol_step_coupled(rsol_handle h, int32_t nsteps, const double* rho, double* 
   return fp32(h->p) ? do_step<float>(h, nsteps, mom, egas, g) : do_step<double>(h, nsteps, mom, egas, g);
 }
 
+int rsol_sync_particles(rsol_handle h) {
+  if (int rc = need(h, false, false)) return rc;
+  return sync_arrays(h);
+}
+
 int rsol_moments(rsol_handle h, double* rho, double* P, double* e) {
   if (int rc = need(h, false, true)) return rc;
+  if (int rc = sync_arrays(h)) return rc;  // reads the registered packets
   const int64_t nc = n_cells(h->p);
   if (rho) RSOL_HIP(h, launch_fill_f64(rho, 0.0, nc, h->stream), "zero rho");
   if (P) RSOL_HIP(h, launch_fill_f64(P, 0.0, 3 * nc, h->stream), "zero P");
@@ -927,6 +978,8 @@ int rsol_moments(rsol_handle h, double* rho, double* P, double* e) {
 
 int rsol_set_flags(rsol_handle h, int32_t flags) {
   if (int rc = need(h, false, false)) return rc;
+  if (int rc = sync_arrays(h)) return rc;
+  h->cells_valid = false;  // the packets change (or the cell-list scratch is reused)
   if (flags & ~kKnownFlags) return fail(h, RSOL_EINVAL, "unknown flag bits");
   if (!flag_conflict(flags).empty()) return fail(h, RSOL_EINVAL, flag_conflict(flags));
   if ((flags ^ h->p.flags) & RSOL_FLAG_LOSSES) return fail(h, RSOL_EINVAL, "RSOL_FLAG_LOSSES is fixed at rsol_init");
@@ -943,6 +996,8 @@ size_t rsol_state_bytes(rsol_handle h) {
 
 int rsol_record_states(rsol_handle h, int32_t nsteps, void* states) {
   if (int rc = need(h, true, true)) return rc;
+  if (int rc = sync_arrays(h)) return rc;
+  h->cells_valid = false;  // the packets change (or the cell-list scratch is reused)
   if (naive(h->p)) return fail(h, RSOL_EINVAL, "the differentiation form covers the RSOL equations only");
   if (pusher_of(h->p.flags) != kPushBoris) return fail(h, RSOL_EINVAL, "the differentiation form is the Boris pusher's");
   if (h->have_losses) return fail(h, RSOL_EINVAL, "the differentiation form carries no losses");
@@ -961,6 +1016,8 @@ int rsol_record_states(rsol_handle h, int32_t nsteps, void* states) {
 int rsol_step_backward(rsol_handle h, int32_t nsteps, const void* states, void* lam_x, void* lam_u,
                        const double* lam_dM, const double* lam_dE, double* gE, double* gB) {
   if (int rc = need(h, true, true)) return rc;
+  if (int rc = sync_arrays(h)) return rc;
+  h->cells_valid = false;  // the packets change (or the cell-list scratch is reused)
   if (naive(h->p)) return fail(h, RSOL_EINVAL, "the differentiation form covers the RSOL equations only");
   if (pusher_of(h->p.flags) != kPushBoris) return fail(h, RSOL_EINVAL, "the differentiation form is the Boris pusher's");
   if (h->have_losses) return fail(h, RSOL_EINVAL, "the differentiation form carries no losses");
@@ -985,6 +1042,7 @@ int rsol_step_backward(rsol_handle h, int32_t nsteps, const void* states, void* 
 int rsol_moments_backward(rsol_handle h, const double* lam_rho, const double* lam_P, const double* lam_e,
                           void* lam_x, void* lam_u) {
   if (int rc = need(h, false, true)) return rc;
+  if (int rc = sync_arrays(h)) return rc;  // reads the registered packets
   if (naive(h->p)) return fail(h, RSOL_EINVAL, "the differentiation form covers the RSOL equations only");
   if (pusher_of(h->p.flags) != kPushBoris) return fail(h, RSOL_EINVAL, "the differentiation form is the Boris pusher's");
   if (h->have_losses) return fail(h, RSOL_EINVAL, "the differentiation form carries no losses");

@@ -30,6 +30,7 @@ RSOL_FLAG_NAIVE = 4
 RSOL_FLAG_LOSSES = 8
 RSOL_FLAG_PUSHER_VAY = 16
 RSOL_FLAG_PUSHER_HC = 32
+RSOL_FLAG_RESIDENT = 64
 
 
 class RSOLError(RuntimeError):
@@ -82,6 +83,7 @@ def lib():
             "rsol_step_coupled": (ctypes.c_int, [vp, i32, vp, vp, vp, vp]),
             "rsol_set_losses": (ctypes.c_int, [vp, dbl, vp, vp]),
             "rsol_moments": (ctypes.c_int, [vp, vp, vp, vp]),
+            "rsol_sync_particles": (ctypes.c_int, [vp]),
             "rsol_check": (ctypes.c_int, [vp]),
             "rsol_timing": (ctypes.c_int, [vp, i32]),
             "rsol_stray_count": (ctypes.c_int, [vp, ctypes.POINTER(i64)]),
@@ -108,7 +110,7 @@ def exported_symbols():
         "rsol_courant_dt", "rsol_set_dt", "rsol_gather", "rsol_push", "rsol_deposit", "rsol_drift",
         "rsol_sort", "rsol_step", "rsol_moments", "rsol_check", "rsol_timing", "rsol_timing_read",
         "rsol_stray_count", "rsol_set_flags", "rsol_state_bytes", "rsol_record_states", "rsol_step_backward",
-        "rsol_moments_backward", "rsol_step_coupled", "rsol_set_losses",
+        "rsol_moments_backward", "rsol_step_coupled", "rsol_set_losses", "rsol_sync_particles",
     ]
 
 
@@ -242,6 +244,9 @@ class Handle:
     def rsol_step_coupled(self, nsteps: int, rho, mom, egas, E):
         self._keep.update(rho=rho, mom=mom, egas=egas, E=E)
         _check(self.h, lib().rsol_step_coupled(self.h, int(nsteps), _ptr(rho), _ptr(mom), _ptr(egas), _ptr(E)))
+
+    def rsol_sync_particles(self):
+        _check(self.h, lib().rsol_sync_particles(self.h))
 
     def rsol_moments(self, rho=None, P=None, e=None):
         _check(self.h, lib().rsol_moments(self.h, _ptr(rho), _ptr(P), _ptr(e)))

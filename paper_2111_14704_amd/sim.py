@@ -78,8 +78,14 @@ class Simulation:
                                  device=self.device)
         self.handle.rsol_set_losses(sigma, self.nn, self.w)
 
+    def sync(self):
+        """Bring the registered packet tensors up to date (with RSOL_FLAG_RESIDENT the
+        packets stay in the library's cell lists between steps)."""
+        self.handle.rsol_sync_particles()
+
     def weights_by_id(self):
         """Packet weights (float64 numpy) indexed by packet id."""
+        self.sync()
         ids = self.ids.cpu().numpy()
         return self.w.double().cpu().numpy()[np.argsort(ids, kind="stable")]
 
@@ -91,6 +97,7 @@ class Simulation:
 
     def positions64(self):
         """Absolute FP64 positions (3, Np) on the device, in the current packet order."""
+        self.sync()
         if not self.fp32:
             return self.x
         x = torch.empty((3, self.n_particles), dtype=torch.float64, device=self.device)
@@ -100,6 +107,7 @@ class Simulation:
 
     def state_by_id(self):
         """(x, u) as float64 numpy arrays indexed by packet id."""
+        self.sync()
         x = self.positions64().cpu().numpy()
         u = self.u.double().cpu().numpy()
         ids = self.ids.cpu().numpy()

@@ -355,6 +355,49 @@ def test_keep_order_without_exchange(precision, tol, per_call):
         assert rel_l2(got.cpu().numpy(), want) <= tol
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_resident_cell_lists(precision):
+    """RSOL_FLAG_RESIDENT: one step per call for 8 calls, a library-side change of the
+    packets (rsol_drift, which first brings the arrays up to date) between calls, then 4
+    more calls; every call after the first reuses the lists the previous one left, except
+    the one after the drift, which must file again.  Moments and the packets read back
+    (both sync the arrays) match the run without the flag.  Packets match the run without the flag bit for bit (by id), the summed
+    exchange up to the order of its sums, and both match the oracle's rollout."""
+    torch = _torch()
+    from paper_2111_14704_amd.sim import Simulation
+    w = make_workload(2, n=16, ppc=8, precision=precision)
+    _say(f"resident cell lists {precision}")
+    out = []
+    for flags in (0, 64):
+        sim = Simulation.from_workload(w, flags=flags)
+        dM = sim.zeros_grid(3)
+        for _ in range(8):
+            sim.step(1, dM, None)
+        sim.handle.rsol_drift()
+        for _ in range(4):
+            sim.step(1, dM, None)
+        sim.handle.rsol_check()
+        rho, P, _ = sim.moments()  # reads the packets: syncs resident lists first
+        torch.cuda.synchronize()
+        x, u = sim.state_by_id()
+        out.append((x, u, dM.cpu().numpy(), sim.dt, rho.cpu().numpy(), P.cpu().numpy()))
+    (x0, u0, d0, dt, r0, P0), (x1, u1, d1, _, r1, P1) = out
+    assert np.array_equal(x0, x1) and np.array_equal(u0, u1)
+    assert rel_l2(r1, r0) <= 1e-13 and rel_l2(P1, P0) <= 1e-13
+    # FP64: only the order of the atomic sums differs; FP32: a packet's slot also decides
+    # the order of the FP32 partial sums a quad keeps in registers
+    assert rel_l2(d1, d0) <= (1e-13 if precision == "fp64" else 1e-6)
+    # the oracle: 8 steps, a drift with the momenta as they stand, 4 steps
+    p = oracle_params(w, dt=dt)
+    E, B = oracle_fields(w)
+    r = oracle.rollout(w.x, w.u, E, B, p, 8)
+    xd = oracle.drift(r["x"], r["u"], p)
+    r2 = oracle.rollout(xd, r["u"], E, B, p, 4)
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    assert np.max(periodic_distance(x1, r2["x"], w.box)) / w.dx <= (1e-10 if precision == "fp64" else 1e-4)
+    assert max_rel_momentum(u1, r2["u"]) <= tol
+
+
 def test_empty_and_single_packet():
     """No packets: every call is a no-op.  One packet: matches the oracle."""
     torch = _torch()
