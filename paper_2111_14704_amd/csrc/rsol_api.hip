@@ -529,16 +529,12 @@ Packets<T> slab_packets(const rsol_ctx* h, const char* at) {
   return P;
 }
 
-template <typename T>
-const T* adj_E(const rsol_ctx* h) { if constexpr (is_fp64<T>()) return h->E; else return h->E32; }
-template <typename T>
-const T* adj_B(const rsol_ctx* h) { if constexpr (is_fp64<T>()) return h->B; else return h->B32; }
 
 template <typename T>
 int record_global(rsol_ctx* h, int32_t nsteps, char* states, const RunConsts& k) {
   const SlabLayout sl = slab_layout(h);
   for (int32_t n = 0; n < nsteps; ++n)
-    RSOL_HIP(h, launch_step_record<T>(h->p.shape, caller_packets<T>(h), adj_E<T>(h), adj_B<T>(h),
+    RSOL_HIP(h, launch_step_record<T>(h->p.shape, caller_packets<T>(h), field_E<T>(h), field_B<T>(h),
                                       states + (size_t)n * sl.total + sl.state, k, h->stream), "record step");
   return RSOL_OK;
 }
@@ -577,7 +573,7 @@ int record_tiled(rsol_ctx* h, int32_t nsteps, char* states, const RunConsts& k) 
     }
     auto ev = timed_begin(h);
     RSOL_HIP(h, launch_step_record_tiled<T>(h->p.shape, cur, slab ? slab + sl.state : nullptr, h->sort_ints,
-                                            h->tiling, kAdjHalo, adj_E<T>(h), adj_B<T>(h), k, h->stream),
+                                            h->tiling, kAdjHalo, field_E<T>(h), field_B<T>(h), k, h->stream),
              "record step");
     timed_end(h, ev, false);
   }
@@ -591,7 +587,7 @@ int backward_global(rsol_ctx* h, int32_t nsteps, const char* states, T* lam_x, T
   const SlabLayout sl = slab_layout(h);
   for (int32_t n = nsteps - 1; n >= 0; --n)
     RSOL_HIP(h, launch_step_backward<T>(h->p.shape, states + (size_t)n * sl.total + sl.state, h->np, lam_x, lam_u,
-                                        adj_E<T>(h), adj_B<T>(h), lam_dM, lam_dE, gE, gB, k, h->stream),
+                                        field_E<T>(h), field_B<T>(h), lam_dM, lam_dE, gE, gB, k, h->stream),
              "step backward");
   return RSOL_OK;
 }
@@ -622,8 +618,8 @@ int backward_tiled(rsol_ctx* h, int32_t nsteps, const char* states, T* lam_x, T*
     }
     const int32_t* offsets = (const int32_t*)(first_slab(b) + sl.offsets);
     RSOL_HIP(h, launch_step_backward_tiled<T>(h->p.shape, slab_packets<T>(h, states + (size_t)n * sl.total + sl.state),
-                                              offsets, h->tiling, kAdjHalo, h->spill, L0, L0 + 3 * np, adj_E<T>(h),
-                                              adj_B<T>(h), lam_dM, lam_dE, gE, gB, k, h->stream), "step backward");
+                                              offsets, h->tiling, kAdjHalo, h->spill, L0, L0 + 3 * np, field_E<T>(h),
+                                              field_B<T>(h), lam_dM, lam_dE, gE, gB, k, h->stream), "step backward");
   }
   const int32_t* order0 = (const int32_t*)(states + sl.order);
   RSOL_HIP(h, launch_permute_rows<T>(L0, lam_x, order0, np, 3, true, h->stream), "adjoint scatter");
