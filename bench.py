@@ -21,6 +21,8 @@ in the cell lists, nucleon density gathered by the step); "pushers" = the FP64 s
 with the Vay and Higuera-Cary momentum updates;
 "backward" = the differentiation form, with a roofline over the whole backward pass
 (algorithmic bytes of the recompute and the reverse step per packet-step);
+"one_step_calls" = ms per rsol_step call of one step, filing the packets every call
+and with RSOL_FLAG_RESIDENT;
 "copy_gbs" in each roofline = a plain device-to-device copy's measured bandwidth on
 the same GPU, "frac_of_copy" the achieved bandwidth against it;
 "cpu_baseline" = the CPU oracle timed on a bounded sample of the same workload.
@@ -172,6 +174,32 @@ def time_path(w, precision, steps, warmup, sort_every, coupled=False, flags=0, l
     return out
 
 
+def time_one_step_calls(w, precision, calls=20):
+    """Wall time of one rsol_step call of one step (the way a code coupled to an MHD
+    solver steps), with the packets filed into the cell lists and copied back by every
+    call, and with them resident in the lists between calls (RSOL_FLAG_RESIDENT)."""
+    import torch
+    from paper_2111_14704_amd.rsol import RSOL_FLAG_RESIDENT
+    from paper_2111_14704_amd.sim import Simulation
+    out = {}
+    for name, flags in (("filed_ms", 0), ("resident_ms", RSOL_FLAG_RESIDENT)):
+        sim = Simulation.from_workload(w, precision=precision, flags=flags)
+        dM, dE = sim.zeros_grid(3), sim.zeros_grid(1)[0]
+        for _ in range(3):
+            sim.step(1, dM, dE)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(calls):
+            sim.step(1, dM, dE)
+        torch.cuda.synchronize()
+        out[name] = (time.perf_counter() - t0) / calls * 1e3
+        sim.sync()
+        sim.handle.rsol_check()
+        del sim
+        torch.cuda.empty_cache()
+    return out
+
+
 def time_backward(precision, nsteps=256, ckpt=16):
     """Differentiation form on workload 5 (32^3 x 32 ppc, CIC): after an untimed two-segment
     warm-up, the forward with checkpoints, then the timed backward (moment adjoint + per
@@ -262,6 +290,7 @@ def main():
     ap.add_argument("--no-naive", action="store_true", help="skip the naive-substitution contrast run")
     ap.add_argument("--no-losses", action="store_true", help="skip the run with catastrophic losses")
     ap.add_argument("--no-pushers", action="store_true", help="skip the Vay and Higuera-Cary pusher runs")
+    ap.add_argument("--no-one-step", action="store_true", help="skip the one-step-per-call timings")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="first run one plain device copy of BYTES bytes (a known-size reference for HBM counters)")
     args = ap.parse_args()
@@ -322,6 +351,12 @@ def main():
             rp[name] = dict(value=r["value"], ms_per_step=r["ms_per_step"], kernel_ms=r["kernel_ms"], dtype="f64")
             print(f"[bench] {name} pusher fp64 {r['value']:.3e} upd/s, kernel {r['kernel_ms']:.3f} ms",
                   file=sys.stderr, flush=True)
+    one = {}
+    if not args.no_one_step:
+        for prec in ("fp64", "fp32"):
+            one[prec] = time_one_step_calls(w, prec)
+            print(f"[bench] one step per call {prec}: {one[prec]['filed_ms']:.3f} ms filed, "
+                  f"{one[prec]['resident_ms']:.3f} ms resident", file=sys.stderr, flush=True)
     copy_gbs = copy_bandwidth()
     print(f"[bench] device copy {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
     for r in (r64, r32, bwd, bwd and bwd.get("fp32")):
@@ -357,6 +392,8 @@ def main():
         line["naive"] = dict(value=rn["value"], ms_per_step=rn["ms_per_step"], kernel_ms=rn["kernel_ms"], dtype="f64")
     if rp:
         line["pushers"] = rp
+    if one:
+        line["one_step_calls"] = one
     if rl:
         line["losses"] = dict(value=rl["value"], ms_per_step=rl["ms_per_step"], kernel_ms=rl["kernel_ms"], dtype="f64",
                               overhead_vs_static=rl["ms_per_step"] / r64["ms_per_step"] - 1.0)
