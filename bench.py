@@ -291,6 +291,8 @@ def main():
     ap.add_argument("--no-losses", action="store_true", help="skip the run with catastrophic losses")
     ap.add_argument("--no-pushers", action="store_true", help="skip the Vay and Higuera-Cary pusher runs")
     ap.add_argument("--no-one-step", action="store_true", help="skip the one-step-per-call timings")
+    ap.add_argument("--no-copy-bw", action="store_true",
+                    help="skip the device-copy bandwidth measurement (counter runs keep --calibrate-copy the only copy)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="first run one plain device copy of BYTES bytes (a known-size reference for HBM counters)")
     args = ap.parse_args()
@@ -357,12 +359,13 @@ def main():
             one[prec] = time_one_step_calls(w, prec)
             print(f"[bench] one step per call {prec}: {one[prec]['filed_ms']:.3f} ms filed, "
                   f"{one[prec]['resident_ms']:.3f} ms resident", file=sys.stderr, flush=True)
-    copy_gbs = copy_bandwidth()
-    print(f"[bench] device copy {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
-    for r in (r64, r32, bwd, bwd and bwd.get("fp32")):
-        if r:
-            r["roofline"]["copy_gbs"] = copy_gbs
-            r["roofline"]["frac_of_copy"] = r["roofline"]["achieved"] / copy_gbs
+    if not args.no_copy_bw:
+        copy_gbs = copy_bandwidth()
+        print(f"[bench] device copy {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+        for r in (r64, r32, bwd, bwd and bwd.get("fp32")):
+            if r:
+                r["roofline"]["copy_gbs"] = copy_gbs
+                r["roofline"]["frac_of_copy"] = r["roofline"]["achieved"] / copy_gbs
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w)
