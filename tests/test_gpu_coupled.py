@@ -98,8 +98,9 @@ def test_coupled_config3_fp32(flags):
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
-@pytest.mark.parametrize("flags,per_call", [(0, 20), (0, 3), (2, 20), (1, 20)],
-                         ids=["cells", "cells-3-per-call", "tiled", "global"])
+@pytest.mark.parametrize("flags,per_call", [(0, 20), (0, 3), (2, 20), (1, 20), (64, 1), (64, 3)],
+                         ids=["cells", "cells-3-per-call", "tiled", "global", "resident-1-per-call",
+                              "resident-3-per-call"])
 def test_coupled_alfven_ragged(precision, tol, flags, per_call):
     """Workload 2 recipe on a 10^3 grid (ragged 4^3 tiles), TSC, 4 ppc, 20 steps: the gas
     flow of the Alfven modes changes by tens of percent, enough to move the packets well
