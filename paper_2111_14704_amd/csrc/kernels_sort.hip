@@ -58,8 +58,10 @@ __device__ __forceinline__ void home_cell(const Packets<T>& P, int64_t i, const 
     const int n[3] = {k.nx, k.ny, k.nz};
     #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      int hd = (int)floor(P.x[d * P.np + i] * k.inv_dx);
-      home[d] = hd >= n[d] ? hd - n[d] : (hd < 0 ? hd + n[d] : hd);
+      // full modulo: a position outside the box (against the contract) must not address
+      // outside the bins
+      int hd = (int)floor(P.x[d * P.np + i] * k.inv_dx) % n[d];
+      home[d] = hd < 0 ? hd + n[d] : hd;
     }
   } else {
     int c = P.cell[i];
