@@ -84,8 +84,8 @@ def test_losses_config1_fp64(flags):
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
-@pytest.mark.parametrize("flags,per_call", [(0, 20), (0, 3), (KEEP_ORDER, 20)], ids=["cells", "cells-3-per-call",
-                                                                                    "global"])
+@pytest.mark.parametrize("flags,per_call", [(0, 20), (0, 3), (KEEP_ORDER, 20), (64, 3)],
+                         ids=["cells", "cells-3-per-call", "global", "resident-3-per-call"])
 def test_losses_alfven_ragged(precision, tol, flags, per_call):
     """Workload 2 recipe on a ragged 10^3 grid (TSC, 4 ppc), 20 steps, packets with
     non-uniform starting weights."""
