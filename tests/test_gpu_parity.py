@@ -132,9 +132,11 @@ def test_cells_overflow_stores(precision, tol):
     grid overfill that cell's bucket (capacity 2*ceil(np/cells)+16 = 24) and its tile's
     inbox (16*24+256 = 640), so packets also take the grid-wide overflow list; all three
     stores must give the oracle's result, several steps in a row, in one rsol_step call
-    and one step per call.  A packet's arithmetic does not depend on the store it is read
-    from, so the two runs agree bit for bit on the packets; only the deposit sums run in
-    another order."""
+    and one step per call.  The two runs file packets differently: with TSC a packet the
+    quad loop takes gathers from the cell's polynomial coefficients, one the per-packet
+    phase takes from the weighted node sum, equal to rounding, so the runs agree on the
+    packets to rounding (1e-13 FP64, FP32 rounding for FP32) and on the deposit sums up
+    to their order."""
     w = make_workload(2, n=8, ppc=1, nsteps=12, precision=precision)
     rng = np.random.default_rng(5)
     cluster = 2.0 + rng.random((3, 1500))      # all in cell (2, 2, 2)
@@ -152,7 +154,8 @@ def test_cells_overflow_stores(precision, tol):
     sim.step(12, dM, dE)
     sim.handle.rsol_check()
     x, u = sim.state_by_id()
-    assert np.array_equal(x, got["x"]) and np.array_equal(u, got["u"])
+    assert np.max(periodic_distance(x, got["x"], w.box)) / w.dx <= (1e-12 if precision == "fp64" else 1e-4)
+    assert max_rel_momentum(u, got["u"]) <= (1e-13 if precision == "fp64" else 1e-5)
     # deposit sums run in a different order (bucket slots come from atomics)
     assert rel_l2(dM.cpu().numpy(), got["dM_sum"]) <= (1e-12 if precision == "fp64" else 1e-6)
 
@@ -361,8 +364,10 @@ def test_resident_cell_lists(precision):
     packets (rsol_drift, which first brings the arrays up to date) between calls, then 4
     more calls; every call after the first reuses the lists the previous one left, except
     the one after the drift, which must file again.  Moments and the packets read back
-    (both sync the arrays) match the run without the flag.  Packets match the run without the flag bit for bit (by id), the summed
-    exchange up to the order of its sums, and both match the oracle's rollout."""
+    (both sync the arrays) match the run without the flag.  The two runs file packets
+    differently, so they agree to rounding (a TSC packet's gather differs by rounding
+    between the quad loop and the per-packet phase), and both match the oracle's
+    rollout."""
     torch = _torch()
     from paper_2111_14704_amd.sim import Simulation
     w = make_workload(2, n=16, ppc=8, precision=precision)
@@ -382,11 +387,13 @@ def test_resident_cell_lists(precision):
         x, u = sim.state_by_id()
         out.append((x, u, dM.cpu().numpy(), sim.dt, rho.cpu().numpy(), P.cpu().numpy()))
     (x0, u0, d0, dt, r0, P0), (x1, u1, d1, _, r1, P1) = out
-    assert np.array_equal(x0, x1) and np.array_equal(u0, u1)
-    assert rel_l2(r1, r0) <= 1e-13 and rel_l2(P1, P0) <= 1e-13
-    # FP64: only the order of the atomic sums differs; FP32: a packet's slot also decides
-    # the order of the FP32 partial sums a quad keeps in registers
-    assert rel_l2(d1, d0) <= (1e-13 if precision == "fp64" else 1e-6)
+    fp64 = precision == "fp64"
+    assert np.max(periodic_distance(x1, x0, w.box)) / w.dx <= (1e-12 if fp64 else 1e-4)
+    assert max_rel_momentum(u1, u0) <= (1e-13 if fp64 else 1e-5)
+    assert rel_l2(r1, r0) <= (1e-13 if fp64 else 1e-6) and rel_l2(P1, P0) <= (1e-13 if fp64 else 1e-5)
+    # FP32: a packet's slot also decides the order of the FP32 partial sums a quad keeps
+    # in registers
+    assert rel_l2(d1, d0) <= (1e-12 if fp64 else 1e-5)
     # the oracle: 8 steps, a drift with the momenta as they stand, 4 steps
     p = oracle_params(w, dt=dt)
     E, B = oracle_fields(w)
