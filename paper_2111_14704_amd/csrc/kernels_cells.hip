@@ -726,14 +726,15 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
           #pragma unroll
           for (int i = 0; i < 12; ++i) w[i] = wj[i];
           const T mine = wj[12 + q];
+          // the x weights scaled by this lane's exchange value: three products instead of
+          // one per y-z pair
+          const T wxq[3] = {w[0] * mine, w[1] * mine, w[2] * mine};
           #pragma unroll
           for (int c = 0; c < 3; ++c)
             #pragma unroll
-            for (int b = 0; b < 3; ++b) {
-              const T wq = w[3 + b + 3 * c] * mine;
+            for (int b = 0; b < 3; ++b)
               #pragma unroll
-              for (int a = 0; a < 3; ++a) D[a + 3 * (b + 3 * c)] += w[a] * wq;
-            }
+              for (int a = 0; a < 3; ++a) D[a + 3 * (b + 3 * c)] += wxq[a] * w[3 + b + 3 * c];
         }
       }
       wave_sync();
