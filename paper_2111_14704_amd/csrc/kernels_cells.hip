@@ -452,17 +452,18 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
   // load has two rounds to arrive); slots past the cell's count hold stale data that
   // the lane ignores, so every round issues the same loads
   T pua[3], pub[3];
-  double pxa[3], pxb[3];
+  using PX = typename std::conditional<is_fp64<T>(), double, float>::type;  // position or offset
+  PX pxa[3], pxb[3];
   int32_t pida, pidb;
   T pwa = T(1), pwb = T(1);
-  auto fetch = [&](int rd, double (&px)[3], T (&pu)[3], int32_t& pid, T& pw) {
+  auto fetch = [&](int rd, PX (&px)[3], T (&pu)[3], int32_t& pid, T& pw) {
     int kk = 4 * rd + q;
     kk = kk < V.cap ? kk : V.cap - 1;
     const int64_t j = ((int64_t)tile * V.cap + kk) * kCellTileCells + quad;
     #pragma unroll
     for (int d = 0; d < 3; ++d) {
       if constexpr (is_fp64<T>()) px[d] = S.x[d * S.stride + j];
-      else px[d] = (double)S.off[d * S.stride + j];
+      else px[d] = S.off[d * S.stride + j];
       pu[d] = su[d * S.stride + j];
     }
     pid = S.id[j];
@@ -588,7 +589,7 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
     auto flush = [&]() {
       store_slot<T, LOSS>(V.out, oj, ojc, oxn, ofn, oun, ow, oid, ocell);
     };
-    auto round = [&](const int rd, double (&px)[3], T (&pu)[3], int32_t& pid, T& pw) {
+    auto round = [&](const int rd, PX (&px)[3], T (&pu)[3], int32_t& pid, T& pw) {
       const bool act = 4 * rd + q < n;
       T f[3], u[3];
       double xa[3] = {0.0, 0.0, 0.0};
