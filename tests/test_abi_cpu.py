@@ -95,4 +95,6 @@ def test_null_handle_calls_fail_cleanly():
     assert L.rsol_step(None, 1, None, None) == -1
     assert L.rsol_step_coupled(None, 1, None, None, None, None) == -1
     assert L.rsol_check(None) == -1
+    assert L.rsol_sync_particles(None) == -1
+    assert L.rsol_moments(None, None, None, None) == -1
     assert L.rsol_destroy(None) == 0
