@@ -22,11 +22,15 @@
  *      FP32 form: cell[np] home cell (int32), off[3][np] in-cell offset in cells
  *                 (float, in [0, 1)), u[3][np] (float)
  *    u = gamma*beta, the packet momentum in units of m c; id[np] (int32) labels packets.
+ *    With RSOL_FLAG_RESIDENT the packets live in the library's cell lists between steps
+ *    and the registered arrays are current only after rsol_sync_particles (or any
+ *    entry point that reads them).
  *  - Every pointer argument is a DEVICE pointer owned by the caller unless stated.
  *    The library never allocates or frees device memory; it keeps the pointers given
  *    to rsol_init / rsol_set_* until rsol_destroy.
  *  - All work is enqueued on the stream given to rsol_init and is asynchronous;
- *    only rsol_courant_dt and rsol_check synchronise that stream.
+ *    only rsol_courant_dt, rsol_check, rsol_stray_count and rsol_timing_read
+ *    synchronise that stream.
  *  - Every call returns RSOL_OK (0) or a negative status; rsol_last_error gives the
  *    message.  No C++ exception crosses this boundary.
  *  - Calls on one handle must not overlap from several host threads.
