@@ -405,6 +405,36 @@ def test_resident_cell_lists(precision):
     assert max_rel_momentum(u1, r2["u"]) <= tol
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_moments_tiled_and_global_agree(precision, monkeypatch):
+    """rsol_moments accumulates per tile in LDS after a permutation-only sort; with 8^3
+    tiles (RSOL_TILE) the region does not fit and the one-thread-per-packet kernel with
+    global atomics runs instead.  Both agree to the order of their sums and with the
+    oracle's moments, on a TSC state with weights (losses registered, sigma = 0)."""
+    torch = _torch()
+    from paper_2111_14704_amd.sim import Simulation
+    from workloads import loss_state
+    w = make_workload(2, n=16, ppc=8, precision=precision)
+    nn, _, _ = loss_state(w)
+    wt = np.random.default_rng(2).uniform(0.5, 1.0, w.n_particles)
+    _say(f"moments tiled vs global {precision}")
+    out = []
+    for tile in (None, "8,8,8"):
+        if tile:
+            monkeypatch.setenv("RSOL_TILE", tile)
+        sim = Simulation.from_workload(w, flags=8)
+        sim.set_losses(0.0, nn, wt)
+        rho, P, e = sim.moments()
+        torch.cuda.synchronize()
+        out.append([a.cpu().numpy() for a in (rho, P, e)])
+    p = oracle_params(w)
+    ref = oracle.moments(w.x, w.u, p, w=wt)
+    tol = 1e-13 if precision == "fp64" else 1e-6
+    for a, b, r in zip(out[0], out[1], ref):
+        assert rel_l2(a, b) <= 1e-13
+        assert rel_l2(a, r) <= tol
+
+
 def test_empty_and_single_packet():
     """No packets: every call is a no-op.  One packet: matches the oracle."""
     torch = _torch()
