@@ -1151,7 +1151,30 @@ __device__ __forceinline__ void copy_out(const Packets<T>& P, const SlotArrays& 
   if (P.w && S.w) P.w[o] = ((const T*)S.w)[j];
 }
 
-// Every occupied slot of buffer cur -> caller arrays at its prefix-sum offset.
+// The buckets of buffer cur -> caller arrays, one wave per cell: the lanes take the
+// cell's slots and write its contiguous output range.  A workgroup's 16 waves take the
+// 16 cells of one z-plane of a tile, whose slots share the lines of each slot row, so a
+// line is read by the waves together.
+constexpr int kCompactThreads = 1024;
+template <typename T>
+__global__ void __launch_bounds__(kCompactThreads) cells_compact_buckets_kernel(Packets<T> P, CellLists L,
+                                                                                const int32_t* __restrict__ offs,
+                                                                                RunConsts k) {
+  const SlotArrays& S = L.buf[L.cur];
+  const int64_t t = blockIdx.x / kCellTile;
+  const int lz = (int)(blockIdx.x - t * kCellTile);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;  // w = lx + 4 ly
+  const int lc = w + kCellTile * kCellTile * lz;
+  const int gx = (int)(t % L.ntx) * kCellTile + (w & 3), gy = (int)((t / L.ntx) % L.nty) * kCellTile + (w >> 2),
+            gz = (int)(t / ((int64_t)L.ntx * L.nty)) * kCellTile + lz;
+  if (gx >= k.nx || gy >= k.ny || gz >= k.nz) return;
+  const int64_t c = gx + (int64_t)k.nx * (gy + (int64_t)k.ny * gz);
+  const int n = offs[c + 1] - offs[c];  // clamped to the bucket capacity by the counts
+  for (int sl = lane; sl < n; sl += 64) copy_out<T>(P, S, (t * L.cap + sl) * kCellTileCells + lc, offs[c] + sl, (int32_t)c);
+}
+
+// The inbox parts and the overflow list of buffer cur -> caller arrays at their
+// prefix-sum offsets (each part's slots write one contiguous run).
 template <typename T>
 __global__ void cells_compact_kernel(Packets<T> P, CellLists L, const int32_t* __restrict__ offs, RunConsts k) {
   const SlotArrays& S = L.buf[L.cur];
@@ -1159,19 +1182,9 @@ __global__ void cells_compact_kernel(Packets<T> P, CellLists L, const int32_t* _
   const int64_t nslot = L.ib0, islots = L.ov0 - L.ib0;
   const int64_t total = L.ov0 + L.ocap;
   const int64_t obase = nc + L.ntiles * kDirs;
-  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < total; s += (int64_t)gridDim.x * blockDim.x) {
-    if (s < nslot) {
-      const int lc = (int)(s % kCellTileCells);
-      const int64_t ts = s / kCellTileCells;
-      const int sl = (int)(ts % L.cap);
-      const int64_t t = ts / L.cap;
-      const int gx = (int)(t % L.ntx) * kCellTile + (lc & 3), gy = (int)((t / L.ntx) % L.nty) * kCellTile + ((lc >> 2) & 3),
-                gz = (int)(t / ((int64_t)L.ntx * L.nty)) * kCellTile + (lc >> 4);
-      if (gx >= k.nx || gy >= k.ny || gz >= k.nz) continue;
-      const int64_t c = gx + (int64_t)k.nx * (gy + (int64_t)k.ny * gz);
-      if (sl >= offs[c + 1] - offs[c]) continue;
-      copy_out<T>(P, S, s, offs[c] + sl, (int32_t)c);
-    } else if (s < nslot + islots) {
+  for (int64_t s = nslot + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < total;
+       s += (int64_t)gridDim.x * blockDim.x) {
+    if (s < nslot + islots) {
       const int64_t si = s - nslot;
       const int64_t t = si / L.per_tile;
       const int r = (int)(si - t * L.per_tile);
@@ -1366,7 +1379,10 @@ hipError_t launch_cells_compact(const Packets<T>& P, CellLists& L, const RunCons
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(scan_total_kernel, dim3(1), dim3(1), 0, s, offs, counts, nscan);
   const int64_t total = L.ov0 + L.ocap;
-  hipLaunchKernelGGL(cells_compact_kernel<T>, dim3(grid_for(total)), dim3(kThreads), 0, s, P, L, offs, k);
+  if (L.ntiles > 0)
+    hipLaunchKernelGGL(cells_compact_buckets_kernel<T>, dim3((unsigned)(L.ntiles * kCellTile)), dim3(kCompactThreads),
+                       0, s, P, L, offs, k);
+  hipLaunchKernelGGL(cells_compact_kernel<T>, dim3(grid_for(total - L.ib0)), dim3(kThreads), 0, s, P, L, offs, k);
   return hipGetLastError();
 }
 
