@@ -390,9 +390,12 @@ __device__ __forceinline__ uint32_t drift3(const RunConsts& k, const int home[3]
 // LOSS: catastrophic losses.  The tile stages the nucleon density NN as a seventh
 // field, the quad's lane 3 (idle in the field gather otherwise) gathers it, and the
 // packet weight travels with the packet through the slot stores.  PUSH: the momentum
-// update (Boris, Vay or Higuera-Cary).
+// update (Boris, Vay or Higuera-Cary).  FP64 TSC without losses runs two workgroups per
+// CU: it then fits in 256 registers (two waves per SIMD, a few values spilled outside
+// the quad loop); with losses the same bound spills inside the loop, and with CIC the
+// step measured 2% slower at two waves than at one.
 template <int M, typename T, bool DEP, bool LOSS, int PUSH>
-__global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const T* __restrict__ E,
+__global__ void __launch_bounds__(kThreads, (is_fp64<T>() && M == 3 && !LOSS) ? 2 : 1) cells_step_kernel(StepView V, const T* __restrict__ E,
                                                               const T* __restrict__ B, const T* __restrict__ NN,
                                                               double* __restrict__ dM, double* __restrict__ dE,
                                                               RunConsts k) {
@@ -736,6 +739,15 @@ __global__ void __launch_bounds__(kThreads) cells_step_kernel(StepView V, const 
             for (int b = 0; b < 3; ++b)
               #pragma unroll
               for (int a = 0; a < 3; ++a) D[a + 3 * (b + 3 * c)] += wxq[a] * w[3 + b + 3 * c];
+        }
+        // FP64: the accumulation happens here.  Left to itself the compiler sinks these
+        // FMAs past the drift and the slot placement, keeping the 52 values read above
+        // live across them (357 registers, one wave per SIMD; pinned here: 256 and two).
+        // FP32 keeps the compiler's order: pinned, it drops to three waves per SIMD,
+        // which measured no faster with TSC and 4% slower with CIC.
+        if constexpr (is_fp64<T>()) {
+          #pragma unroll
+          for (int i = 0; i < 27; ++i) asm volatile("" : "+v"(D[i]));
         }
       }
       wave_sync();
