@@ -175,14 +175,21 @@ __device__ __forceinline__ void gather27(const T* w, F fetch, T out[NC]) {
     }
 }
 
-// Bucket slot s of the cell with grid coordinates h: buckets are laid out tile by
-// tile as [slot][cell in tile], so the 16 cells a wave works on keep each slot
-// row in whole cache lines.
+// Bucket slot s of local cell lc of tile t (cap a multiple of kSlotGroup): a tile's
+// buckets are laid out as [slot group][cell in tile][slot in group].  A quad round
+// reads one group of each of its wave's 16 cells (whole cache lines), and the four
+// packets a cell files in a round mostly land in one group (one 32-byte sector in
+// FP64) instead of in four rows a cache line apart.
+__device__ __forceinline__ int64_t slot_index(int64_t t, int s, int lc, int cap) {
+  return ((t * (cap / kSlotGroup) + s / kSlotGroup) * kCellTileCells + lc) * kSlotGroup + s % kSlotGroup;
+}
+
+// Bucket slot s of the cell with grid coordinates h.
 __device__ __forceinline__ int64_t bucket_index(const int h[3], int s, int ntx, int nty, int cap) {
   const int tx = h[0] / kCellTile, ty = h[1] / kCellTile, tz = h[2] / kCellTile;
   const int64_t t = tx + (int64_t)ntx * (ty + (int64_t)nty * tz);
   const int lc = (h[0] - tx * kCellTile) + kCellTile * ((h[1] - ty * kCellTile) + kCellTile * (h[2] - tz * kCellTile));
-  return (t * cap + s) * kCellTileCells + lc;
+  return slot_index(t, s, lc, cap);
 }
 
 __device__ __forceinline__ void cell_coords(int c, const RunConsts& k, int h[3]) {
@@ -313,7 +320,7 @@ __device__ __forceinline__ int64_t place(const StepView& V, int ttx, int tty, in
     if (slot < V.cap) {
       *bucket = true;
       const int64_t t = tx + (int64_t)V.ntx * (ty + (int64_t)V.nty * tz);
-      return (t * V.cap + slot) * kCellTileCells + local;
+      return slot_index(t, slot, local, V.cap);
     }
   }
   const int s = atomicAdd(&cntD[dir], 1);
@@ -462,7 +469,7 @@ __global__ void __launch_bounds__(kThreads, (is_fp64<T>() && M == 3 && !LOSS) ? 
   auto fetch = [&](int rd, PX (&px)[3], T (&pu)[3], int32_t& pid, T& pw) {
     int kk = 4 * rd + q;
     kk = kk < V.cap ? kk : V.cap - 1;
-    const int64_t j = ((int64_t)tile * V.cap + kk) * kCellTileCells + quad;
+    const int64_t j = slot_index(tile, kk, quad, V.cap);
     #pragma unroll
     for (int d = 0; d < 3; ++d) {
       if constexpr (is_fp64<T>()) px[d] = S.x[d * S.stride + j];
@@ -857,7 +864,7 @@ __global__ void __launch_bounds__(kThreads, (is_fp64<T>() && M == 3 && !LOSS) ? 
         home[0] = ttx * kCellTile + (lc & 3);
         home[1] = tty * kCellTile + ((lc >> 2) & 3);
         home[2] = ttz * kCellTile + (lc >> 4);
-        const int64_t j = ((int64_t)tile * V.cap + 4 * R + (i - sLo[lc])) * kCellTileCells + lc;
+        const int64_t j = slot_index(tile, 4 * R + (i - sLo[lc]), lc, V.cap);
         #pragma unroll
         for (int d = 0; d < 3; ++d) {
           if constexpr (is_fp64<T>()) {
@@ -1182,7 +1189,7 @@ __global__ void __launch_bounds__(kCompactThreads) cells_compact_buckets_kernel(
   if (gx >= k.nx || gy >= k.ny || gz >= k.nz) return;
   const int64_t c = gx + (int64_t)k.nx * (gy + (int64_t)k.ny * gz);
   const int n = offs[c + 1] - offs[c];  // clamped to the bucket capacity by the counts
-  for (int sl = lane; sl < n; sl += 64) copy_out<T>(P, S, (t * L.cap + sl) * kCellTileCells + lc, offs[c] + sl, (int32_t)c);
+  for (int sl = lane; sl < n; sl += 64) copy_out<T>(P, S, slot_index(t, sl, lc, L.cap), offs[c] + sl, (int32_t)c);
 }
 
 // The inbox parts and the overflow list of buffer cur -> caller arrays at their
@@ -1270,7 +1277,7 @@ CellLists carve(int nx, int ny, int nz, int64_t np, int precision, bool weights,
   // self (full buckets) and faces take four buckets' worth, edges one, corners a
   // quarter.
   const int64_t mean = (np + ncells - 1) / ncells;
-  L.cap = (int)(2 * mean + 16);
+  L.cap = (int)((2 * mean + 16 + kSlotGroup - 1) / kSlotGroup * kSlotGroup);
   int off = 0;
   for (int d = 0; d < kDirs; ++d) {
     const int axes = (d % 3 != 1) + ((d / 3) % 3 != 1) + (d / 9 != 1);

@@ -13,6 +13,7 @@ namespace rsol {
 
 constexpr int kCellTile = 4;                         // tile edge (cells)
 constexpr int kCellTileCells = 64;                   // cells per tile
+constexpr int kSlotGroup = 4;                        // consecutive bucket slots of a cell in memory
 constexpr int kRegionEdge = kCellTile + 2;           // tile + one-cell halo
 constexpr int kRegionCells = kRegionEdge * kRegionEdge * kRegionEdge;
 constexpr int kDirs = 27;                            // 3x3x3 tile offsets, index (dx+1) + 3 (dy+1) + 9 (dz+1)
@@ -38,9 +39,10 @@ struct SlotArrays {
 // overflow list and a few trash slots that idle lanes write to.  A packet's place
 // is therefore a single slot index.
 //
-// Buckets are laid out tile by tile as [slot][cell in tile]: slot s of local cell lc
-// of tile t is (t*cap + s)*64 + lc, so the 16 cells a wave works on keep each slot
-// row in whole cache lines.  Every tile has an inbox split into 27 parts by the tile
+// Buckets are laid out tile by tile as [slot group][cell in tile][slot in group]:
+// slot s of local cell lc of tile t is ((t*cap/4 + s/4)*64 + lc)*4 + s%4 (cap a
+// multiple of 4), so a quad round reads whole cache lines and the packets a cell
+// files in one round share a 32-byte sector.  Every tile has an inbox split into 27 parts by the tile
 // offset a packet moved by: part dir of tile t holds packets that came from the tile
 // at t - dir, which is that part's only writer (slots from an LDS counter, the final
 // count stored with a plain store).  The self part (kSelfDir) takes a tile's own

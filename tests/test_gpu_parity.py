@@ -129,7 +129,7 @@ def test_alfven_tsc_small(precision, tol, path, sort_every):
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
 def test_cells_overflow_stores(precision, tol):
     """Cell-list path with a clustered start: 1500 of 2012 packets in one cell of an 8^3
-    grid overfill that cell's bucket (capacity 2*ceil(np/cells)+16 = 24) and its tile's
+    grid overfill that cell's bucket (capacity 2*ceil(np/cells)+16, a multiple of 4, = 24) and its tile's
     inbox (16*24+256 = 640), so packets also take the grid-wide overflow list; all three
     stores must give the oracle's result, several steps in a row, in one rsol_step call
     and one step per call.  The two runs file packets differently: with TSC a packet the
