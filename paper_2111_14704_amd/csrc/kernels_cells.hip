@@ -397,12 +397,17 @@ __device__ __forceinline__ uint32_t drift3(const RunConsts& k, const int home[3]
 // LOSS: catastrophic losses.  The tile stages the nucleon density NN as a seventh
 // field, the quad's lane 3 (idle in the field gather otherwise) gathers it, and the
 // packet weight travels with the packet through the slot stores.  PUSH: the momentum
-// update (Boris, Vay or Higuera-Cary).  FP64 TSC without losses runs two workgroups per
-// CU: it then fits in 256 registers (two waves per SIMD, a few values spilled outside
-// the quad loop); with losses the same bound spills inside the loop, and with CIC the
-// step measured 2% slower at two waves than at one.
+// update (Boris, Vay or Higuera-Cary).  two_wave_step() variants, FP64 without losses,
+// run two workgroups per CU (two waves per SIMD, 256 registers) and prefetch packets
+// one quad round ahead instead of two; the loss variants would spill inside the loop
+// under that bound, and FP32 reaches two waves by itself.
+template <int M, typename T, bool LOSS>
+constexpr bool two_wave_step() {
+  return is_fp64<T>() && !LOSS;
+}
+
 template <int M, typename T, bool DEP, bool LOSS, int PUSH>
-__global__ void __launch_bounds__(kThreads, (is_fp64<T>() && M == 3 && !LOSS) ? 2 : 1) cells_step_kernel(StepView V, const T* __restrict__ E,
+__global__ void __launch_bounds__(kThreads, (two_wave_step<M, T, LOSS>() ? 2 : 1)) cells_step_kernel(StepView V, const T* __restrict__ E,
                                                               const T* __restrict__ B, const T* __restrict__ NN,
                                                               double* __restrict__ dM, double* __restrict__ dE,
                                                               RunConsts k) {
@@ -458,9 +463,12 @@ __global__ void __launch_bounds__(kThreads, (is_fp64<T>() && M == 3 && !LOSS) ? 
 
   const SlotArrays& S = V.in;
   const T* su = (const T*)S.u;
-  // packet state of the next two rounds (two register sets used alternately, so a
-  // load has two rounds to arrive); slots past the cell's count hold stale data that
-  // the lane ignores, so every round issues the same loads
+  // packet state of the next rounds: two register sets used alternately, so a load has
+  // two rounds to arrive, or, with two waves per SIMD, one set a round ahead (the other
+  // wave covers the latency, and the registers saved keep the loop free of spills:
+  // with two sets the FP64 step spilled to scratch inside the loop and its reloads
+  // waited on every outstanding load).  Slots past the cell's count hold stale data
+  // that the lane ignores, so every round issues the same loads
   T pua[3], pub[3];
   using PX = typename std::conditional<is_fp64<T>(), double, float>::type;  // position or offset
   PX pxa[3], pxb[3];
@@ -479,8 +487,9 @@ __global__ void __launch_bounds__(kThreads, (is_fp64<T>() && M == 3 && !LOSS) ? 
     pid = S.id[j];
     if constexpr (LOSS) pw = ((const T*)S.w)[j];
   };
+  constexpr int kDepth = two_wave_step<M, T, LOSS>() ? 1 : 2;
   fetch(0, pxa, pua, pida, pwa);
-  fetch(1, pxb, pub, pidb, pwb);
+  if constexpr (kDepth == 2) fetch(1, pxb, pub, pidb, pwb);
   // this tile's inbox counts by direction, one per lane of the first wave
   const int cin = threadIdx.x < kDirs ? V.icnt_in[(int64_t)tile * kDirs + threadIdx.x] : 0;
 
@@ -617,7 +626,7 @@ __global__ void __launch_bounds__(kThreads, (is_fp64<T>() && M == 3 && !LOSS) ? 
         u[d] = act ? pu[d] : T(0);
       }
       flush();
-      fetch(rd + 2, px, pu, pid, pw);
+      fetch(rd + kDepth, px, pu, pid, pw);
 
       // own weights -> LDS: x weights, then the nine y-z products
       {
@@ -777,7 +786,8 @@ __global__ void __launch_bounds__(kThreads, (is_fp64<T>() && M == 3 && !LOSS) ? 
     for (int rd = 0; __ballot(rd < rounds) != 0; rd += 2) {
       round(rd, pxa, pua, pida, pwa);
       if (__ballot(rd + 1 < rounds) == 0) break;
-      round(rd + 1, pxb, pub, pidb, pwb);
+      if constexpr (kDepth == 1) round(rd + 1, pxa, pua, pida, pwa);
+      else round(rd + 1, pxb, pub, pidb, pwb);
     }
     flush();
     if (deposit && n > 0) {
