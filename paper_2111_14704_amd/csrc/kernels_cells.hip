@@ -397,17 +397,21 @@ __device__ __forceinline__ uint32_t drift3(const RunConsts& k, const int home[3]
 // LOSS: catastrophic losses.  The tile stages the nucleon density NN as a seventh
 // field, the quad's lane 3 (idle in the field gather otherwise) gathers it, and the
 // packet weight travels with the packet through the slot stores.  PUSH: the momentum
-// update (Boris, Vay or Higuera-Cary).  two_wave_step() variants, FP64 without losses,
-// run two workgroups per CU (two waves per SIMD, 256 registers) and prefetch packets
-// one quad round ahead instead of two; the loss variants would spill inside the loop
-// under that bound, and FP32 reaches two waves by itself.
-template <int M, typename T, bool LOSS>
+// update (Boris, Vay or Higuera-Cary).  FP64 without losses runs two workgroups per CU
+// (two waves per SIMD, 256 registers; with losses that bound spills inside the loop)
+// and FP32 three by its register count.  Both prefetch packets one quad round ahead;
+// the FP64 loss variants, at one wave per SIMD, two rounds ahead.
+template <typename T, bool LOSS>
 constexpr bool two_wave_step() {
   return is_fp64<T>() && !LOSS;
 }
+template <typename T, bool LOSS>
+constexpr int prefetch_depth() {
+  return (is_fp64<T>() && LOSS) ? 2 : 1;
+}
 
 template <int M, typename T, bool DEP, bool LOSS, int PUSH>
-__global__ void __launch_bounds__(kThreads, (two_wave_step<M, T, LOSS>() ? 2 : 1)) cells_step_kernel(StepView V, const T* __restrict__ E,
+__global__ void __launch_bounds__(kThreads, (two_wave_step<T, LOSS>() ? 2 : 1)) cells_step_kernel(StepView V, const T* __restrict__ E,
                                                               const T* __restrict__ B, const T* __restrict__ NN,
                                                               double* __restrict__ dM, double* __restrict__ dE,
                                                               RunConsts k) {
@@ -463,12 +467,12 @@ __global__ void __launch_bounds__(kThreads, (two_wave_step<M, T, LOSS>() ? 2 : 1
 
   const SlotArrays& S = V.in;
   const T* su = (const T*)S.u;
-  // packet state of the next rounds: two register sets used alternately, so a load has
-  // two rounds to arrive, or, with two waves per SIMD, one set a round ahead (the other
-  // wave covers the latency, and the registers saved keep the loop free of spills:
-  // with two sets the FP64 step spilled to scratch inside the loop and its reloads
-  // waited on every outstanding load).  Slots past the cell's count hold stale data
-  // that the lane ignores, so every round issues the same loads
+  // packet state of the next rounds: one register set filled a round ahead (the other
+  // waves of the SIMD cover the load latency, and the registers saved keep the FP64
+  // loop free of spills: with two sets it spilled to scratch inside the loop, and its
+  // reloads waited on every outstanding load), or, at one wave per SIMD, two sets used
+  // alternately so that a load has two rounds to arrive.  Slots past the cell's count
+  // hold stale data that the lane ignores, so every round issues the same loads
   T pua[3], pub[3];
   using PX = typename std::conditional<is_fp64<T>(), double, float>::type;  // position or offset
   PX pxa[3], pxb[3];
@@ -487,7 +491,7 @@ __global__ void __launch_bounds__(kThreads, (two_wave_step<M, T, LOSS>() ? 2 : 1
     pid = S.id[j];
     if constexpr (LOSS) pw = ((const T*)S.w)[j];
   };
-  constexpr int kDepth = two_wave_step<M, T, LOSS>() ? 1 : 2;
+  constexpr int kDepth = prefetch_depth<T, LOSS>();
   fetch(0, pxa, pua, pida, pwa);
   if constexpr (kDepth == 2) fetch(1, pxb, pub, pidb, pwb);
   // this tile's inbox counts by direction, one per lane of the first wave
@@ -756,15 +760,11 @@ __global__ void __launch_bounds__(kThreads, (two_wave_step<M, T, LOSS>() ? 2 : 1
               #pragma unroll
               for (int a = 0; a < 3; ++a) D[a + 3 * (b + 3 * c)] += wxq[a] * w[3 + b + 3 * c];
         }
-        // FP64: the accumulation happens here.  Left to itself the compiler sinks these
-        // FMAs past the drift and the slot placement, keeping the 52 values read above
-        // live across them (357 registers, one wave per SIMD; pinned here: 256 and two).
-        // FP32 keeps the compiler's order: pinned, it drops to three waves per SIMD,
-        // which measured no faster with TSC and 4% slower with CIC.
-        if constexpr (is_fp64<T>()) {
-          #pragma unroll
-          for (int i = 0; i < 27; ++i) asm volatile("" : "+v"(D[i]));
-        }
+        // the accumulation happens here: left to itself the compiler sinks these FMAs
+        // past the drift and the slot placement, keeping the 52 values read above live
+        // across them (FP64 357 registers and one wave per SIMD, FP32 209 and two)
+        #pragma unroll
+        for (int i = 0; i < 27; ++i) asm volatile("" : "+v"(D[i]));
       }
       wave_sync();
 
