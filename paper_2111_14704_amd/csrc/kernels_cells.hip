@@ -471,8 +471,9 @@ __global__ void __launch_bounds__(kThreads, (two_wave_step<T, LOSS>() ? 2 : 1)) 
   // waves of the SIMD cover the load latency, and the registers saved keep the FP64
   // loop free of spills: with two sets it spilled to scratch inside the loop, and its
   // reloads waited on every outstanding load), or, at one wave per SIMD, two sets used
-  // alternately so that a load has two rounds to arrive.  Slots past the cell's count
-  // hold stale data that the lane ignores, so every round issues the same loads
+  // alternately so that a load has two rounds to arrive.  The first rounds load
+  // before the cell's count is known, whatever the slots hold (stale data the lane
+  // ignores); in the loop a lane past its cell's count skips the load
   T pua[3], pub[3];
   using PX = typename std::conditional<is_fp64<T>(), double, float>::type;  // position or offset
   PX pxa[3], pxb[3];
@@ -630,7 +631,7 @@ __global__ void __launch_bounds__(kThreads, (two_wave_step<T, LOSS>() ? 2 : 1)) 
         u[d] = act ? pu[d] : T(0);
       }
       flush();
-      fetch(rd + kDepth, px, pu, pid, pw);
+      if (4 * (rd + kDepth) + q < n) fetch(rd + kDepth, px, pu, pid, pw);
 
       // own weights -> LDS: x weights, then the nine y-z products
       {
