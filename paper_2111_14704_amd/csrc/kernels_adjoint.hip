@@ -352,8 +352,11 @@ __global__ void __launch_bounds__(kBlock) step_backward_kernel(const void* __res
 // the region to the grid with one atomic per node and component.  A packet whose
 // stencil leaves the region (it moved further than the halo allows since the sort) is
 // appended to `spill` (count in spill[0], packet indices after it) for
-// step_backward_list_kernel.
-template <int M, typename T>
+// step_backward_list_kernel.  LD false: no exchange adjoint (lam_dM NULL) and no Ls
+// region staged, which lets FP32 CIC run three workgroups per CU (TSC keeps the region
+// and checks lam_dM at run time: without it the compiler's allocation of FP32 TSC grew
+// to one wave per SIMD).
+template <int M, typename T, bool LD>
 __global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> slab,
                                                                      const int32_t* __restrict__ offsets, Tiling tl,
                                                                      int halo, int parts, int32_t* __restrict__ spill,
@@ -365,7 +368,7 @@ __global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> 
                                                                      double* __restrict__ gE, double* __restrict__ gB,
                                                                      RunConsts k) {
   __shared__ T Fs[6 * kAdjRegion];
-  __shared__ double Ls[4 * kAdjRegion];
+  __shared__ double Ls[LD ? 4 * kAdjRegion : 1];
   __shared__ double Gs[6 * kAdjRegion];
   const int64_t tile = blockIdx.x / parts;
   const int part = blockIdx.x - (int)(tile * parts);
@@ -377,7 +380,7 @@ __global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> 
   const int rc = rx * ry * rz;
   const int pz = region_plane_pitch(rx, ry);
   const int64_t nc = k.ncells, np = slab.np;
-  const bool ld = lam_dM != nullptr;
+  const bool ld = LD && lam_dM != nullptr;
   for (int r = threadIdx.x; r < rc; r += blockDim.x) {
     const int ax = r % rx, ay = (r / rx) % ry, az = r / (rx * ry);
     const int64_t g = wrap_mod(ox + ax, k.nx) + (int64_t)k.nx * (wrap_mod(oy + ay, k.ny) + (int64_t)k.ny * wrap_mod(oz + az, k.nz));
@@ -387,10 +390,12 @@ __global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> 
       Fs[d * kAdjRegion + s] = E[d * nc + g];
       Fs[(3 + d) * kAdjRegion + s] = B[d * nc + g];
     }
-    if (ld) {
-      #pragma unroll
-      for (int d = 0; d < 3; ++d) Ls[d * kAdjRegion + s] = lam_dM[d * nc + g];
-      Ls[3 * kAdjRegion + s] = lam_dE ? lam_dE[g] : 0.0;
+    if constexpr (LD) {
+      if (ld) {
+        #pragma unroll
+        for (int d = 0; d < 3; ++d) Ls[d * kAdjRegion + s] = lam_dM[d * nc + g];
+        Ls[3 * kAdjRegion + s] = lam_dE ? lam_dE[g] : 0.0;
+      }
     }
     #pragma unroll
     for (int d = 0; d < 6; ++d) Gs[d * kAdjRegion + s] = 0.0;
@@ -636,12 +641,16 @@ hipError_t launch_step_backward_tiled(int shape, const Packets<T>& slab, const i
   hipLaunchKernelGGL(clear_count_kernel, dim3(1), dim3(1), 0, s, spill);
   const dim3 lgrid((unsigned)(grid_for(slab.np) < 256 ? grid_for(slab.np) : 256));
   if (shape == kShapeCIC) {
-    hipLaunchKernelGGL((step_backward_tiled_kernel<2, T>), grid, dim3(kBlock), 0, s, slab, offsets, t, halo,
-                       parts, spill, lam_x, lam_u, E, B, lam_dM, lam_dE, gE, gB, k);
+    if (lam_dM)
+      hipLaunchKernelGGL((step_backward_tiled_kernel<2, T, true>), grid, dim3(kBlock), 0, s, slab, offsets, t, halo,
+                         parts, spill, lam_x, lam_u, E, B, lam_dM, lam_dE, gE, gB, k);
+    else
+      hipLaunchKernelGGL((step_backward_tiled_kernel<2, T, false>), grid, dim3(kBlock), 0, s, slab, offsets, t,
+                         halo, parts, spill, lam_x, lam_u, E, B, lam_dM, lam_dE, gE, gB, k);
     hipLaunchKernelGGL((step_backward_list_kernel<2, T>), lgrid, dim3(kBlock), 0, s, slab, spill, lam_x, lam_u, E, B,
                        lam_dM, lam_dE, gE, gB, k);
   } else {
-    hipLaunchKernelGGL((step_backward_tiled_kernel<3, T>), grid, dim3(kBlock), 0, s, slab, offsets, t, halo,
+    hipLaunchKernelGGL((step_backward_tiled_kernel<3, T, true>), grid, dim3(kBlock), 0, s, slab, offsets, t, halo,
                        parts, spill, lam_x, lam_u, E, B, lam_dM, lam_dE, gE, gB, k);
     hipLaunchKernelGGL((step_backward_list_kernel<3, T>), lgrid, dim3(kBlock), 0, s, slab, spill, lam_x, lam_u, E, B,
                        lam_dM, lam_dE, gE, gB, k);
