@@ -66,7 +66,8 @@ def courant_dt(u, B, c, c_tilde, qomc, dx, courant, naive=False, sigma=0.0, nn=N
     beta = np.sqrt(u[0] ** 2 + u[1] ** 2 + u[2] ** 2) / gamma
     bmag = np.sqrt(np.sum(np.asarray(B).reshape(3, -1) ** 2, axis=0))
     dt_cell = courant * dx / (c_tilde * np.max(beta))
-    omega_max = (1.0 if naive else c_tilde / c) * qomc * np.max(bmag) / np.min(gamma)
+    # the limit concerns the gyro frequency's magnitude, whatever the sign of the charge
+    omega_max = (1.0 if naive else c_tilde / c) * abs(qomc) * np.max(bmag) / np.min(gamma)
     dt_gyro = courant / omega_max
     dt = min(dt_cell, dt_gyro)
     if sigma > 0 and nn is not None and np.max(nn) > 0 and np.max(beta) > 0:
@@ -309,8 +310,11 @@ def rollout_with_losses(x, u, w, E, B, nn, sigma, p: Params, nsteps):
 
 
 def wrap(x, length):
-    """Periodic wrap into [0, length); a result equal to length maps to 0."""
+    """Periodic wrap into [0, length): x - length floor(x/length); a result equal to
+    length maps to 0, and so does a tiny negative x whose quotient underflows to -0
+    (it would otherwise stay negative)."""
     y = x - length * np.floor(np.real(x) / length)
+    y = np.where(np.real(y) < 0, y + length, y)
     return np.where(np.real(y) >= length, y - length, y)
 
 

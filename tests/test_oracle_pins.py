@@ -373,6 +373,156 @@ def test_courant_dt_scaling_and_guarantees():
     assert np.max(np.arccos(np.clip(cosang, -1, 1))) <= 2 * math.atan(w.courant / 2) + 1e-9
 
 
+def _rotation_angles(u0, u1):
+    """Signed rotation angle of each packet's momentum about +x between two states
+    (in uniform B along x the parallel component is untouched)."""
+    return np.arctan2(u0[1] * u1[2] - u0[2] * u1[1], u0[1] * u1[1] + u0[2] * u1[2])
+
+
+def _courant_pin_errors(ratio=10.0, qomc=4000.0):
+    """Relative errors of the timestep rule against what each of its limits guarantees
+    exactly when it binds (Sec. 4: dt < C / Omega_eff and dt < C dx / |v_eff|, with
+    Omega_eff = (c_tilde/c) q|B|/(gamma m c) from the closing discussion of Sec. 2 and
+    v_eff = c_tilde beta).  The measurements use the oracle's kick and drift, whose
+    rotation angle and drift speed are pinned separately above.
+
+    gyro: gyro-limited packets (|u| = 1 and 1.5) in a non-uniform |B| along x.  The
+      packet with the smallest gamma sits at the centre of the cell with the largest |B|
+      (CIC then reads that node alone), so it must rotate by exactly 2 atan(C/2) per
+      step, the largest rotation of all packets.
+    cell: cell-limited packets (|u| = 10 and one with |u| = 20) in uniform B: the
+      fastest packet must move exactly C dx in the step.
+    sign: a negative charge gives the same dt and the opposite rotation."""
+    n, c, courant = 8, 1000.0, 0.3
+    nc = n ** 3
+    rng = np.random.default_rng(17)
+    out = {}
+    # gyro limit with non-uniform |B| and several gammas
+    Bx = rng.uniform(0.5, 1.5, nc)
+    hot = int(np.argmax(Bx))
+    B = np.zeros((3, nc))
+    B[0] = Bx
+    E = np.zeros((3, nc))
+    cells = rng.choice(nc, 40, replace=False)
+    cells[0] = hot
+    ix, iy, iz = cells % n, (cells // n) % n, cells // (n * n)
+    x0 = np.stack([ix, iy, iz]).astype(float) + 0.5
+    mag = np.where(np.arange(40) < 20, 1.0, 1.5)
+    mag[0] = 1.0
+    phi = rng.uniform(0, 2 * np.pi, 40)
+    u0 = np.stack([np.zeros(40), mag * np.cos(phi), mag * np.sin(phi)])
+    dt = oracle.courant_dt(u0, B, c, c / ratio, qomc, 1.0, courant)
+    p = oracle.Params(n, n, n, 1.0, "cic", c, c / ratio, qomc, dt, 1.0)
+    _, u1, _, _ = oracle.step(x0, u0, E, B, p)
+    ang = _rotation_angles(u0, u1)
+    want = 2.0 * math.atan(courant / 2.0)
+    out["gyro"] = abs(float(np.max(np.abs(ang))) - want) / want
+    out["gyro_hot"] = abs(abs(float(ang[0])) - want) / want
+    out["sign_dt"] = ang[0]
+    # cell limit: uniform B, |u| = 10 packets and one at |u| = 20
+    Eu, Bu = _uniform_fields(n)
+    m = 64
+    x0 = rng.uniform(0, n, (3, m))
+    d = rng.standard_normal((3, m))
+    d /= np.linalg.norm(d, axis=0)
+    u0 = 10.0 * d
+    u0[:, 0] *= 2.0
+    dt = oracle.courant_dt(u0, Bu, c, c / ratio, qomc, 1.0, courant)
+    p = oracle.Params(n, n, n, 1.0, "cic", c, c / ratio, qomc, dt, 1.0)
+    x1, _, _, _ = oracle.step(x0, u0, Eu, Bu, p)
+    from tests.helpers import periodic_distance
+    moved = periodic_distance(x1, x0, (n, n, n))
+    out["cell"] = abs(float(np.max(moved)) - courant) / courant
+    out["cell_fastest"] = abs(float(moved[0]) - courant) / courant
+    return out
+
+
+@pytest.mark.parametrize("ratio", [1.0, 10.0, 100.0])
+def test_courant_dt_values_when_each_limit_binds(ratio):
+    """The timestep is exactly at each limit when that limit binds (Sec. 4): the packet
+    with the smallest Lorentz factor at the largest |B| rotates by 2 atan(C/2) per step
+    (Omega_eff dt = C), and the fastest packet of a cell-limited set moves C dx."""
+    e = _courant_pin_errors(ratio)
+    assert e["gyro"] < 1e-12 and e["gyro_hot"] < 1e-12
+    assert e["cell"] < 1e-12 and e["cell_fastest"] < 1e-12
+
+
+def test_courant_dt_of_a_negative_charge():
+    """A negative charge rotates the other way at the same gyro frequency: the same dt and
+    a rotation of -2 atan(C/2) where a positive charge turns by +2 atan(C/2)."""
+    pos, neg = _courant_pin_errors(10.0, 4000.0), _courant_pin_errors(10.0, -4000.0)
+    assert neg["gyro"] < 1e-12 and neg["cell"] < 1e-12
+    assert pos["sign_dt"] == pytest.approx(-neg["sign_dt"], rel=1e-14)
+    u = np.array([[0.0, 1.0], [1.0, 0.0], [0.0, 2.0]])
+    B = np.tile(np.array([[1.0], [0.0], [0.0]]), (1, 8))
+    assert oracle.courant_dt(u, B, 1000.0, 100.0, -4000.0, 1.0, 0.3) == oracle.courant_dt(u, B, 1000.0, 100.0, 4000.0,
+                                                                                          1.0, 0.3)
+
+
+def test_planted_mistakes_fail_the_courant_pins(monkeypatch):
+    """Each of these misreadings of the timestep rule fails a pin: either limit halved,
+    min |B| in place of max |B|, max gamma in place of min gamma, max beta replaced by
+    the mean beta."""
+    pic = oracle.pic
+    good = pic.courant_dt
+
+    def variant(gyro=1.0, cell=1.0, bsel=np.max, gsel=np.min, vsel=np.max):
+        def dt_rule(u, B, c, c_tilde, qomc, dx, courant, naive=False, sigma=0.0, nn=None):
+            gamma = pic.lorentz_gamma(u)
+            beta = np.sqrt(u[0] ** 2 + u[1] ** 2 + u[2] ** 2) / gamma
+            bmag = np.sqrt(np.sum(np.asarray(B).reshape(3, -1) ** 2, axis=0))
+            d_cell = cell * courant * dx / (c_tilde * vsel(beta))
+            d_gyro = gyro * courant / ((c_tilde / c) * abs(qomc) * bsel(bmag) / gsel(gamma))
+            return float(min(d_cell, d_gyro))
+        return dt_rule
+
+    assert max(_courant_pin_errors().values()) < 10.0  # sanity of the helper with the real rule
+    for kw, key in ((dict(gyro=0.5), "gyro"), (dict(cell=0.5), "cell"), (dict(bsel=np.min), "gyro"),
+                    (dict(gsel=np.max), "gyro"), (dict(vsel=np.mean), "cell")):
+        with monkeypatch.context() as m:
+            m.setattr(pic, "courant_dt", variant(**kw))
+            m.setattr(oracle, "courant_dt", variant(**kw))
+            e = _courant_pin_errors()
+            assert e[key] > 1e-3, (kw, e)
+    assert pic.courant_dt is good
+
+
+def test_periodic_wrap_ties():
+    """The periodic wrap maps every coordinate into [0, L): values already inside are
+    untouched, one period is added or removed exactly where that is representable, and
+    a result that rounds to L (a tiny negative coordinate) becomes 0, as does L itself."""
+    L = 16.0
+    tiny = 1e-300
+    below = np.nextafter(L, 0.0)
+    cases = [(-0.0, 0.0), (-tiny, 0.0), (0.0, 0.0), (tiny, tiny), (below, below), (L, 0.0),
+             (-0.5, 15.5), (L + 0.25, 0.25), (2 * L, 0.0), (-L, 0.0), (-np.nextafter(0.0, 1.0), 0.0),
+             (np.nextafter(2 * L, 0.0), np.nextafter(2 * L, 0.0) - L), (-3 * L - 2.0, L - 2.0)]
+    x = np.array([a for a, _ in cases])
+    got = oracle.wrap(x, L)
+    want = np.array([b for _, b in cases])
+    assert np.all(got >= 0.0) and np.all(got < L)
+    assert np.array_equal(got, want), (got, want)
+    # a drift that lands a hair below 0 leaves the packet at 0, inside the box
+    p = _uniform_params(4, "cic", 1.0, dt=1.0)
+    x0 = np.array([[0.0], [1.5], [2.5]])
+    u = np.array([[-tiny * 1e-8], [0.0], [0.0]])
+    x1 = oracle.drift(x0, u, p)
+    assert x1[0, 0] == 0.0 and 0.0 <= x1[0, 0] < 4.0
+
+
+def test_planted_mistake_fails_the_wrap_pin(monkeypatch):
+    """Without the rule that a result equal to L becomes 0, the wrap pin fails."""
+    pic = oracle.pic
+    with monkeypatch.context() as m:
+        def no_tie(x, length):
+            y = x - length * np.floor(np.real(x) / length)
+            return np.where(np.real(y) < 0, y + length, y)
+        m.setattr(pic, "wrap", no_tie)
+        m.setattr(oracle, "wrap", pic.wrap)
+        with pytest.raises(AssertionError):
+            test_periodic_wrap_ties()
+
+
 # ---------------------------------------------------------------- moments (Sec. 2 packet totals)
 
 @pytest.mark.parametrize("shape", ["cic", "tsc"])
