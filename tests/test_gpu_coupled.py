@@ -19,7 +19,7 @@ import pytest
 
 import oracle
 from workloads import make_workload, gas_state
-from tests.helpers import oracle_params, periodic_distance, rel_l2, max_rel_momentum
+from tests.helpers import oracle_params, periodic_distance, rel_l2, rel_linf, max_rel_momentum
 
 pytestmark = pytest.mark.gpu
 
@@ -66,15 +66,14 @@ def _compare(w, gas, got, ref, tol, label):
     p = ref["p"]
     _, mom0, egas0 = gas
     dist = float(np.max(periodic_distance(got["x"], ref["x"], w.box))) if w.n_particles else 0.0
-    errs = dict(x=dist / max(w.box),
+    errs = dict(x_cells=dist / w.dx,
                 u=max_rel_momentum(got["u"], ref["u"]) if w.n_particles else 0.0,
-                mom=rel_l2(got["mom"] - mom0, ref["mom"] - mom0),
+                mom=rel_l2(got["mom"] - mom0, ref["mom"] - mom0), mom_inf=rel_linf(got["mom"] - mom0, ref["mom"] - mom0),
                 egas_abs=float(np.linalg.norm(got["egas"] - ref["egas"]) / _energy_scale(w, p)),
-                E=rel_l2(got["E"], ref["E"]))
-    _say(f"{label}: x_cells={dist / w.dx:.2e}, " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+                E=rel_l2(got["E"], ref["E"]), E_inf=rel_linf(got["E"], ref["E"]))
+    _say(f"{label}: " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()))
     for k, v in errs.items():
         assert v <= tol, (label, k, v)
-    assert dist / w.dx <= (1e-10 if tol <= 1e-10 else 1e-4), (label, "x_cells", dist / w.dx)
 
 
 @pytest.mark.parametrize("flags", [0, 2, 1], ids=["cells", "tiled", "global"])

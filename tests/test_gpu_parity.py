@@ -1,15 +1,27 @@
 """Parity of the HIP path (through the C ABI) with the CPU oracle on the same seeded
 inputs, element by element, plus edge cases.
 
-Tolerances (relative unless stated): FP64 path 1e-10, FP32 precision form 1e-5, on
-packet positions (periodic distance relative to the box length L), momenta
-(|du|/|u| per packet), the deposited exchange and the CR moments (relative L2 over
-the grid).  Positions are also bounded in cells: 1e-10 dx for FP64, and 1e-4 dx for
-FP32, where after 100 steps the FP32 rounding of the rotation leaves a momentum phase
-error of a few 1e-6 that the orbit turns into r_g times that in position.  The energy
-exchange of a step is a small difference of packet energies (dgamma << gamma), so it
-is compared in absolute terms against its natural scale (c/c_tilde) M c^2 gamma per
-cell, at the same 1e-10 / 1e-5 levels."""
+Error metrics: packet positions as the largest periodic distance in cells (dx),
+momenta as max_j |du_j|/|u_j|, and every grid quantity (exchange of the last step and
+summed over the steps, CR moments) both as a relative L2 over the grid and as the
+largest error of any cell relative to the largest value (L-infinity), so that one
+cell far off fails.  The energy exchange of a step is a small difference of packet
+energies (dgamma << gamma), so it is compared in absolute terms against its natural
+scale (c/c_tilde) M c^2 gamma per cell.
+
+Bars: the FP64 path 1e-10 on every quantity (positions 1e-10 dx).  The FP32 precision
+form 1e-5, except where storing the packet state in FP32 costs more than that by
+itself: the oracle is then re-run with its state rounded to the FP32 form after every
+step (FP64 arithmetic otherwise), and the GPU may exceed that run's error by at most
+half.  On workload 3 this is the case for positions: the float32 momentum's rounding
+walks |u|, and with it the gyro frequency, a little at random every step, and the
+orbit phase integrates that into ~1.6e-5 dx after 100 steps even with exact
+arithmetic.
+
+The oracle always takes its own Courant timestep from the initial FP64 state; the
+GPU's must equal it (1e-14 relative in FP64; in the FP32 form, whose timestep comes
+from its float32 momenta, 1e-6, and the oracle then runs with the GPU's value so that
+the comparison is of trajectories, not of timesteps)."""
 
 import sys
 
@@ -18,7 +30,8 @@ import pytest
 
 import oracle
 from workloads import make_workload
-from tests.helpers import oracle_params, oracle_fields, periodic_distance, rel_l2, max_rel_momentum
+from tests.helpers import (oracle_params, oracle_fields, periodic_distance, rel_l2, rel_linf, max_rel_momentum,
+                           fp32_storage_rollout)
 
 pytestmark = pytest.mark.gpu
 
@@ -57,12 +70,21 @@ def _gpu_rollout(w, nsteps, **kw):
     return out, sim
 
 
-def _oracle_rollout(w, nsteps, dt):
-    p = oracle_params(w, dt=dt)
+def _oracle_rollout(w, nsteps, gpu_dt, fp32=None):
+    """The oracle's rollout with its own Courant timestep, after checking the GPU's
+    timestep against it (FP32 form: to float32 rounding, and the rollout then takes the
+    GPU's value)."""
+    p = oracle_params(w)
+    fp32 = (w.precision == "fp32") if fp32 is None else fp32
+    rel = abs(gpu_dt - p.dt) / p.dt
+    _say(f"dt gpu {gpu_dt!r} oracle {p.dt!r} rel {rel:.1e}")
+    assert rel <= (1e-6 if fp32 else 1e-14), (gpu_dt, p.dt)
+    if fp32:
+        p.dt = gpu_dt
     E, B = oracle_fields(w)
     r = oracle.rollout(w.x, w.u, E, B, p, nsteps)
     rho, P, e = oracle.moments(r["x"], r["u"], p)
-    r.update(rho=rho, P=P, e=e, p=p)
+    r.update(rho=rho, P=P, e=e, p=p, nsteps=nsteps)
     return r
 
 
@@ -71,20 +93,40 @@ def _energy_scale(w, p):
     return (p.c / p.c_tilde) * p.mass * p.c ** 2 * g * w.ppc * np.sqrt(w.n_cells) / p.volume
 
 
-def _compare(w, got, ref, tol, label):
+def _errors(w, got, ref):
     p = ref["p"]
-    box = w.box
-    dist = float(np.max(periodic_distance(got["x"], ref["x"], box)))
-    eu = max_rel_momentum(got["u"], ref["u"])
-    errs = dict(x=dist / max(box), u=eu, dM=rel_l2(got["dM"], ref["dM"]), dM_sum=rel_l2(got["dM_sum"], ref["dM_sum"]),
-                rho=rel_l2(got["rho"], ref["rho"]), P=rel_l2(got["P"], ref["P"]), e=rel_l2(got["e"], ref["e"]))
+    errs = dict(x_cells=float(np.max(periodic_distance(got["x"], ref["x"], w.box))) / w.dx,
+                u=max_rel_momentum(got["u"], ref["u"]))
+    for k in ("dM", "dM_sum", "rho", "P", "e"):
+        if k in got:
+            errs[k] = rel_l2(got[k], ref[k])
+            errs[k + "_inf"] = rel_linf(got[k], ref[k])
     escale = _energy_scale(w, p)
-    errs["dE_abs"] = float(np.linalg.norm(got["dE"] - ref["dE"]) / escale)
-    errs["dE_sum_abs"] = float(np.linalg.norm(got["dE_sum"] - ref["dE_sum"]) / escale)
-    _say(f"{label}: x_cells={dist / w.dx:.2e}, " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    for k in ("dE", "dE_sum"):
+        if k in got:
+            errs[k + "_abs"] = float(np.linalg.norm(got[k] - ref[k]) / escale)
+            errs[k + "_abs_inf"] = float(np.max(np.abs(got[k] - ref[k])) * np.sqrt(w.n_cells) / escale)
+    return errs
+
+
+def _compare(w, got, ref, tol, label):
+    """Assert every error metric of got vs ref at the bar described in the module
+    docstring; returns the errors."""
+    errs = _errors(w, got, ref)
+    bars = {k: tol for k in errs}
+    if tol > 1e-10:
+        # FP32 form: the error of the state's storage alone, from the oracle with rounding
+        p = ref["p"]
+        E, B = oracle_fields(w)
+        fl = fp32_storage_rollout(w.x, w.u, E, B, p, ref["nsteps"])
+        if "rho" in got:
+            fl["rho"], fl["P"], fl["e"] = oracle.moments(fl["x"], fl["u"], p)
+        floor = _errors(w, {k: fl[k] for k in got if k in fl}, ref)
+        _say(f"{label} fp32-storage floor: " + ", ".join(f"{k}={v:.2e}" for k, v in floor.items()))
+        bars = {k: max(tol, 1.5 * floor.get(k, 0.0)) for k in errs}
+    _say(f"{label}: " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()))
     for k, v in errs.items():
-        assert v <= tol, (label, k, v)
-    assert dist / w.dx <= (1e-10 if tol <= 1e-10 else 1e-4), (label, "x_cells", dist / w.dx)
+        assert v <= bars[k], (label, k, v, bars[k])
     return errs
 
 
@@ -98,7 +140,6 @@ def test_config1_fp64_100_steps(flags):
     _say(f"config1 fp64 flags={flags}")
     got, _ = _gpu_rollout(w, w.nsteps, flags=flags)
     ref = _oracle_rollout(w, w.nsteps, got["dt"])
-    assert got["dt"] == pytest.approx(ref["p"].dt, rel=1e-15)
     _compare(w, got, ref, 1e-10, f"config1 fp64 flags={flags}")
 
 
@@ -154,7 +195,7 @@ def test_cells_overflow_stores(precision, tol):
     sim.step(12, dM, dE)
     sim.handle.rsol_check()
     x, u = sim.state_by_id()
-    assert np.max(periodic_distance(x, got["x"], w.box)) / w.dx <= (1e-12 if precision == "fp64" else 1e-4)
+    assert np.max(periodic_distance(x, got["x"], w.box)) / w.dx <= (1e-12 if precision == "fp64" else 1e-5)
     assert max_rel_momentum(u, got["u"]) <= (1e-13 if precision == "fp64" else 1e-5)
     # deposit sums run in a different order (bucket slots come from atomics)
     assert rel_l2(dM.cpu().numpy(), got["dM_sum"]) <= (1e-12 if precision == "fp64" else 1e-6)
@@ -318,11 +359,17 @@ def test_full_size_sampled_trajectories(k, precision, nsteps, tol):
     p = oracle_params(w, dt=sim.dt)
     E, B = oracle_fields(w)
     r = oracle.rollout(w.x[:, pick], w.u[:, pick], E, B, p, nsteps)
-    dist = float(np.max(periodic_distance(xg, r["x"], w.box)))
+    ex = float(np.max(periodic_distance(xg, r["x"], w.box))) / w.dx
     eu = max_rel_momentum(ug, r["u"])
-    _say(f"workload {k} {precision}: x_cells={dist:.2e} x={dist / max(w.box):.2e} e_u={eu:.2e}")
-    assert dist / max(w.box) <= tol and eu <= tol
-    assert dist / w.dx <= (1e-10 if tol <= 1e-10 else 1e-4)
+    bx, bu = tol, tol
+    if precision == "fp32":
+        fl = fp32_storage_rollout(w.x[:, pick], w.u[:, pick], E, B, p, nsteps)
+        fx = float(np.max(periodic_distance(fl["x"], r["x"], w.box))) / w.dx
+        fu = max_rel_momentum(fl["u"], r["u"])
+        _say(f"workload {k} fp32-storage floor: x_cells={fx:.2e} e_u={fu:.2e}")
+        bx, bu = max(tol, 1.5 * fx), max(tol, 1.5 * fu)
+    _say(f"workload {k} {precision}: x_cells={ex:.2e} e_u={eu:.2e}")
+    assert ex <= bx and eu <= bu, (ex, bx, eu, bu)
 
 
 @pytest.mark.parametrize("precision,tol,per_call", [("fp64", 1e-10, 100), ("fp64", 1e-10, 3), ("fp32", 1e-5, 100)])
@@ -349,13 +396,8 @@ def test_keep_order_without_exchange(precision, tol, per_call):
     assert torch.equal(sim.ids, ids0)
     x, u = sim.state_by_id()
     ref = _oracle_rollout(w, 100, sim.dt)
-    dist = float(np.max(periodic_distance(x, ref["x"], w.box)))
-    eu = max_rel_momentum(u, ref["u"])
-    _say(f"keep order without exchange {precision}: x_cells={dist / w.dx:.2e} u={eu:.2e}")
-    assert dist / w.dx <= (1e-10 if tol <= 1e-10 else 1e-4)
-    assert eu <= tol
-    for got, want in ((rho, ref["rho"]), (P, ref["P"]), (e, ref["e"])):
-        assert rel_l2(got.cpu().numpy(), want) <= tol
+    _compare(w, dict(x=x, u=u, rho=rho.cpu().numpy(), P=P.cpu().numpy(), e=e.cpu().numpy()), ref, tol,
+             f"keep order without exchange {precision} per_call={per_call}")
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -388,7 +430,7 @@ def test_resident_cell_lists(precision):
         out.append((x, u, dM.cpu().numpy(), sim.dt, rho.cpu().numpy(), P.cpu().numpy()))
     (x0, u0, d0, dt, r0, P0), (x1, u1, d1, _, r1, P1) = out
     fp64 = precision == "fp64"
-    assert np.max(periodic_distance(x1, x0, w.box)) / w.dx <= (1e-12 if fp64 else 1e-4)
+    assert np.max(periodic_distance(x1, x0, w.box)) / w.dx <= (1e-12 if fp64 else 1e-5)
     assert max_rel_momentum(u1, u0) <= (1e-13 if fp64 else 1e-5)
     assert rel_l2(r1, r0) <= (1e-13 if fp64 else 1e-6) and rel_l2(P1, P0) <= (1e-13 if fp64 else 1e-5)
     # FP32: a packet's slot also decides the order of the FP32 partial sums a quad keeps
@@ -401,8 +443,10 @@ def test_resident_cell_lists(precision):
     xd = oracle.drift(r["x"], r["u"], p)
     r2 = oracle.rollout(xd, r["u"], E, B, p, 4)
     tol = 1e-10 if precision == "fp64" else 1e-5
-    assert np.max(periodic_distance(x1, r2["x"], w.box)) / w.dx <= (1e-10 if precision == "fp64" else 1e-4)
-    assert max_rel_momentum(u1, r2["u"]) <= tol
+    ex = float(np.max(periodic_distance(x1, r2["x"], w.box))) / w.dx
+    eu = max_rel_momentum(u1, r2["u"])
+    _say(f"resident {precision}: x_cells={ex:.2e} e_u={eu:.2e}")
+    assert ex <= tol and eu <= tol
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
