@@ -134,7 +134,7 @@ def _alfvenic_turbulence(rng, nx, ny, nz, b0, n_max, rms):
     ex[par], ey[par], ez[par] = 0.0, 0.0, 1.0
     phase = rng.uniform(0.0, 2.0 * np.pi, kmag.shape)
     spec = amp * np.exp(1j * phase)
-    dB = np.stack([np.fft.irfftn(spec * e, s=(nz, ny, nx)) for e in (ex, ey, ez)])
+    dB = np.stack([np.fft.irfftn(spec * e, s=(nz, ny, nx), axes=(0, 1, 2)) for e in (ex, ey, ez)])
     scale = rms / np.sqrt(np.mean(np.sum(dB * dB, axis=0)))
     return dB * scale
 
