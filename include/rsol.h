@@ -136,6 +136,25 @@ size_t rsol_scratch_bytes(const rsol_params* p, int64_t n_particles);
 int rsol_init(const rsol_params* p, int64_t n_particles, void* stream, void* scratch,
               size_t scratch_bytes, rsol_handle* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): one call that does what rsol_init,
+ * rsol_set_fields, rsol_set_particles, rsol_set_dt and rsol_step do together, with the
+ * scratch taken from a static device array inside the library (64 MiB per GPU, held by
+ * each GPU the library runs on until the process ends) instead of a caller buffer.
+ * Nothing here allocates device memory.  Arguments as for those entry points: p with
+ * p->dt > 0 (no Courant timestep is computed here) and neither RSOL_FLAG_RESIDENT nor
+ * RSOL_FLAG_LOSSES; E, B [3][n_cells] doubles; pos/off/u/id the packet arrays of the
+ * precision (updated in place, permuted as rsol_step permutes them); dM, dE added to as
+ * rsol_step adds (both may be NULL; dE needs dM).  The stream must belong to the current
+ * device.  Errors: RSOL_ESCRATCH when rsol_scratch_bytes(p, n_particles) exceeds the
+ * static array, the other codes as rsol_init and rsol_step; the message is
+ * rsol_last_error(NULL).  Device-detected faults (RSOL_ECOURANT, RSOL_ENAN) are not
+ * reported (there is no handle to check).  All calls on one GPU share its array, which
+ * keeps the last call's contents: calls that overlap on one GPU (several host threads,
+ * or work still running on another stream) race and corrupt each other. */
+int rsol_step_static(const rsol_params* p, int64_t n_particles, void* stream, const double* E, const double* B,
+                     void* pos, float* off, void* u, int32_t* id, int32_t nsteps, double* dM, double* dE);
+
 /* Free the host-side handle (device memory stays with the caller). */
 int rsol_destroy(rsol_handle h);
 

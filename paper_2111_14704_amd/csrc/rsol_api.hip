@@ -3,6 +3,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -652,6 +653,53 @@ int moments(rsol_ctx* h, double* rho, double* P, double* e) {
   return RSOL_OK;
 }
 
+// Fill a new context for np packets over the scratch at `scratch` (bytes long, already
+// checked against the layout): carve the regions, the cell lists, clear the status words.
+int init_ctx(rsol_ctx* h, const rsol_params* p, int64_t n_particles, void* stream, void* scratch,
+             size_t scratch_bytes) {
+  h->p = *p;
+  h->np = n_particles;
+  h->stream = (hipStream_t)stream;
+  h->scratch = (char*)scratch;
+  h->scratch_bytes = scratch_bytes;
+  h->plan = plan_step(p->nx, p->ny, p->nz, p->shape, p->precision, p->sort_every, p->courant);
+  h->tiling = make_tiling(p->nx, p->ny, p->nz, h->plan.tx, h->plan.ty, h->plan.tz);
+  layout(*p, n_particles, h);
+  h->cells = cell_list_carve(p->nx, p->ny, p->nz, n_particles, p->precision, loss_layout(*p), h->cells_base);
+  hipError_t e = launch_fill_u32(h->status, 0u, 4, h->stream);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "init status");
+  return RSOL_OK;
+}
+
+// ---------------------------------------------------------------- static scratch
+// The scratch of rsol_step_static: a device array of fixed size in the library's code
+// object, so that the entry point needs no device allocation.  Host code must not pass
+// the array's name to a kernel (on the host it is a stand-in, not a device address):
+// static_scratch() looks up its address once per device and every use goes through it.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+char* g_static_ptr[kMaxDevices] = {};
+
+int static_scratch(char** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(nullptr, RSOL_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetSymbolAddress(scratch)");
+    if (!ptr || ((uintptr_t)ptr) % kAlign) return fail(nullptr, RSOL_EHIP, "static scratch address unusable");
+    g_static_ptr[dev] = (char*)ptr;
+  }
+  *out = g_static_ptr[dev];
+  return RSOL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -675,23 +723,36 @@ int rsol_init(const rsol_params* p, int64_t n_particles, void* stream, void* scr
                 "scratch too small: need " + std::to_string(need_bytes) + " bytes, got " + std::to_string(scratch_bytes));
   rsol_ctx* h = new (std::nothrow) rsol_ctx();
   if (!h) return fail(nullptr, RSOL_EINVAL, "out of host memory");
-  h->p = *p;
-  h->np = n_particles;
-  h->stream = (hipStream_t)stream;
-  h->scratch = (char*)scratch;
-  h->scratch_bytes = scratch_bytes;
-  h->plan = plan_step(p->nx, p->ny, p->nz, p->shape, p->precision, p->sort_every, p->courant);
-  h->tiling = make_tiling(p->nx, p->ny, p->nz, h->plan.tx, h->plan.ty, h->plan.tz);
-  layout(*p, n_particles, h);
-  h->cells = cell_list_carve(p->nx, p->ny, p->nz, n_particles, p->precision, loss_layout(*p), h->cells_base);
-  hipError_t e = launch_fill_u32(h->status, 0u, 4, h->stream);
-  if (e != hipSuccess) {
-    int rc = hip_fail(nullptr, e, "init status");
+  if (int rc = init_ctx(h, p, n_particles, stream, scratch, scratch_bytes)) {
     delete h;
     return rc;
   }
   *out = h;
   return RSOL_OK;
+}
+
+int rsol_step_static(const rsol_params* p, int64_t n_particles, void* stream, const double* E, const double* B,
+                     void* pos, float* off, void* u, int32_t* id, int32_t nsteps, double* dM, double* dE) {
+  const std::string bad = validate(p, n_particles);
+  if (!bad.empty()) return fail(nullptr, RSOL_EINVAL, bad);
+  if (!(p->dt > 0)) return fail(nullptr, RSOL_EINVAL, "dt must be > 0 (no Courant timestep is computed here)");
+  if (p->flags & (RSOL_FLAG_RESIDENT | RSOL_FLAG_LOSSES))
+    return fail(nullptr, RSOL_EINVAL, "RSOL_FLAG_RESIDENT and RSOL_FLAG_LOSSES need a handle");
+  if (nsteps < 0) return fail(nullptr, RSOL_EINVAL, "nsteps < 0");
+  const size_t need_bytes = layout(*p, n_particles, nullptr);
+  if (need_bytes > kStaticScratchBytes)
+    return fail(nullptr, RSOL_ESCRATCH,
+                "the static scratch holds " + std::to_string(kStaticScratchBytes) + " bytes; this problem needs " +
+                    std::to_string(need_bytes));
+  char* base = nullptr;
+  if (int rc = static_scratch(&base)) return rc;
+  rsol_ctx h{};
+  if (int rc = init_ctx(&h, p, n_particles, stream, base, kStaticScratchBytes)) return rc;
+  int rc = rsol_set_fields(&h, E, B);
+  if (!rc) rc = rsol_set_particles(&h, pos, off, u, id);
+  if (!rc) rc = rsol_step(&h, nsteps, dM, dE);
+  if (rc) g_init_error = h.err;
+  return rc;
 }
 
 int rsol_destroy(rsol_handle h) {

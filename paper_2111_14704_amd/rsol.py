@@ -94,6 +94,7 @@ def lib():
             "rsol_moments_backward": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
             "rsol_timing_read": (ctypes.c_int, [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64),
                                                  ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
+            "rsol_step_static": (ctypes.c_int, [P, i64, vp, vp, vp, vp, vp, vp, vp, i32, vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -111,6 +112,7 @@ def exported_symbols():
         "rsol_sort", "rsol_step", "rsol_moments", "rsol_check", "rsol_timing", "rsol_timing_read",
         "rsol_stray_count", "rsol_set_flags", "rsol_state_bytes", "rsol_record_states", "rsol_step_backward",
         "rsol_moments_backward", "rsol_step_coupled", "rsol_set_losses", "rsol_sync_particles",
+        "rsol_step_static",
     ]
 
 
@@ -160,6 +162,20 @@ def rsol_scratch_bytes(params: Params, n_particles: int) -> int:
     if n == 0:
         raise RSOLError(-1, "invalid parameters")
     return n
+
+
+def rsol_step_static(params: Params, pos, off, u, ids, E, B, nsteps: int, dM=None, dE=None, stream=None):
+    """rsol_step_static: nsteps steps of the packets (pos, off, u, ids: device tensors of
+    the precision's layout, updated in place) in the fields E, B with params.dt, using the
+    library's static device scratch (no device allocation, no handle)."""
+    n = int(u.shape[1])
+    p = params.to_c()
+    st = stream if stream is not None else torch.cuda.current_stream(u.device)
+    rc = lib().rsol_step_static(ctypes.byref(p), n, ctypes.c_void_p(st.cuda_stream), _ptr(E), _ptr(B), _ptr(pos),
+                                _ptr(off), _ptr(u), _ptr(ids), int(nsteps), _ptr(dM), _ptr(dE))
+    if rc != RSOL_OK:
+        msg = lib().rsol_last_error(None)
+        raise RSOLError(rc, msg.decode() if msg else "")
 
 
 class Handle:
