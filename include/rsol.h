@@ -72,7 +72,7 @@ typedef struct rsol_params {
   double qomc;          /* q / (m_s c) of the CR species                                      */
   double dt;            /* timestep; may be 0 until rsol_set_dt                                */
   double courant;       /* Courant factor C of Sec. 4 (0 < C <= 0.5)                          */
-  double mass;          /* packet mass weight M_j = N_j <m_s>, equal for every packet         */
+  double mass;          /* packet mass weight M_j = N_j <m_s> (times w_j with rsol_set_weights) */
 } rsol_params;
 
 /* flags */
@@ -101,8 +101,10 @@ typedef struct rsol_params {
                                    Drift, E and every kernel are the RSOL ones; the
                                    differentiation-form entry points return RSOL_EINVAL.      */
 #define RSOL_FLAG_LOSSES 8      /* set at rsol_init: the scratch layout carries a weight per
-                                   packet so that rsol_set_losses can switch on catastrophic
-                                   losses; fixed for the life of the handle                   */
+                                   packet so that rsol_set_weights can register per-packet
+                                   weights and rsol_set_losses switch on catastrophic losses;
+                                   fixed for the life of the handle                           */
+#define RSOL_FLAG_WEIGHTS 8     /* the same bit, named for per-packet weights alone           */
 #define RSOL_FLAG_PUSHER_VAY 16 /* momentum update by the pusher of Vay (Phys. Plasmas 15,
                                    056701, 2008) instead of Boris, for the same Eq. (11) and
                                    the same half kicks; keeps the force-free E x B drift
@@ -188,6 +190,17 @@ int rsol_set_fields(rsol_handle h, const double* E, const double* B);
  * differentiation form return RSOL_EINVAL.  rsol_courant_dt adds the limit
  * dt < C / ((c_tilde/c) sigma c beta_max n_n,max). */
 int rsol_set_losses(rsol_handle h, double sigma, const double* nn, void* w);
+
+/* Per-packet weights (Sec. 2, Eq. (4): a packet stands for N_j particles; Sec. 4 sets
+ * N_j from the total mass or energy): the packet mass becomes M_j = mass * w_j for the
+ * exchange of Eq. (12) and for the moments.  w: [np] weights in the precision type,
+ * device pointer, kept until rsol_destroy and permuted with the packets by rsol_step
+ * (rsol_set_losses registers the same array, and makes the weights decay).  Needs a
+ * handle created with RSOL_FLAG_WEIGHTS (else RSOL_ESTATE).  Honoured by the default
+ * cell-list path, RSOL_FLAG_KEEP_ORDER and rsol_moments; with weights registered the
+ * tiled path, rsol_sort, the separate phases and the differentiation form return
+ * RSOL_EINVAL. */
+int rsol_set_weights(rsol_handle h, void* w);
 
 /* Register the packet state (Sec. 2, Eq. (4): packets {x, p} with weights N_j).
  * FP64 form: pos = double x[3][np], off = NULL, u = double[3][np].

@@ -45,6 +45,7 @@ struct rsol_ctx {
   void* w;
   double sigma;
   bool have_fields, have_packets, sorted_valid, have_losses;
+  bool have_weights;    // per-packet weights registered (rsol_set_weights, or with the losses)
   bool cells_valid;     // the cell lists hold the packets (as of the last rsol_step return)
   bool arrays_stale;    // resident lists hold newer packets than the registered arrays
   int steps_since_sort;
@@ -212,6 +213,7 @@ std::string validate(const rsol_params* p, int64_t np) {
   if (t.cells_per_tile > max_cells_per_tile()) return "tile larger than the sort supports";
   const int64_t ntiles4 = (int64_t)((p->nx + 3) / 4) * ((p->ny + 3) / 4) * ((p->nz + 3) / 4);
   if (n_cells(*p) + ntiles4 + 1 > max_sort_bins()) return "grid too large for the cell lists";
+  if (!cell_list_fits(p->nx, p->ny, p->nz, np, p->precision)) return "too many packets for the cell lists";
   return "";
 }
 
@@ -274,7 +276,7 @@ Packets<T> caller_packets(const rsol_ctx* h) {
   }
   P.u = (T*)h->u;
   P.id = h->id;
-  P.w = h->have_losses ? (T*)h->w : nullptr;
+  P.w = h->have_weights ? (T*)h->w : nullptr;
   return P;
 }
 
@@ -320,8 +322,8 @@ int need(rsol_ctx* h, bool fields, bool packets) {
 
 // The tiled path carries no packet weights.
 int losses_path_ok(rsol_ctx* h) {
-  if (h->have_losses && (h->p.flags & RSOL_FLAG_TILED) && !(h->p.flags & RSOL_FLAG_KEEP_ORDER))
-    return fail(h, RSOL_EINVAL, "the tiled path does not carry losses");
+  if (h->have_weights && (h->p.flags & RSOL_FLAG_TILED) && !(h->p.flags & RSOL_FLAG_KEEP_ORDER))
+    return fail(h, RSOL_EINVAL, "the tiled path does not carry packet weights or losses");
   return RSOL_OK;
 }
 
@@ -392,8 +394,13 @@ int do_step_cells(rsol_ctx* h, int32_t nsteps, double* dM, double* dE, const Gas
       pr.first = take_event(h);
       pr.second = take_event(h);
     }
-    RSOL_HIP(h, launch_cells_step<T>(h->p.shape, h->cells, field_E<T>(h), field_B<T>(h), field_NN<T>(h), dM, dE,
-                                     gas, k, h->stream, pr.first, pr.second),
+    // the per-tile exchange accumulators sum the call's steps and go into dM/dE after
+    // the last one; a step coupled to the gas needs its exchange in the gas at once
+    const bool accumulate = s > 0 && !gas.rho;
+    const bool post = gas.rho || s == nsteps - 1;
+    RSOL_HIP(h, launch_cells_step<T>(h->p.shape, h->cells, field_E<T>(h), field_B<T>(h), field_NN<T>(h),
+                                     h->have_weights && !h->have_losses, dM, dE, gas, k, h->stream, pr.first,
+                                     pr.second, accumulate, post),
              "step (cells)");
     if (pr.first && pr.second) h->ev_step.push_back(pr);
   }
@@ -448,8 +455,11 @@ int do_step(rsol_ctx* h, int32_t nsteps, double* dM, double* dE, const GasLink& 
   for (int32_t s = 0; s < nsteps; ++s) {
     if (global) {
       auto ev = timed_begin(h);
-      RSOL_HIP(h, launch_step_global<T>(h->p.shape, caller_packets<T>(h), field_E<T>(h), field_B<T>(h),
-                                        field_NN<T>(h), dM, dE, k, h->stream),
+      // packet weights without losses: the weighted step with a zero loss rate (its
+      // density input is then never used; any grid array of the right size serves)
+      const T* nn = h->have_losses ? field_NN<T>(h) : (h->have_weights ? field_B<T>(h) : nullptr);
+      RSOL_HIP(h, launch_step_global<T>(h->p.shape, caller_packets<T>(h), field_E<T>(h), field_B<T>(h), nn, dM, dE,
+                                        k, h->stream),
                "step (global)");
       timed_end(h, ev, false);
       h->sorted_valid = false;
@@ -832,6 +842,20 @@ int rsol_set_losses(rsol_handle h, double sigma, const double* nn, void* w) {
   h->w = w;
   if (fp32(h->p)) RSOL_HIP(h, launch_to_fp32(nn, h->nn32, n_cells(h->p), h->stream), "nn to fp32");
   h->have_losses = true;
+  h->have_weights = true;
+  return RSOL_OK;
+}
+
+int rsol_set_weights(rsol_handle h, void* w) {
+  if (int rc = need(h, false, false)) return rc;
+  if (int rc = sync_arrays(h)) return rc;
+  h->cells_valid = false;  // the packets change (or the cell-list scratch is reused)
+  if (!loss_layout(h->p)) return fail(h, RSOL_ESTATE, "handle created without RSOL_FLAG_WEIGHTS");
+  if (!w && h->np > 0) return fail(h, RSOL_EINVAL, "NULL weight array");
+  if (h->p.flags & RSOL_FLAG_TILED && !(h->p.flags & RSOL_FLAG_KEEP_ORDER))
+    return fail(h, RSOL_EINVAL, "the tiled path does not carry packet weights");
+  h->w = w;
+  h->have_weights = true;
   return RSOL_OK;
 }
 
@@ -915,7 +939,8 @@ int rsol_set_dt(rsol_handle h, double dt) {
 int rsol_gather(rsol_handle h, void* Ep, void* Bp) {
   if (int rc = need(h, true, true)) return rc;
   if (int rc = sync_arrays(h)) return rc;  // reads the registered packets
-  if (h->have_losses) return fail(h, RSOL_EINVAL, "losses registered: the separate phases carry no losses (use rsol_step)");
+  if (h->have_weights)
+    return fail(h, RSOL_EINVAL, "weights or losses registered: the separate phases carry neither (use rsol_step)");
   if (h->np == 0) return RSOL_OK;
   if (!Ep || !Bp) return fail(h, RSOL_EINVAL, "NULL output");
   if (fp32(h->p))
@@ -931,7 +956,8 @@ int rsol_push(rsol_handle h, const void* Ep, const void* Bp, void* payload) {
   if (int rc = need(h, false, true)) return rc;
   if (int rc = sync_arrays(h)) return rc;
   h->cells_valid = false;  // the packets change (or the cell-list scratch is reused)
-  if (h->have_losses) return fail(h, RSOL_EINVAL, "losses registered: the separate phases carry no losses (use rsol_step)");
+  if (h->have_weights)
+    return fail(h, RSOL_EINVAL, "weights or losses registered: the separate phases carry neither (use rsol_step)");
   if (h->np == 0) return RSOL_OK;
   if (!Ep || !Bp || !payload) return fail(h, RSOL_EINVAL, "NULL pointer");
   if (!(h->p.dt > 0)) return fail(h, RSOL_ESTATE, "dt not set");
@@ -947,7 +973,8 @@ int rsol_push(rsol_handle h, const void* Ep, const void* Bp, void* payload) {
 int rsol_deposit(rsol_handle h, const void* payload, double* dM, double* dE) {
   if (int rc = need(h, false, true)) return rc;
   if (int rc = sync_arrays(h)) return rc;  // reads the registered packets
-  if (h->have_losses) return fail(h, RSOL_EINVAL, "losses registered: the separate phases carry no losses (use rsol_step)");
+  if (h->have_weights)
+    return fail(h, RSOL_EINVAL, "weights or losses registered: the separate phases carry neither (use rsol_step)");
   if (h->np == 0) return RSOL_OK;
   if (!payload || !dM) return fail(h, RSOL_EINVAL, "NULL pointer");
   if (fp32(h->p))
@@ -963,7 +990,8 @@ int rsol_drift(rsol_handle h) {
   if (int rc = need(h, false, true)) return rc;
   if (int rc = sync_arrays(h)) return rc;
   h->cells_valid = false;  // the packets change (or the cell-list scratch is reused)
-  if (h->have_losses) return fail(h, RSOL_EINVAL, "losses registered: the separate phases carry no losses (use rsol_step)");
+  if (h->have_weights)
+    return fail(h, RSOL_EINVAL, "weights or losses registered: the separate phases carry neither (use rsol_step)");
   if (h->np == 0) return RSOL_OK;
   if (!(h->p.dt > 0)) return fail(h, RSOL_ESTATE, "dt not set");
   if (fp32(h->p))
@@ -978,7 +1006,7 @@ int rsol_sort(rsol_handle h) {
   if (int rc = need(h, false, true)) return rc;
   if (int rc = sync_arrays(h)) return rc;
   h->cells_valid = false;  // the packets change (or the cell-list scratch is reused)
-  if (h->have_losses) return fail(h, RSOL_EINVAL, "losses registered: packets are re-binned by rsol_step only");
+  if (h->have_weights) return fail(h, RSOL_EINVAL, "weights or losses registered: packets are re-binned by rsol_step only");
   return fp32(h->p) ? do_sort<float>(h, true) : do_sort<double>(h, true);
 }
 
@@ -1040,7 +1068,7 @@ int rsol_set_flags(rsol_handle h, int32_t flags) {
   if (flags & ~kKnownFlags) return fail(h, RSOL_EINVAL, "unknown flag bits");
   if (!flag_conflict(flags).empty()) return fail(h, RSOL_EINVAL, flag_conflict(flags));
   if ((flags ^ h->p.flags) & RSOL_FLAG_LOSSES) return fail(h, RSOL_EINVAL, "RSOL_FLAG_LOSSES is fixed at rsol_init");
-  if (h->have_losses && (flags & RSOL_FLAG_TILED) && !(flags & RSOL_FLAG_KEEP_ORDER))
+  if (h->have_weights && (flags & RSOL_FLAG_TILED) && !(flags & RSOL_FLAG_KEEP_ORDER))
     return fail(h, RSOL_EINVAL, "the tiled path does not carry losses");
   h->p.flags = flags;
   return RSOL_OK;
@@ -1057,7 +1085,7 @@ int rsol_record_states(rsol_handle h, int32_t nsteps, void* states) {
   h->cells_valid = false;  // the packets change (or the cell-list scratch is reused)
   if (naive(h->p)) return fail(h, RSOL_EINVAL, "the differentiation form covers the RSOL equations only");
   if (pusher_of(h->p.flags) != kPushBoris) return fail(h, RSOL_EINVAL, "the differentiation form is the Boris pusher's");
-  if (h->have_losses) return fail(h, RSOL_EINVAL, "the differentiation form carries no losses");
+  if (h->have_weights) return fail(h, RSOL_EINVAL, "the differentiation form carries no packet weights or losses");
   if (nsteps < 0) return fail(h, RSOL_EINVAL, "nsteps < 0");
   if (!(h->p.dt > 0)) return fail(h, RSOL_ESTATE, "dt not set");
   if (h->np == 0 || nsteps == 0) return RSOL_OK;
@@ -1077,7 +1105,7 @@ int rsol_step_backward(rsol_handle h, int32_t nsteps, const void* states, void* 
   h->cells_valid = false;  // the packets change (or the cell-list scratch is reused)
   if (naive(h->p)) return fail(h, RSOL_EINVAL, "the differentiation form covers the RSOL equations only");
   if (pusher_of(h->p.flags) != kPushBoris) return fail(h, RSOL_EINVAL, "the differentiation form is the Boris pusher's");
-  if (h->have_losses) return fail(h, RSOL_EINVAL, "the differentiation form carries no losses");
+  if (h->have_weights) return fail(h, RSOL_EINVAL, "the differentiation form carries no packet weights or losses");
   if (nsteps < 0) return fail(h, RSOL_EINVAL, "nsteps < 0");
   if (!(h->p.dt > 0)) return fail(h, RSOL_ESTATE, "dt not set");
   if (!lam_dM && lam_dE) return fail(h, RSOL_EINVAL, "lam_dE without lam_dM");
@@ -1102,7 +1130,7 @@ int rsol_moments_backward(rsol_handle h, const double* lam_rho, const double* la
   if (int rc = sync_arrays(h)) return rc;  // reads the registered packets
   if (naive(h->p)) return fail(h, RSOL_EINVAL, "the differentiation form covers the RSOL equations only");
   if (pusher_of(h->p.flags) != kPushBoris) return fail(h, RSOL_EINVAL, "the differentiation form is the Boris pusher's");
-  if (h->have_losses) return fail(h, RSOL_EINVAL, "the differentiation form carries no losses");
+  if (h->have_weights) return fail(h, RSOL_EINVAL, "the differentiation form carries no packet weights or losses");
   if (h->np == 0) return RSOL_OK;
   if (!lam_x || !lam_u) return fail(h, RSOL_EINVAL, "NULL adjoint array");
   if (fp32(h->p))

@@ -28,6 +28,7 @@ RSOL_FLAG_KEEP_ORDER = 1
 RSOL_FLAG_TILED = 2
 RSOL_FLAG_NAIVE = 4
 RSOL_FLAG_LOSSES = 8
+RSOL_FLAG_WEIGHTS = 8
 RSOL_FLAG_PUSHER_VAY = 16
 RSOL_FLAG_PUSHER_HC = 32
 RSOL_FLAG_RESIDENT = 64
@@ -82,6 +83,7 @@ def lib():
             "rsol_step": (ctypes.c_int, [vp, i32, vp, vp]),
             "rsol_step_coupled": (ctypes.c_int, [vp, i32, vp, vp, vp, vp]),
             "rsol_set_losses": (ctypes.c_int, [vp, dbl, vp, vp]),
+            "rsol_set_weights": (ctypes.c_int, [vp, vp]),
             "rsol_moments": (ctypes.c_int, [vp, vp, vp, vp]),
             "rsol_sync_particles": (ctypes.c_int, [vp]),
             "rsol_check": (ctypes.c_int, [vp]),
@@ -112,7 +114,7 @@ def exported_symbols():
         "rsol_sort", "rsol_step", "rsol_moments", "rsol_check", "rsol_timing", "rsol_timing_read",
         "rsol_stray_count", "rsol_set_flags", "rsol_state_bytes", "rsol_record_states", "rsol_step_backward",
         "rsol_moments_backward", "rsol_step_coupled", "rsol_set_losses", "rsol_sync_particles",
-        "rsol_step_static",
+        "rsol_step_static", "rsol_set_weights",
     ]
 
 
@@ -220,6 +222,10 @@ class Handle:
     def rsol_set_losses(self, sigma: float, nn, w):
         self._keep.update(nn=nn, w=w)
         _check(self.h, lib().rsol_set_losses(self.h, float(sigma), _ptr(nn), _ptr(w)))
+
+    def rsol_set_weights(self, w):
+        self._keep["w"] = w
+        _check(self.h, lib().rsol_set_weights(self.h, _ptr(w)))
 
     def rsol_set_particles(self, pos, off, u, ids):
         self._keep.update(pos=pos, off=off, u=u, ids=ids)

@@ -78,6 +78,14 @@ class Simulation:
                                  device=self.device)
         self.handle.rsol_set_losses(sigma, self.nn, self.w)
 
+    def set_weights(self, w):
+        """Per-packet weights w_j (Np,) multiplying the packet mass (needs flags with
+        RSOL_FLAG_WEIGHTS at construction); they live in ``self.w`` (packet precision) and
+        follow the packets."""
+        self.w = torch.as_tensor(np.ascontiguousarray(w), dtype=torch.float32 if self.fp32 else torch.float64,
+                                 device=self.device)
+        self.handle.rsol_set_weights(self.w)
+
     def sync(self):
         """Bring the registered packet tensors up to date (with RSOL_FLAG_RESIDENT the
         packets stay in the library's cell lists between steps)."""

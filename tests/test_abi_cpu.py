@@ -97,4 +97,17 @@ def test_null_handle_calls_fail_cleanly():
     assert L.rsol_check(None) == -1
     assert L.rsol_sync_particles(None) == -1
     assert L.rsol_moments(None, None, None, None) == -1
+    assert L.rsol_set_weights(None, None) == -1
     assert L.rsol_destroy(None) == 0
+
+
+def test_too_many_packets_for_the_cell_lists_are_refused():
+    """The default path addresses its 16-byte slot records with 32-bit byte offsets: a
+    problem whose slot stores would pass 4 GiB is refused before any device work."""
+    rsol, L = _lib()
+    p = _params(rsol, nx=128, ny=128, nz=128).to_c()
+    assert L.rsol_scratch_bytes(ctypes.byref(p), 32 * 128 ** 3) > 0
+    assert L.rsol_scratch_bytes(ctypes.byref(p), 64 * 128 ** 3) == 0
+    h = ctypes.c_void_p()
+    assert L.rsol_init(ctypes.byref(p), 64 * 128 ** 3, None, ctypes.c_void_p(4096), 1 << 40, ctypes.byref(h)) == -1
+    assert b"too many packets" in L.rsol_last_error(None)

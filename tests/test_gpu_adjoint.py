@@ -5,8 +5,9 @@ check at the full workload-5 size.
 
 Loss (workload 5): L = || P_N - T ||_2, P_N the CR momentum density after N steps.
 Bar: FP64 adjoint within 1e-6 (relative, per coordinate, floored at 1e-6 of the
-largest gradient component) of the oracle's gradient; the FP32 variant's error is
-reported and bounded loosely."""
+largest gradient component) of the oracle's complex-step gradient; the FP32 variant
+within 1e-4 on the small workload, and after the 256 steps of the full one within 1e-2
+at most and 1e-4 in the median."""
 
 import sys
 
@@ -54,7 +55,7 @@ def _errors(got, ref):
     return np.abs(got - ref) / np.maximum(np.abs(ref), 1e-6 * scale)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-6), ("fp32", 5e-2)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-6), ("fp32", 1e-4)])
 def test_adjoint_matches_oracle_small(precision, tol):
     """Workload-5 recipe at 8^3 x 4 ppc, 24 steps, checkpoints every 8: the 64 sampled
     coordinates (16 of E, 16 of B, 32 of u0) against the oracle's complex step."""
@@ -245,33 +246,53 @@ def test_directional_derivative_full_size_workload5_tsc():
     assert abs(adj - fd) <= 1e-6 * abs(fd)
 
 
-def test_workload5_full_size_matches_oracle_golden():
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_workload5_full_size_matches_oracle_golden(precision):
     """Workload 5 as specified (CIC, 1.05M packets, 256 steps, checkpoints every 16): the
     adjoint at the 64 sampled coordinates against the oracle's complex-step gradients and
     its exact-summation central differences (tests/golden/workload5_gradients.json, written
     by tests/golden/make_workload5_gradients.py from the oracle alone; central differences
-    that crossed a CIC kink are marked there and skipped)."""
+    that crossed a CIC kink are marked there and skipped).
+
+    FP64: within 1e-6 of the complex step at every coordinate.  Against the central
+    differences the error is stated per coordinate as |adjoint - fd| / |fd|; a central
+    difference carries its own error, measured as its distance from the exact complex-step
+    derivative (up to 1.8e-6 relative on the smallest gradients of the golden file), so
+    each coordinate is held to 1e-6 beyond that error of its own difference.
+    FP32 (float32 packet state and arithmetic, FP64 accumulation of the field gradients):
+    after 256 steps the error against the complex step is a few 1e-5 on most coordinates
+    (median 1.3e-5 measured) and up to 5.6e-3 on the coordinates whose gradient is a small
+    sum of larger packet contributions; held to 1e-2 at most and 1e-4 in the median."""
     import json
     import os
     path = os.path.join(os.path.dirname(__file__), "golden", "workload5_gradients.json")
     gold = json.load(open(path))
     w = make_workload(5)
-    _say(f"workload 5 full size vs golden: {w.n_particles} packets, {gold['nsteps']} steps")
-    g = _gpu_grads(w, gold["dt"], gold["nsteps"], 16)
+    _say(f"workload 5 full size vs golden {precision}: {w.n_particles} packets, {gold['nsteps']} steps")
+    g = _gpu_grads(w, gold["dt"], gold["nsteps"], 16, precision)
     coords = [tuple(c) for c in gold["coords"]]
     got = _pick(g, coords)
     cs = np.array(gold["complex_step"])
     fd = np.array(gold["central_difference"])
     ok_fd = ~np.array(gold["fd_rejected"])
     e_cs = _errors(got, cs)
-    # the central differences carry their own rounding floor: compare them relative to at
-    # least 1e-3 of their largest component
-    e_fd = np.abs(got[ok_fd] - fd[ok_fd]) / np.maximum(np.abs(fd[ok_fd]), 1e-3 * np.max(np.abs(fd)))
-    _say(f"workload 5: loss rel {abs(g['L'] - gold['loss']) / gold['loss']:.2e}, adjoint vs complex step max "
-         f"{e_cs.max():.2e}, vs central difference max {e_fd.max():.2e} over {ok_fd.sum()} coordinates")
-    assert abs(g["L"] - gold["loss"]) <= 1e-10 * gold["loss"]
+    lrel = abs(g["L"] - gold["loss"]) / gold["loss"]
+    if precision == "fp32":
+        _say(f"workload 5 fp32: loss rel {lrel:.2e}, adjoint vs complex step max {e_cs.max():.2e}, "
+             f"median {np.median(e_cs):.2e}")
+        assert lrel <= 1e-5 and e_cs.max() <= 1e-2 and np.median(e_cs) <= 1e-4
+        return
+    e_fd = np.abs(got[ok_fd] - fd[ok_fd]) / np.abs(fd[ok_fd])
+    fd_own = np.abs(fd[ok_fd] - cs[ok_fd]) / np.abs(cs[ok_fd])
+    for (kind, comp, where), a, b in zip([c for c, o in zip(coords, ok_fd) if o], e_fd, fd_own):
+        _say(f"  {kind}[{comp},{where}]: adjoint vs central difference {a:.2e} (the difference's own error {b:.2e})")
+    _say(f"workload 5: loss rel {lrel:.2e}, adjoint vs complex step max {e_cs.max():.2e}; vs central difference: "
+         f"{int(np.sum(e_fd <= 1e-6))} of {ok_fd.sum()} coordinates within 1e-6, max {e_fd.max():.2e}, max among "
+         f"differences whose own error is below 1e-7: {e_fd[fd_own < 1e-7].max():.2e}")
+    assert lrel <= 1e-10
     assert e_cs.max() <= 1e-6
-    assert ok_fd.sum() >= 16 and e_fd.max() <= 1e-6
+    assert ok_fd.sum() >= 16 and np.all(e_fd <= 1e-6 + 1.5 * fd_own)
+    assert e_fd[fd_own < 1e-7].max() <= 1e-6
 
 
 def test_reverse_sweep_over_a_prefix_of_the_recorded_steps():
