@@ -121,18 +121,24 @@ struct GlobalAccess {
   __device__ __forceinline__ int64_t node(const int base[3], int cx, int cy, int cz) const {
     return wrapn(base[0] + cx, nx) + (int64_t)nx * (wrapn(base[1] + cy, ny) + (int64_t)ny * wrapn(base[2] + cz, nz));
   }
-  __device__ __forceinline__ T e(int64_t n, int c) const { return E[c * nc + n]; }
-  __device__ __forceinline__ T b(int64_t n, int c) const { return B[c * nc + n]; }
+  // E then B at node n
+  __device__ __forceinline__ void fields(int64_t n, T v[6]) const {
+    #pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      v[c] = E[c * nc + n];
+      v[3 + c] = B[c * nc + n];
+    }
+  }
   __device__ __forceinline__ bool has_ld() const { return ldM != nullptr; }
   __device__ __forceinline__ T lm(int64_t n, int c) const { return (T)ldM[c * nc + n]; }
   __device__ __forceinline__ T le(int64_t n) const { return ldE ? (T)ldE[n] : T(0); }
-  __device__ __forceinline__ void scatter(int64_t n, const V3<T>& lE, const V3<T>& lB, T w) const {
-    atomicAdd(&gE[n], (double)(w * lE.x));
-    atomicAdd(&gE[nc + n], (double)(w * lE.y));
-    atomicAdd(&gE[2 * nc + n], (double)(w * lE.z));
-    atomicAdd(&gB[n], (double)(w * lB.x));
-    atomicAdd(&gB[nc + n], (double)(w * lB.y));
-    atomicAdd(&gB[2 * nc + n], (double)(w * lB.z));
+  // gE += w lE, gB += w lB at node n (FP64 products and sums)
+  __device__ __forceinline__ void scatter(int64_t n, const double lE[3], const double lB[3], double w) const {
+    #pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      atomicAdd(&gE[c * nc + n], w * lE[c]);
+      atomicAdd(&gB[c * nc + n], w * lB[c]);
+    }
   }
 };
 
@@ -146,18 +152,21 @@ struct TileAccess {
   __device__ __forceinline__ int64_t node(const int base[3], int cx, int cy, int cz) const {
     return region_index(base[0] + cx - ox, base[1] + cy - oy, base[2] + cz - oz, rx, pz);
   }
-  __device__ __forceinline__ T e(int64_t n, int c) const { return F[c * kAdjRegion + n]; }
-  __device__ __forceinline__ T b(int64_t n, int c) const { return F[(3 + c) * kAdjRegion + n]; }
+  // E then B at node n (component-major: the lanes of a wave, holding packets of
+  // neighbouring cells, read neighbouring words of each component)
+  __device__ __forceinline__ void fields(int64_t n, T v[6]) const {
+    #pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] = F[c * kAdjRegion + n];
+  }
   __device__ __forceinline__ bool has_ld() const { return L != nullptr; }
   __device__ __forceinline__ T lm(int64_t n, int c) const { return (T)L[c * kAdjRegion + n]; }
   __device__ __forceinline__ T le(int64_t n) const { return (T)L[3 * kAdjRegion + n]; }
-  __device__ __forceinline__ void scatter(int64_t n, const V3<T>& lE, const V3<T>& lB, T w) const {
-    atomicAdd(&G[n], (double)(w * lE.x));
-    atomicAdd(&G[kAdjRegion + n], (double)(w * lE.y));
-    atomicAdd(&G[2 * kAdjRegion + n], (double)(w * lE.z));
-    atomicAdd(&G[3 * kAdjRegion + n], (double)(w * lB.x));
-    atomicAdd(&G[4 * kAdjRegion + n], (double)(w * lB.y));
-    atomicAdd(&G[5 * kAdjRegion + n], (double)(w * lB.z));
+  __device__ __forceinline__ void scatter(int64_t n, const double lE[3], const double lB[3], double w) const {
+    #pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      atomicAdd(&G[c * kAdjRegion + n], w * lE[c]);
+      atomicAdd(&G[(3 + c) * kAdjRegion + n], w * lB[c]);
+    }
   }
 };
 
@@ -181,23 +190,27 @@ __device__ __forceinline__ void packet_backward(const A& acc, const int home[3],
       for (int cx = 0; cx < M; ++cx) {
         const int64_t node = acc.node(base, cx, cy, cz);
         const T w = st.a[0].w[cx] * wyz;
-        Ep.x += w * acc.e(node, 0);
-        Ep.y += w * acc.e(node, 1);
-        Ep.z += w * acc.e(node, 2);
-        Bp.x += w * acc.b(node, 0);
-        Bp.y += w * acc.b(node, 1);
-        Bp.z += w * acc.b(node, 2);
+        T v[6];
+        acc.fields(node, v);
+        Ep.x += w * v[0];
+        Ep.y += w * v[1];
+        Ep.z += w * v[2];
+        Bp.x += w * v[3];
+        Bp.y += w * v[4];
+        Bp.z += w * v[5];
       }
     }
 
-  // ---- recompute the Boris kick (Eq. (11)), keeping its intermediates
+  // ---- recompute the Boris kick (Eq. (11)), keeping its intermediates; Lorentz factors
+  // enter through their reciprocals (hardware estimate plus Newton steps, no IEEE
+  // division or square-root sequence)
   const V3<T> u0 = {u0a[0], u0a[1], u0a[2]};
   const V3<T> um = axpy(h, Ep, u0);
-  const T gm = sqrt(T(1) + dot(um, um));
-  const T kq = h / gm;
+  const T igm = rsqrt_nr<T>(T(1) + dot(um, um));  // 1 / gamma-
+  const T kq = h * igm;
   const V3<T> t = {kq * Bp.x, kq * Bp.y, kq * Bp.z};
   const T tt = dot(t, t);
-  const T sf = T(2) / (T(1) + tt);
+  const T sf = T(2) * rcp_nr<T>(T(1) + tt);
   const V3<T> s = {sf * t.x, sf * t.y, sf * t.z};
   const V3<T> up = [&] {
     const V3<T> c = cross(um, t);
@@ -206,18 +219,18 @@ __device__ __forceinline__ void packet_backward(const A& acc, const int home[3],
   const V3<T> r = cross(up, s);
   const V3<T> du = {T(2) * h * Ep.x + r.x, T(2) * h * Ep.y + r.y, T(2) * h * Ep.z + r.z};
   const V3<T> u1 = {u0.x + du.x, u0.y + du.y, u0.z + du.z};
-  const T g1 = sqrt(T(1) + dot(u1, u1));
+  const T g1sq = T(1) + dot(u1, u1);
+  const T ig1 = rsqrt_nr<T>(g1sq);  // 1 / gamma(u1)
 
   // ---- drift adjoint: x1 = x0 + c_tilde dt u1 / g1
   V3<T> lx = {lxa[0], lxa[1], lxa[2]};
   V3<T> lu1 = {lua[0], lua[1], lua[2]};
   {
     const T cd = (T)k.cdt;
-    const T ig = T(1) / g1;
-    const T ul = dot(u1, lx) * ig * ig * ig;
-    lu1.x += cd * (lx.x * ig - u1.x * ul);
-    lu1.y += cd * (lx.y * ig - u1.y * ul);
-    lu1.z += cd * (lx.z * ig - u1.z * ul);
+    const T ul = dot(u1, lx) * ig1 * ig1 * ig1;
+    lu1.x += cd * (lx.x * ig1 - u1.x * ul);
+    lu1.y += cd * (lx.y * ig1 - u1.y * ul);
+    lu1.z += cd * (lx.z * ig1 - u1.z * ul);
   }
 
   // ---- exchange-deposit adjoint (cotangent of the summed exchange, optional)
@@ -227,8 +240,10 @@ __device__ __forceinline__ void packet_backward(const A& acc, const int home[3],
     V3<T> ldu = {0, 0, 0};
     T ldg = 0;
     const T pf = (T)k.pfac, ef = (T)k.efac;
-    const T g0 = sqrt(T(1) + dot(u0, u0));
-    const T dg = dot(du, V3<T>{u1.x + u0.x, u1.y + u0.y, u1.z + u0.z}) / (g0 + g1);
+    const T g0sq = T(1) + dot(u0, u0);
+    const T ig0 = rsqrt_nr<T>(g0sq);
+    // gamma(u1) - gamma(u0) = (u1 - u0) . (u1 + u0) / (gamma(u1) + gamma(u0))
+    const T dg = dot(du, V3<T>{u1.x + u0.x, u1.y + u0.y, u1.z + u0.z}) * rcp_nr<T>(g0sq * ig0 + g1sq * ig1);
     #pragma unroll
     for (int cz = 0; cz < M; ++cz)
       #pragma unroll
@@ -249,12 +264,12 @@ __device__ __forceinline__ void packet_backward(const A& acc, const int home[3],
           gxw[2] += st.a[0].w[cx] * st.a[1].w[cy] * st.dw[2][cz] * val;
         }
     // du = u1 - u0, dgamma = gamma(u1) - gamma(u0)
-    lu1.x += ldu.x + ldg * u1.x / g1;
-    lu1.y += ldu.y + ldg * u1.y / g1;
-    lu1.z += ldu.z + ldg * u1.z / g1;
-    lu0_extra.x = -ldu.x - ldg * u0.x / g0;
-    lu0_extra.y = -ldu.y - ldg * u0.y / g0;
-    lu0_extra.z = -ldu.z - ldg * u0.z / g0;
+    lu1.x += ldu.x + ldg * u1.x * ig1;
+    lu1.y += ldu.y + ldg * u1.y * ig1;
+    lu1.z += ldu.z + ldg * u1.z * ig1;
+    lu0_extra.x = -ldu.x - ldg * u0.x * ig0;
+    lu0_extra.y = -ldu.y - ldg * u0.y * ig0;
+    lu0_extra.z = -ldu.z - ldg * u0.z * ig0;
   }
 
   // ---- Boris adjoint, in reverse order of the forward sequence
@@ -280,17 +295,21 @@ __device__ __forceinline__ void packet_backward(const A& acc, const int home[3],
   }
   // t = (h/gm) B_p
   const V3<T> lB = {kq * lt.x, kq * lt.y, kq * lt.z};
-  const T lgm = -(kq / gm) * dot(Bp, lt);
-  // gm = sqrt(1 + u-.u-)
-  lum.x += lgm * um.x / gm;
-  lum.y += lgm * um.y / gm;
-  lum.z += lgm * um.z / gm;
+  const T lgm = -(kq * igm) * dot(Bp, lt);
+  // gamma- = sqrt(1 + u-.u-): d gamma- / d u- = u- / gamma-
+  lum.x += lgm * um.x * igm;
+  lum.y += lgm * um.y * igm;
+  lum.z += lgm * um.z * igm;
   // u- = u0 + h E
   lE.x += h * lum.x;
   lE.y += h * lum.y;
   lE.z += h * lum.z;
 
-  // ---- gather adjoint: scatter into gE, gB and the weight-gradient term for x
+  // ---- gather adjoint: scatter into gE, gB (in FP64: the cotangents are widened once
+  // and each node's weight once, instead of every product) and the weight-gradient term
+  // for x
+  const double lEd[3] = {(double)lE.x, (double)lE.y, (double)lE.z};
+  const double lBd[3] = {(double)lB.x, (double)lB.y, (double)lB.z};
   #pragma unroll
   for (int cz = 0; cz < M; ++cz)
     #pragma unroll
@@ -300,9 +319,10 @@ __device__ __forceinline__ void packet_backward(const A& acc, const int home[3],
       for (int cx = 0; cx < M; ++cx) {
         const int64_t node = acc.node(base, cx, cy, cz);
         const T w = st.a[0].w[cx] * wy_wz;
-        acc.scatter(node, lE, lB, w);
-        const T val = acc.e(node, 0) * lE.x + acc.e(node, 1) * lE.y + acc.e(node, 2) * lE.z +
-                      acc.b(node, 0) * lB.x + acc.b(node, 1) * lB.y + acc.b(node, 2) * lB.z;
+        acc.scatter(node, lEd, lBd, (double)w);
+        T v[6];
+        acc.fields(node, v);
+        const T val = v[0] * lE.x + v[1] * lE.y + v[2] * lE.z + v[3] * lB.x + v[4] * lB.y + v[5] * lB.z;
         gxw[0] += st.dw[0][cx] * wy_wz * val;
         gxw[1] += st.a[0].w[cx] * st.dw[1][cy] * st.a[2].w[cz] * val;
         gxw[2] += st.a[0].w[cx] * st.a[1].w[cy] * st.dw[2][cz] * val;

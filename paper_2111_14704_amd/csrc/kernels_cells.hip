@@ -59,13 +59,31 @@ __device__ __forceinline__ int wrap_near(int i, int n) {
   return min(max(i, 0), n - 1);
 }
 
-// Per-lane strides (elements) of the quad loop's LDS exchange areas: 12 weights + 4
-// exchange values, and up to 8 partial sums, padded so that the 16 quads of a wave
-// (and the lanes of a wave) start on distinct 16-byte bank groups.
+// Layout of the quad loop's LDS exchange areas, chosen against gfx950's measured bank
+// behaviour: reads of 4 bytes go through 32 banks, 32 lanes at a time; reads of 8 bytes
+// through 64 banks, 32 lanes at a time; reads of 12 or 16 bytes through 64 banks, 16
+// lanes at a time; writes and atomics through 32 banks, 32, 16 or 8 lanes at a time for
+// 4, 8 or 16 bytes.  Pk holds per lane 16 values (12 weights, then the 3 offsets that
+// the 4 exchange values replace) at lane pitch kPkLane within a quad and quad pitch
+// kPkQuad (elements): with 24 / 100 (FP32) and 20 / 82 (FP64) the lanes' own 16-byte
+// writes, the quads' broadcast reads and the per-lane reads of one exchange value
+// each fall on distinct banks.  Rs holds per lane up to 8 partial sums at an odd
+// pitch, so that its writes and the reads in which each lane of a quad takes one value
+// from each of its quad's lanes meet no conflict either.
 template <typename T>
-constexpr int kPkStride = sizeof(T) == 8 ? 18 : 20;
+constexpr int kPkLane = sizeof(T) == 8 ? 20 : 24;
 template <typename T>
-constexpr int kRsStride = 10;
+constexpr int kPkQuad = sizeof(T) == 8 ? 82 : 100;
+constexpr int kRsStride = 9;
+// Offset in a wave's Pk area of the values of wave lane L.
+template <typename T>
+__device__ __forceinline__ int pk_at(int L) {
+  return (L >> 2) * kPkQuad<T> + (L & 3) * kPkLane<T>;
+}
+// Pitch (doubles) of one component of the tail's exchange accumulator: 8 dwords apart
+// modulo the 32 banks, so that the four lanes of a quad, adding the four components of
+// one node, never meet in a bank.
+constexpr int kAccPitch = kRegionCells + 4;
 
 // Order the wave's own LDS writes before its following LDS reads (lanes of one wave
 // exchange data through LDS; no other wave touches the area).
@@ -389,8 +407,8 @@ __device__ __forceinline__ int tile_step(int t, int tt, int n) {
 // (wrapped) home cell is h: the part of h's tile inbox reserved for packets from this
 // tile (the self part when h is in this tile).  Returns -1 when the part is full or h's
 // tile is not a neighbour (the packet then needs an overflow slot).
-__device__ __forceinline__ int64_t place_inbox(const StepView& V, int ttx, int tty, int ttz, int* cntD,
-                                               const int* sDcap, const int* sDoff, const int h[3]) {
+__device__ __forceinline__ int place_inbox(const StepView& V, int ttx, int tty, int ttz, int* cntD,
+                                           const int* sDcap, const int* sDoff, const int h[3]) {
   const int tx = (int)((unsigned)h[0] / kCellTile), ty = (int)((unsigned)h[1] / kCellTile),
             tz = (int)((unsigned)h[2] / kCellTile);
   const int sx = tile_step(tx, ttx, V.ntx), sy = tile_step(ty, tty, V.nty), sz = tile_step(tz, ttz, V.ntz);
@@ -398,27 +416,28 @@ __device__ __forceinline__ int64_t place_inbox(const StepView& V, int ttx, int t
   const int dir = (sx + 1) + 3 * ((sy + 1) + 3 * (sz + 1));
   const int s = atomicAdd(&cntD[dir], 1);
   if (s < sDcap[dir]) {
-    const int64_t t = tx + (int64_t)V.ntx * (ty + (int64_t)V.nty * tz);
-    return V.ib0 + t * V.per_tile + sDoff[dir] + s;
+    const uint32_t t = (uint32_t)tx + (uint32_t)V.ntx * ((uint32_t)ty + (uint32_t)V.nty * (uint32_t)tz);
+    return (int)((uint32_t)V.ib0 + t * (uint32_t)V.per_tile + (uint32_t)(sDoff[dir] + s));
   }
   return -1;
 }
 
 // Slot in the return part of the inbox of h's tile, which any workgroup fills through a
 // global counter (cleared after every step), or -1 when that part is full.
-__device__ __forceinline__ int64_t place_return(const StepView& V, const int h[3]) {
-  const int64_t t = (int)((unsigned)h[0] / kCellTile) +
-                    (int64_t)V.ntx * ((int)((unsigned)h[1] / kCellTile) + (int64_t)V.nty * (int)((unsigned)h[2] / kCellTile));
-  const int s = atomicAdd(V.icnt_out + t * kParts + kReturnPart, 1);
-  if (s < V.dcap[kReturnPart]) return V.ib0 + t * V.per_tile + V.doff[kReturnPart] + s;
+__device__ __forceinline__ int place_return(const StepView& V, const int h[3]) {
+  const uint32_t t = (unsigned)h[0] / kCellTile +
+                     (uint32_t)V.ntx * ((unsigned)h[1] / kCellTile + (uint32_t)V.nty * ((unsigned)h[2] / kCellTile));
+  const int s = atomicAdd(V.icnt_out + (int64_t)t * kParts + kReturnPart, 1);
+  if (s < V.dcap[kReturnPart])
+    return (int)((uint32_t)V.ib0 + t * (uint32_t)V.per_tile + (uint32_t)(V.doff[kReturnPart] + s));
   return -1;
 }
 
 // Slot in the next overflow list (global counter), or -1 and ERR_TILE when that is
 // full too (the packet is then lost and the step reports it).
-__device__ __forceinline__ int64_t place_overflow(const StepView& V, uint32_t& err) {
+__device__ __forceinline__ int place_overflow(const StepView& V, uint32_t& err) {
   const int s = atomicAdd(V.icnt_out + V.ntiles * kParts, 1);
-  if ((int64_t)s < V.ocap) return V.ov0 + s;
+  if ((int64_t)s < V.ocap) return (int)((uint32_t)V.ov0 + (uint32_t)s);
   err |= ERR_TILE;
   return -1;
 }
@@ -493,11 +512,11 @@ constexpr bool two_wave_step() {
 // (exchange accumulator of the tile plus halo), which share the same bytes.
 template <typename T>
 struct LoopLds {
-  T Pk[kThreads / 64][64 * kPkStride<T>];  // per lane: the packet's weights, offsets and exchange values
-  T Rs[kThreads / 64][64 * kRsStride<T>];  // per lane: its partial field sums
+  T Pk[kThreads / 64][16 * kPkQuad<T>];  // per lane: the packet's weights, offsets and exchange values
+  T Rs[kThreads / 64][64 * kRsStride];    // per lane: its partial field sums
 };
 struct TailLds {
-  double Acc[4][kRegionCells];
+  double Acc[4][kAccPitch];
 };
 template <typename T>
 union StepLds {
@@ -527,6 +546,7 @@ __global__ void __launch_bounds__(kThreads, (two_wave_step<T, WM>() ? 2 : 1))
   __shared__ int sNb[kCellTileCells];    // bucket packets per local cell
   __shared__ int sPerm[kCellTileCells];  // local cell of each quad, fullest first
   __shared__ uint32_t sQ[kQueue];        // inbox slot of each listed packet, grouped by cell
+  __shared__ unsigned char sLc[kQueue];  // local cell of each listed packet, in inbox order
 
   const int64_t ntiles = V.ntiles;
   int tile = blockIdx.x;
@@ -622,7 +642,9 @@ __global__ void __launch_bounds__(kThreads, (two_wave_step<T, WM>() ? 2 : 1))
   for (int i = tid; i < nlist; i += kThreads) {
     int h[3];
     home_of<T>(Si, inbox_slot(i), k, h);
-    atomicAdd(&qCnt[local_of(h)], 1);
+    const int lc = local_of(h);
+    sLc[i] = (unsigned char)lc;
+    atomicAdd(&qCnt[lc], 1);
   }
   __syncthreads();
   if (tid < kCellTileCells) {
@@ -647,11 +669,8 @@ __global__ void __launch_bounds__(kThreads, (two_wave_step<T, WM>() ? 2 : 1))
   }
   __syncthreads();
   for (int i = tid; i < nlist; i += kThreads) {
-    const uint32_t j = inbox_slot(i);
-    int h[3];
-    home_of<T>(Si, j, k, h);
-    const int lc = local_of(h);
-    sQ[qOff[lc] + atomicAdd(&qFill[lc], 1)] = j;
+    const int lc = sLc[i];
+    sQ[qOff[lc] + atomicAdd(&qFill[lc], 1)] = inbox_slot(i);
   }
   __syncthreads();
 
@@ -762,7 +781,7 @@ __global__ void __launch_bounds__(kThreads, (two_wave_step<T, WM>() ? 2 : 1))
       weights3<M, T>(f[0], wx);
       weights3<M, T>(f[1], wy);
       weights3<M, T>(f[2], wz);
-      T* o = pkw + lane * kPkStride<T>;
+      T* o = pkw + pk_at<T>(lane);
       o[0] = wx[0];
       o[1] = wx[1];
       o[2] = wx[2];
@@ -786,58 +805,58 @@ __global__ void __launch_bounds__(kThreads, (two_wave_step<T, WM>() ? 2 : 1))
     if constexpr (LOSS) {
       #pragma unroll
       for (int J = 0; J < 4; ++J) {
-        const T* wj = pkw + (qbase + J) * kPkStride<T>;
+        const T* wj = pkw + pk_at<T>(qbase + J);
         if constexpr (M == 3) {
           const T dv[3] = {wj[12], wj[13], wj[14]};
-          rsw[lane * kRsStride<T> + 2 * J] = tsc_poly<T>(dv, F0);
-          rsw[lane * kRsStride<T> + 2 * J + 1] = tsc_poly<T>(dv, F1);
+          rsw[lane * kRsStride + 2 * J] = tsc_poly<T>(dv, F0);
+          rsw[lane * kRsStride + 2 * J + 1] = tsc_poly<T>(dv, F1);
         } else {
           T w[12];
           #pragma unroll
           for (int i = 0; i < 12; ++i) w[i] = wj[i];
-          rsw[lane * kRsStride<T> + 2 * J] = stencil_sum<T>(w, F0);
-          rsw[lane * kRsStride<T> + 2 * J + 1] = stencil_sum<T>(w, F1);
+          rsw[lane * kRsStride + 2 * J] = stencil_sum<T>(w, F0);
+          rsw[lane * kRsStride + 2 * J + 1] = stencil_sum<T>(w, F1);
         }
       }
       wave_sync();
       #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        eb[c] = rsw[(qbase + c) * kRsStride<T> + 2 * q];
-        eb[3 + c] = rsw[(qbase + c) * kRsStride<T> + 2 * q + 1];
+        eb[c] = rsw[(qbase + c) * kRsStride + 2 * q];
+        eb[3 + c] = rsw[(qbase + c) * kRsStride + 2 * q + 1];
       }
     } else {
       #pragma unroll
       for (int J = 0; J < 4; ++J) {
-        const T* wj = pkw + (qbase + J) * kPkStride<T>;
+        const T* wj = pkw + pk_at<T>(qbase + J);
         if constexpr (M == 3) {
           const T dv[3] = {wj[12], wj[13], wj[14]};
-          rsw[lane * kRsStride<T> + J] = tsc_poly<T>(dv, F0);
+          rsw[lane * kRsStride + J] = tsc_poly<T>(dv, F0);
         } else {
           T w[12];
           #pragma unroll
           for (int i = 0; i < 12; ++i) w[i] = wj[i];
-          rsw[lane * kRsStride<T> + J] = stencil_sum<T>(w, F0);
+          rsw[lane * kRsStride + J] = stencil_sum<T>(w, F0);
         }
       }
       #pragma unroll
       for (int p = 0; p < 2; ++p) {
-        const T* wj = pkw + (qbase + 2 * p + (q >> 1)) * kPkStride<T>;
+        const T* wj = pkw + pk_at<T>(qbase + 2 * p + (q >> 1));
         if constexpr (M == 3) {
           const T dv[3] = {wj[12], wj[13], wj[14]};
-          rsw[lane * kRsStride<T> + 4 + p] = tsc_poly<T>(dv, F1);
+          rsw[lane * kRsStride + 4 + p] = tsc_poly<T>(dv, F1);
         } else {
           T w[12];
           #pragma unroll
           for (int i = 0; i < 12; ++i) w[i] = wj[i];
-          rsw[lane * kRsStride<T> + 4 + p] = stencil_sum<T>(w, F1);
+          rsw[lane * kRsStride + 4 + p] = stencil_sum<T>(w, F1);
         }
       }
       wave_sync();
       #pragma unroll
-      for (int c = 0; c < 4; ++c) eb[c] = rsw[(qbase + c) * kRsStride<T> + q];
+      for (int c = 0; c < 4; ++c) eb[c] = rsw[(qbase + c) * kRsStride + q];
       const int hy = qbase + 2 * (q & 1);  // lane holding B_y for this lane's packet
-      eb[4] = rsw[hy * kRsStride<T> + 4 + (q >> 1)];
-      eb[5] = rsw[(hy + 1) * kRsStride<T> + 4 + (q >> 1)];
+      eb[4] = rsw[hy * kRsStride + 4 + (q >> 1)];
+      eb[5] = rsw[(hy + 1) * kRsStride + 4 + (q >> 1)];
     }
 
     // kick (Eq. (11))
@@ -847,13 +866,13 @@ __global__ void __launch_bounds__(kThreads, (two_wave_step<T, WM>() ? 2 : 1))
     // wn du - w lost u (momentum) and wn dgamma - w lost gamma (energy)
     T wn = wv, lost = T(0);
     if constexpr (LOSS) {
-      const T nnp = rsw[(qbase + 3) * kRsStride<T> + 2 * q];
+      const T nnp = rsw[(qbase + 3) * kRsStride + 2 * q];
       loss_step<T>(un[0], un[1], un[2], nnp, lrate, wv, &wn, &lost);
     }
 
     // exchange (Eq. (12)) into the quad's registers, lane q taking component q
     if constexpr (DEP) {
-      T* o = pkw + lane * kPkStride<T>;
+      T* o = pkw + pk_at<T>(lane);
       if constexpr (LOSS) {
         const T wl = wv * lost;
         o[12] = act ? pf * (wn * kq.dux - wl * u[0]) : T(0);
@@ -874,7 +893,7 @@ __global__ void __launch_bounds__(kThreads, (two_wave_step<T, WM>() ? 2 : 1))
       wave_sync();
       #pragma unroll
       for (int J = 0; J < 4; ++J) {
-        const T* wj = pkw + (qbase + J) * kPkStride<T>;
+        const T* wj = pkw + pk_at<T>(qbase + J);
         T w[12];
         #pragma unroll
         for (int i = 0; i < 12; ++i) w[i] = wj[i];
@@ -910,7 +929,7 @@ __global__ void __launch_bounds__(kThreads, (two_wave_step<T, WM>() ? 2 : 1))
     if (stay && slot < (int)cap) {
       oj = slot32((uint32_t)tile, (uint32_t)slot, (uint32_t)lc, cap);
     } else if (act) {
-      int64_t j2 = place_inbox(V, ttx, tty, ttz, cntD, sDcap, sDoff, hn);
+      int j2 = place_inbox(V, ttx, tty, ttz, cntD, sDcap, sDoff, hn);
       if (j2 < 0) j2 = place_return(V, hn);
       if (j2 < 0) j2 = place_overflow(V, err);
       ost = j2 >= 0;
@@ -936,7 +955,7 @@ __global__ void __launch_bounds__(kThreads, (two_wave_step<T, WM>() ? 2 : 1))
   __syncthreads();  // every wave is out of its quad loop: the exchange areas become the accumulator
   double* acc = &U.tail.Acc[0][0];
   if constexpr (DEP) {
-    for (int r = tid; r < 4 * kRegionCells; r += kThreads) acc[r] = 0.0;
+    for (int r = tid; r < 4 * kAccPitch; r += kThreads) acc[r] = 0.0;
     __syncthreads();
     if (n > 0) {
       #pragma unroll
@@ -946,7 +965,7 @@ __global__ void __launch_bounds__(kThreads, (two_wave_step<T, WM>() ? 2 : 1))
           #pragma unroll
           for (int a = 0; a < 3; ++a) {
             const int r = (lx + a) + kRegionEdge * ((ly + b) + kRegionEdge * (lz + c));
-            atomicAdd(&acc[q * kRegionCells + r], (double)D[a + 3 * (b + 3 * c)]);
+            atomicAdd(&acc[q * kAccPitch + r], (double)D[a + 3 * (b + 3 * c)]);
           }
     }
   }
@@ -987,7 +1006,7 @@ __global__ void __launch_bounds__(kThreads, (two_wave_step<T, WM>() ? 2 : 1))
             const T W = w[a] * wyz;
             if (W != T(0)) {
               #pragma unroll
-              for (int d = 0; d < 4; ++d) atomicAdd(&acc[d * kRegionCells + r], (double)(W * qv[d]));
+              for (int d = 0; d < 4; ++d) atomicAdd(&acc[d * kAccPitch + r], (double)(W * qv[d]));
             }
           }
         }
@@ -996,7 +1015,7 @@ __global__ void __launch_bounds__(kThreads, (two_wave_step<T, WM>() ? 2 : 1))
     double xn[3];
     T fn[3];
     err |= drift3<T>(k, hm, f, xa, un, hn, xn, fn);
-    int64_t j2 = place_inbox(V, ttx, tty, ttz, cntD, sDcap, sDoff, hn);
+    int j2 = place_inbox(V, ttx, tty, ttz, cntD, sDcap, sDoff, hn);
     if (j2 < 0) j2 = place_return(V, hn);
     if (j2 < 0) j2 = place_overflow(V, err);
     if (j2 >= 0)
@@ -1069,7 +1088,7 @@ __global__ void __launch_bounds__(kThreads, (two_wave_step<T, WM>() ? 2 : 1))
       double xn[3];
       T fn[3];
       err |= drift3<T>(k, hm, f, xa, un, hn, xn, fn);
-      int64_t j2 = place_return(V, hn);
+      int j2 = place_return(V, hn);
       if (j2 < 0) j2 = place_overflow(V, err);
       if (j2 >= 0)
         store_packet<T, WGT>(So, (uint32_t)j2, xn, fn, un, wn, id, hn[0] + k.nx * (hn[1] + k.ny * hn[2]));
@@ -1081,10 +1100,10 @@ __global__ void __launch_bounds__(kThreads, (two_wave_step<T, WM>() ? 2 : 1))
   // ------------------------------------------------------------ outputs
   if constexpr (DEP) {
     double* out = V.halo + (int64_t)tile * 4 * kRegionCells;
-    if (V.accumulate) {
-      for (int r = tid; r < 4 * kRegionCells; r += kThreads) out[r] += acc[r];
-    } else {
-      for (int r = tid; r < 4 * kRegionCells; r += kThreads) out[r] = acc[r];
+    for (int i = tid; i < 4 * kRegionCells; i += kThreads) {
+      const int d = i / kRegionCells;
+      const double v = acc[d * kAccPitch + (i - d * kRegionCells)];
+      out[i] = V.accumulate ? out[i] + v : v;
     }
   }
   if (q == 0 && valid) V.bcnt_out[home[0] + (int64_t)k.nx * (home[1] + (int64_t)k.ny * home[2])] = S < (int)cap ? S : (int)cap;

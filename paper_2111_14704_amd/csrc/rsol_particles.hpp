@@ -27,6 +27,16 @@ struct Packets {
 template <typename T>
 constexpr bool is_fp64() { return std::is_same<T, double>::value; }
 
+// a / b for 0 <= a < 2^31 and b >= 1: the FP64 product with 1/b (a uniform value the
+// compiler hoists out of loops) is within one of the quotient, and one comparison
+// each way (remainder in 64 bits) makes it exact; cheaper than the integer division
+// sequence.
+__device__ __forceinline__ int div_nonneg(int a, int b) {
+  const int q = (int)((double)a * (1.0 / (double)b));
+  const int64_t r = (int64_t)a - (int64_t)q * b;
+  return q + (r < 0 ? -1 : (r >= b ? 1 : 0));
+}
+
 // Home cell coordinates and the in-cell offset (in cells) of packet i.
 template <typename T>
 __device__ __forceinline__ void load_position(const Packets<T>& P, int64_t i, const RunConsts& k,
@@ -42,9 +52,9 @@ __device__ __forceinline__ void load_position(const Packets<T>& P, int64_t i, co
   } else {
     const int c = P.cell[i];
     const int nxy = k.nx * k.ny;
-    const int iz = c / nxy;
+    const int iz = div_nonneg(c, nxy);
     const int r = c - iz * nxy;
-    const int iy = r / k.nx;
+    const int iy = div_nonneg(r, k.nx);
     home[0] = r - iy * k.nx;
     home[1] = iy;
     home[2] = iz;
