@@ -220,6 +220,11 @@ int rsol_cells_to_positions(rsol_handle h, const int32_t* cell, const float* off
  * not change the handle's dt (use rsol_set_dt). */
 int rsol_courant_dt(rsol_handle h, double* dt);
 int rsol_set_dt(rsol_handle h, double dt);
+/* The timestep the next step uses (Sec. 4): the handle's dt when set (rsol_params.dt > 0
+ * or rsol_set_dt); when it is 0, the Courant timestep of the registered packets and
+ * fields (rsol_courant_dt) becomes the handle's dt and is returned.  *dt is a host
+ * pointer.  RSOL_ESTATE when dt is unset and fields or packets are not registered. */
+int rsol_get_dt(rsol_handle h, double* dt);
 
 /* A packet step split into its phases, for any packet order.
  * rsol_gather: Ep, Bp [3][np] (precision type) = fields at the current positions.

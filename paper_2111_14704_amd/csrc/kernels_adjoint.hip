@@ -429,18 +429,38 @@ __global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> 
   const int64_t len = b1 - b0;
   const int64_t j0 = b0 + len * part / parts, j1 = b0 + len * (part + 1) / parts;
   const int n3[3] = {k.nx, k.ny, k.nz};
-  for (int64_t i = j0 + threadIdx.x; i < j1; i += blockDim.x) {
+  // a packet's inputs: state before the step and the adjoint of the state after it
+  struct In {
     int home[3];
-    T f[3], u0a[3];
-    load_position(slab, i, k, home, f);
+    T f[3], u0[3], lx[3], lu[3];
+  };
+  auto load_in = [&](int64_t i, In& p) {
+    load_position(slab, i, k, p.home, p.f);
     #pragma unroll
-    for (int d = 0; d < 3; ++d) u0a[d] = slab.u[d * np + i];
+    for (int d = 0; d < 3; ++d) {
+      p.u0[d] = slab.u[d * np + i];
+      p.lx[d] = lam_x[d * np + i];
+      p.lu[d] = lam_u[d * np + i];
+    }
+  };
+  // each thread's packets in turn; without the exchange adjoint (the variant with room
+  // in its registers) the next packet's inputs load while the current one is reversed
+  constexpr bool kAhead = !LD;
+  int64_t i = j0 + threadIdx.x;
+  In cur, nxt;
+  if (kAhead && i < j1) load_in(i, cur);
+  for (; i < j1; i += blockDim.x) {
+    if constexpr (kAhead) {
+      if (i + blockDim.x < j1) load_in(i + blockDim.x, nxt);
+    } else {
+      load_in(i, cur);
+    }
     // home in the tile's unwrapped frame; the stencil spans home-1 .. home+1
     bool inside = true;
     int hu[3];
     #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const int hw = wrapn(home[d], n3[d]);
+      const int hw = wrapn(cur.home[d], n3[d]);
       int delta = hw - t0[d];
       if (2 * delta >= n3[d]) delta -= n3[d];
       else if (2 * delta < -n3[d]) delta += n3[d];
@@ -450,16 +470,15 @@ __global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> 
     }
     if (!inside) {
       spill[1 + atomicAdd(&spill[0], 1)] = (int32_t)i;
-      continue;
+    } else {
+      packet_backward<M, T>(acc, hu, cur.f, cur.u0, cur.lx, cur.lu, k);
+      #pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        lam_x[d * np + i] = cur.lx[d];
+        lam_u[d * np + i] = cur.lu[d];
+      }
     }
-    T lx[3] = {lam_x[i], lam_x[np + i], lam_x[2 * np + i]};
-    T lu[3] = {lam_u[i], lam_u[np + i], lam_u[2 * np + i]};
-    packet_backward<M, T>(acc, hu, f, u0a, lx, lu, k);
-    #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      lam_x[d * np + i] = lx[d];
-      lam_u[d * np + i] = lu[d];
-    }
+    if constexpr (kAhead) cur = nxt;
   }
   __syncthreads();
   for (int r = threadIdx.x; r < rc; r += blockDim.x) {

@@ -936,6 +936,18 @@ int rsol_set_dt(rsol_handle h, double dt) {
   return RSOL_OK;
 }
 
+int rsol_get_dt(rsol_handle h, double* dt) {
+  if (int rc = need(h, false, false)) return rc;
+  if (!dt) return fail(h, RSOL_EINVAL, "dt is NULL");
+  if (!(h->p.dt > 0)) {
+    double c = 0.0;
+    if (int rc = rsol_courant_dt(h, &c)) return rc;
+    h->p.dt = c;
+  }
+  *dt = h->p.dt;
+  return RSOL_OK;
+}
+
 int rsol_gather(rsol_handle h, void* Ep, void* Bp) {
   if (int rc = need(h, true, true)) return rc;
   if (int rc = sync_arrays(h)) return rc;  // reads the registered packets

@@ -75,6 +75,7 @@ def lib():
             "rsol_cells_to_positions": (ctypes.c_int, [vp, vp, vp, vp]),
             "rsol_courant_dt": (ctypes.c_int, [vp, ctypes.POINTER(dbl)]),
             "rsol_set_dt": (ctypes.c_int, [vp, dbl]),
+            "rsol_get_dt": (ctypes.c_int, [vp, ctypes.POINTER(dbl)]),
             "rsol_gather": (ctypes.c_int, [vp, vp, vp]),
             "rsol_push": (ctypes.c_int, [vp, vp, vp, vp]),
             "rsol_deposit": (ctypes.c_int, [vp, vp, vp, vp]),
@@ -110,7 +111,7 @@ def exported_symbols():
     return [
         "rsol_scratch_bytes", "rsol_init", "rsol_destroy", "rsol_last_error", "rsol_electric_field",
         "rsol_set_fields", "rsol_set_particles", "rsol_positions_to_cells", "rsol_cells_to_positions",
-        "rsol_courant_dt", "rsol_set_dt", "rsol_gather", "rsol_push", "rsol_deposit", "rsol_drift",
+        "rsol_courant_dt", "rsol_set_dt", "rsol_get_dt", "rsol_gather", "rsol_push", "rsol_deposit", "rsol_drift",
         "rsol_sort", "rsol_step", "rsol_moments", "rsol_check", "rsol_timing", "rsol_timing_read",
         "rsol_stray_count", "rsol_set_flags", "rsol_state_bytes", "rsol_record_states", "rsol_step_backward",
         "rsol_moments_backward", "rsol_step_coupled", "rsol_set_losses", "rsol_sync_particles",
@@ -244,6 +245,11 @@ class Handle:
 
     def rsol_set_dt(self, dt: float):
         _check(self.h, lib().rsol_set_dt(self.h, float(dt)))
+
+    def rsol_get_dt(self) -> float:
+        dt = ctypes.c_double()
+        _check(self.h, lib().rsol_get_dt(self.h, ctypes.byref(dt)))
+        return dt.value
 
     def rsol_gather(self, Ep, Bp):
         _check(self.h, lib().rsol_gather(self.h, _ptr(Ep), _ptr(Bp)))

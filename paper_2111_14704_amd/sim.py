@@ -51,8 +51,11 @@ class Simulation:
             self.x = x64
             self.u = torch.as_tensor(np.ascontiguousarray(u), **f64)
             h.rsol_set_particles(self.x, None, self.u, self.ids)
-        self.dt = h.rsol_courant_dt() if dt is None else float(dt)
-        h.rsol_set_dt(self.dt)
+        if dt is None:
+            self.dt = h.rsol_get_dt()  # the handle's dt is unset: it adopts the Courant timestep
+        else:
+            self.dt = float(dt)
+            h.rsol_set_dt(self.dt)
 
     @classmethod
     def from_workload(cls, w, **kw):

@@ -98,6 +98,8 @@ def test_null_handle_calls_fail_cleanly():
     assert L.rsol_sync_particles(None) == -1
     assert L.rsol_moments(None, None, None, None) == -1
     assert L.rsol_set_weights(None, None) == -1
+    dt = ctypes.c_double(-1.0)
+    assert L.rsol_get_dt(None, ctypes.byref(dt)) == -1 and dt.value == -1.0
     assert L.rsol_destroy(None) == 0
 
 

@@ -602,3 +602,9 @@ def test_electric_field_and_courant_dt_match_oracle():
         assert np.max(np.abs(sim.E.cpu().numpy() - E_ref)) <= 1e-15 * max(1e-300, np.abs(E_ref).max()) + 1e-300
         p = oracle_params(w)
         assert sim.dt == pytest.approx(p.dt, rel=1e-15)
+        # the Simulation took its dt from rsol_get_dt on a handle whose dt was unset (the
+        # Courant timestep, pinned to the oracle's above); once set it is returned as is
+        assert sim.handle.rsol_courant_dt() == sim.dt
+        assert sim.handle.rsol_get_dt() == sim.dt
+        sim.handle.rsol_set_dt(0.5 * sim.dt)
+        assert sim.handle.rsol_get_dt() == 0.5 * sim.dt
