@@ -44,11 +44,13 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "particle-updates/s (gather+RSOL push+deposit), FP32 vs FP64, % of HBM peak"
 KERNEL_SOURCES = ["paper_2111_14704_amd/csrc/kernels_cells.hip", "paper_2111_14704_amd/csrc/rsol_cells.hpp",
                   "paper_2111_14704_amd/csrc/rsol_device.hpp"]
+REVERSE_SOURCES = ["paper_2111_14704_amd/csrc/kernels_adjoint.hip", "paper_2111_14704_amd/csrc/rsol_adjoint.hpp",
+                   "paper_2111_14704_amd/csrc/rsol_particles.hpp", "paper_2111_14704_amd/csrc/rsol_device.hpp"]
 
 
-def kernel_hash():
+def kernel_hash(sources=KERNEL_SOURCES):
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in sources:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -81,6 +83,19 @@ def algorithmic_bytes_backward(precision, ppc):
     return packet + cell / ppc
 
 
+def algorithmic_bytes_reverse(precision, ppc):
+    """Bytes one packet must move at minimum in one reverse-step launch: its stored state
+    read and its adjoint (lam_x, lam_u) read and written; per cell, shared by the ppc
+    packets, the fields read and dL/dE, dL/dB (FP64) read-modify-written."""
+    if precision == "fp64":
+        packet = 48 + 2 * 48
+        cell = 48 + 2 * 48
+    else:
+        packet = 28 + 2 * 24                   # cell, offset, u; FP32 adjoint
+        cell = 24 + 2 * 48
+    return packet + cell / ppc
+
+
 def copy_bandwidth(nbytes=1 << 31, reps=5):
     """Achieved bandwidth of a plain device-to-device copy (torch copy_) of nbytes, in GB/s
     counting the bytes read and written; median of reps timed copies."""
@@ -102,9 +117,10 @@ def copy_bandwidth(nbytes=1 << 31, reps=5):
     return 2 * nbytes / times[len(times) // 2] / 1e9
 
 
-def measured_traffic(precision, workload):
-    """HBM bytes per step-kernel launch from the committed rocprofv3 counter runs,
-    if they were taken on the current kernel source; else None."""
+def measured_traffic(precision, workload, kind="step"):
+    """HBM bytes per launch of the step kernel (kind "step") or of the reverse-step kernel
+    (kind "reverse") from the committed rocprofv3 counter runs, if they were taken on
+    the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -112,8 +128,10 @@ def measured_traffic(precision, workload):
         data = json.load(open(path))
     except Exception:
         return None
-    rec = data.get(f"{workload}:{precision}")
-    if not rec or rec.get("kernel_hash") != kernel_hash():
+    key = f"{workload}:{precision}" + ("" if kind == "step" else f":{kind}")
+    rec = data.get(key)
+    sources = KERNEL_SOURCES if kind == "step" else REVERSE_SOURCES
+    if not rec or rec.get("kernel_hash") != kernel_hash(sources):
         return None
     return rec.get("bytes_per_launch")
 
@@ -241,11 +259,26 @@ def time_backward(precision, nsteps=256, ckpt=16):
     value = npk * nsteps / (t2 - t1)
     balg = algorithmic_bytes_backward(precision, w.ppc)
     achieved = balg * value / 1e9
+    # a second, untimed pass with the reverse-step launches bracketed by the library's
+    # HIP events (on its stream): the dominant kernel's roofline
+    E.grad = B.grad = u0.grad = None
+    tspec = dict(spec, time_reverse=True)
+    rho, P, e = RSOLRollout.apply(E, B, x0, u0, tspec, nsteps, ckpt)
+    torch.sqrt(((P - T) ** 2).sum()).backward()
+    torch.cuda.synchronize()
+    rev_s = tspec["reverse_ms"] / max(tspec["reverse_launches"], 1) / 1e3
+    brev = algorithmic_bytes_reverse(precision, w.ppc)
+    rev_launch = brev * npk
+    rev_achieved = rev_launch / rev_s / 1e9
     return dict(workload=w.name, dtype="f64" if precision == "fp64" else "f32", value=value,
                 unit="particle-updates/s", backward_s=t2 - t1, forward_s=t1 - t0, steps=nsteps, ckpt=ckpt,
-                roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                              frac=achieved / HBM_PEAK_GBS, traffic=None, bytes_per_packet_step=balg,
-                              scope="whole backward pass"))
+                reverse_kernel_us=rev_s * 1e6,
+                roofline=dict(bound="hbm", achieved=rev_achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                              frac=rev_achieved / HBM_PEAK_GBS,
+                              traffic=measured_traffic(precision, w.name, "reverse"),
+                              bytes_per_launch=rev_launch, bytes_per_packet=brev, kernel="step_backward_tiled_kernel",
+                              whole_pass=dict(achieved=achieved, frac=achieved / HBM_PEAK_GBS,
+                                              bytes_per_packet_step=balg)))
 
 
 def cpu_baseline(w, sample=1 << 20, steps=10):
@@ -415,10 +448,14 @@ def main():
     bwd = None
     if not args.no_backward:
         bwd = time_backward("fp64")
-        print(f"[bench] backward fp64 {bwd['value']:.3e} upd/s", file=sys.stderr, flush=True)
+        print(f"[bench] backward fp64 {bwd['value']:.3e} upd/s, reverse kernel {bwd['reverse_kernel_us']:.1f} us",
+              file=sys.stderr, flush=True)
         b32 = time_backward("fp32")
-        bwd["fp32"] = dict(value=b32["value"], backward_s=b32["backward_s"], roofline=b32["roofline"])
-        print(f"[bench] backward fp32 {b32['value']:.3e} upd/s", file=sys.stderr, flush=True)
+        bwd["fp32"] = dict(value=b32["value"], backward_s=b32["backward_s"], reverse_kernel_us=b32["reverse_kernel_us"],
+                           roofline=b32["roofline"],
+                           reverse_time_vs_fp64=b32["reverse_kernel_us"] / bwd["reverse_kernel_us"])
+        print(f"[bench] backward fp32 {b32['value']:.3e} upd/s, reverse kernel {b32['reverse_kernel_us']:.1f} us",
+              file=sys.stderr, flush=True)
     if not args.no_copy_bw:
         copy_gbs = copy_bandwidth()
         print(f"[bench] device copy {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)

@@ -325,8 +325,10 @@ int rsol_moments_backward(rsol_handle h, const double* lam_rho, const double* la
 
 /* Launch timing (a profiling aid, not part of the method): while enabled, every step and
  * sort launch made by rsol_step / rsol_sort is bracketed by HIP events on the handle's
- * stream.  rsol_timing_read synchronises the stream, returns the summed milliseconds and
- * launch counts since the last read (host pointers, any may be NULL) and resets them. */
+ * stream, and so is every reverse-step launch of rsol_step_backward (counted with the
+ * step launches).  rsol_timing_read synchronises the stream, returns the summed
+ * milliseconds and launch counts since the last read (host pointers, any may be NULL)
+ * and resets them. */
 int rsol_timing(rsol_handle h, int32_t enable);
 int rsol_timing_read(rsol_handle h, double* step_ms, int64_t* n_step, double* sort_ms, int64_t* n_sort);
 

@@ -89,6 +89,7 @@ class RSOLRollout(torch.autograd.Function):
         run.h.rsol_moments(rho, P, e)
         ctx.run = run
         ctx.ckpts = ckpts
+        ctx.spec = spec
         return rho, P, e
 
     @staticmethod
@@ -106,10 +107,25 @@ class RSOLRollout(torch.autograd.Function):
             slab = h.rsol_state_bytes()
             longest = max(seg for _, seg in ckpts)
             states = torch.empty(slab * longest, dtype=torch.uint8, device=dev)
+            # spec["time_reverse"]: time the reverse-step launches alone with the
+            # library's launch events (a profiling aid; it synchronises once per segment)
+            # and leave their summed milliseconds and count in the spec
+            timing = bool(ctx.spec.get("time_reverse"))
+            rev_ms, rev_n = 0.0, 0
             for snap, seg in reversed(ckpts):
                 run.restore(snap)
                 h.rsol_record_states(seg, states)
+                if timing:
+                    h.rsol_timing(True)
                 h.rsol_step_backward(seg, states, lam_x, lam_u, gE, gB)
+                if timing:
+                    ms, n, _, _ = h.rsol_timing_read()
+                    h.rsol_timing(False)
+                    rev_ms += ms
+                    rev_n += n
+            if timing:
+                ctx.spec["reverse_ms"] = rev_ms
+                ctx.spec["reverse_launches"] = rev_n
         order = run.ids.long()
         gx = torch.zeros((3, run.n), dtype=torch.float64, device=dev)
         gu = torch.zeros_like(gx)
@@ -117,6 +133,7 @@ class RSOLRollout(torch.autograd.Function):
         gu[:, order] = lam_u.double()
         ctx.run = None
         ctx.ckpts = None
+        ctx.spec = None
         return gE, gB, gx, gu, None, None, None
 
 

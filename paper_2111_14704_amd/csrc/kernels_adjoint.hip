@@ -371,7 +371,7 @@ __global__ void __launch_bounds__(kBlock) step_backward_kernel(const void* __res
 // the tile plus a halo of `halo` cells in LDS, accumulates dL/dE, dL/dB there and adds
 // the region to the grid with one atomic per node and component.  A packet whose
 // stencil leaves the region (it moved further than the halo allows since the sort) is
-// appended to `spill` (count in spill[0], packet indices after it) for
+// appended to `spill` (count in spill[parity], packet indices from spill[2]) for
 // step_backward_list_kernel.  LD false: no exchange adjoint (lam_dM NULL) and no Ls
 // region staged, which lets FP32 CIC run three workgroups per CU (TSC keeps the region
 // and checks lam_dM at run time: without it the compiler's allocation of FP32 TSC grew
@@ -380,6 +380,7 @@ template <int M, typename T, bool LD>
 __global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> slab,
                                                                      const int32_t* __restrict__ offsets, Tiling tl,
                                                                      int halo, int parts, int32_t* __restrict__ spill,
+                                                                     int parity,
                                                                      T* __restrict__ lam_x,
                                                                      T* __restrict__ lam_u, const T* __restrict__ E,
                                                                      const T* __restrict__ B,
@@ -469,7 +470,7 @@ __global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> 
       inside &= rel >= 1 && rel <= rext[d] - 2;
     }
     if (!inside) {
-      spill[1 + atomicAdd(&spill[0], 1)] = (int32_t)i;
+      spill[2 + atomicAdd(&spill[parity], 1)] = (int32_t)i;
     } else {
       packet_backward<M, T>(acc, hu, cur.f, cur.u0, cur.lx, cur.lu, k);
       #pragma unroll
@@ -494,21 +495,25 @@ __global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> 
   }
 }
 
-// The packets a tiled reverse step left out (spill[0] of them, indices after it), with
-// the global fields and atomics.
+// The packets a tiled reverse step left out (spill[parity] of them, indices from
+// spill[2]), with the global fields and atomics.  The other count, which the next
+// (earlier) step's tiled kernel fills, is cleared here: that kernel runs after this one
+// on the same stream.
 template <int M, typename T>
-__global__ void __launch_bounds__(kBlock) step_backward_list_kernel(Packets<T> slab, const int32_t* __restrict__ spill,
-                                                                    T* __restrict__ lam_x, T* __restrict__ lam_u,
-                                                                    const T* __restrict__ E, const T* __restrict__ B,
+__global__ void __launch_bounds__(kBlock) step_backward_list_kernel(Packets<T> slab, int32_t* __restrict__ spill,
+                                                                    int parity, T* __restrict__ lam_x,
+                                                                    T* __restrict__ lam_u, const T* __restrict__ E,
+                                                                    const T* __restrict__ B,
                                                                     const double* __restrict__ lam_dM,
                                                                     const double* __restrict__ lam_dE,
                                                                     double* __restrict__ gE, double* __restrict__ gB,
                                                                     RunConsts k) {
   const int64_t np = slab.np;
-  const int n = spill[0];
+  const int n = spill[parity];
+  if (blockIdx.x == 0 && threadIdx.x == 0) spill[1 - parity] = 0;
   const GlobalAccess<T> gacc{E, B, lam_dM, lam_dE, gE, gB, (int64_t)k.ncells, k.nx, k.ny, k.nz};
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-    const int64_t i = spill[1 + t];
+    const int64_t i = spill[2 + t];
     int home[3];
     T f[3], u0a[3];
     load_position(slab, i, k, home, f);
@@ -525,7 +530,7 @@ __global__ void __launch_bounds__(kBlock) step_backward_list_kernel(Packets<T> s
   }
 }
 
-__global__ void clear_count_kernel(int32_t* c) { c[0] = 0; }
+__global__ void clear_counts_kernel(int32_t* c) { c[0] = c[1] = 0; }
 
 __global__ void iota_kernel(int32_t* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -665,35 +670,49 @@ hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_spill_clear(int32_t* spill, hipStream_t s) {
+  hipLaunchKernelGGL(clear_counts_kernel, dim3(1), dim3(1), 0, s, spill);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_step_backward_tiled(int shape, const Packets<T>& slab, const int32_t* offsets,
-                                      const Tiling& t, int halo, int32_t* spill, T* lam_x, T* lam_u, const T* E,
-                                      const T* B, const double* lam_dM, const double* lam_dE, double* gE, double* gB,
-                                      const RunConsts& k, hipStream_t s) {
-  if (!step_backward_tiled_fits(t, halo)) return hipErrorInvalidValue;
+                                      const Tiling& t, int halo, int32_t* spill, int parity, T* lam_x, T* lam_u,
+                                      const T* E, const T* B, const double* lam_dM, const double* lam_dE, double* gE,
+                                      double* gB, const RunConsts& k, hipStream_t s) {
+  if (!step_backward_tiled_fits(t, halo) || (parity != 0 && parity != 1)) return hipErrorInvalidValue;
   // split a tile's packets over several workgroups when tiles are few and full
   const int64_t ntiles = t.ntiles();
   const int64_t per_tile = (slab.np + ntiles - 1) / (ntiles > 0 ? ntiles : 1);
   int parts = (int)((per_tile + 1023) / 1024);
   parts = parts < 1 ? 1 : (parts > 4 ? 4 : parts);
   const dim3 grid((unsigned)(ntiles * parts));
-  hipLaunchKernelGGL(clear_count_kernel, dim3(1), dim3(1), 0, s, spill);
-  const dim3 lgrid((unsigned)(grid_for(slab.np) < 256 ? grid_for(slab.np) : 256));
   if (shape == kShapeCIC) {
     if (lam_dM)
       hipLaunchKernelGGL((step_backward_tiled_kernel<2, T, true>), grid, dim3(kBlock), 0, s, slab, offsets, t, halo,
-                         parts, spill, lam_x, lam_u, E, B, lam_dM, lam_dE, gE, gB, k);
+                         parts, spill, parity, lam_x, lam_u, E, B, lam_dM, lam_dE, gE, gB, k);
     else
       hipLaunchKernelGGL((step_backward_tiled_kernel<2, T, false>), grid, dim3(kBlock), 0, s, slab, offsets, t,
-                         halo, parts, spill, lam_x, lam_u, E, B, lam_dM, lam_dE, gE, gB, k);
-    hipLaunchKernelGGL((step_backward_list_kernel<2, T>), lgrid, dim3(kBlock), 0, s, slab, spill, lam_x, lam_u, E, B,
-                       lam_dM, lam_dE, gE, gB, k);
+                         halo, parts, spill, parity, lam_x, lam_u, E, B, lam_dM, lam_dE, gE, gB, k);
   } else {
     hipLaunchKernelGGL((step_backward_tiled_kernel<3, T, true>), grid, dim3(kBlock), 0, s, slab, offsets, t, halo,
-                       parts, spill, lam_x, lam_u, E, B, lam_dM, lam_dE, gE, gB, k);
-    hipLaunchKernelGGL((step_backward_list_kernel<3, T>), lgrid, dim3(kBlock), 0, s, slab, spill, lam_x, lam_u, E, B,
-                       lam_dM, lam_dE, gE, gB, k);
+                       parts, spill, parity, lam_x, lam_u, E, B, lam_dM, lam_dE, gE, gB, k);
   }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_step_backward_spilled(int shape, const Packets<T>& slab, int32_t* spill, int parity, T* lam_x,
+                                        T* lam_u, const T* E, const T* B, const double* lam_dM, const double* lam_dE,
+                                        double* gE, double* gB, const RunConsts& k, hipStream_t s) {
+  if (parity != 0 && parity != 1) return hipErrorInvalidValue;
+  const dim3 lgrid((unsigned)(grid_for(slab.np) < 256 ? grid_for(slab.np) : 256));
+  if (shape == kShapeCIC)
+    hipLaunchKernelGGL((step_backward_list_kernel<2, T>), lgrid, dim3(kBlock), 0, s, slab, spill, parity, lam_x,
+                       lam_u, E, B, lam_dM, lam_dE, gE, gB, k);
+  else
+    hipLaunchKernelGGL((step_backward_list_kernel<3, T>), lgrid, dim3(kBlock), 0, s, slab, spill, parity, lam_x,
+                       lam_u, E, B, lam_dM, lam_dE, gE, gB, k);
   return hipGetLastError();
 }
 
@@ -718,9 +737,12 @@ hipError_t launch_moments_backward(int shape, const Packets<T>& P, const double*
   template hipError_t launch_permute_rows<T>(const T*, T*, const int32_t*, int64_t, int, bool, hipStream_t);   \
   template hipError_t launch_unsort<T>(const Packets<T>&, const Packets<T>&, hipStream_t);                      \
   template hipError_t launch_step_backward_tiled<T>(int, const Packets<T>&, const int32_t*,                        \
-                                                    const Tiling&, int, int32_t*, T*, T*, const T*, const T*,      \
+                                                    const Tiling&, int, int32_t*, int, T*, T*, const T*, const T*, \
                                                     const double*, const double*, double*, double*,                \
-                                                    const RunConsts&, hipStream_t);
+                                                    const RunConsts&, hipStream_t);                                \
+  template hipError_t launch_step_backward_spilled<T>(int, const Packets<T>&, int32_t*, int, T*, T*, const T*,     \
+                                                      const T*, const double*, const double*, double*, double*,    \
+                                                      const RunConsts&, hipStream_t);
 
 RSOL_ADJ_INSTANTIATE(double)
 RSOL_ADJ_INSTANTIATE(float)

@@ -40,17 +40,24 @@ hipError_t launch_step_backward(int shape, const void* slab, int64_t np, T* lam_
 // Same reverse step with the packets held in tile order: tile t's packets are entries
 // [offsets[t*cells_per_tile], offsets[(t+1)*cells_per_tile]) of slab, lam_x and lam_u,
 // as a counting sort of this step's starting state or of one a few steps earlier leaves
-// them.  dL/dE, dL/dB accumulate per tile in LDS
-// over the tile plus a halo of `halo` cells; packets outside it are listed in `spill`
-// (np + 1 int32 of scratch) and reversed by a second kernel with global atomics.  Needs
-// step_backward_tiled_fits(t, halo).
+// them.  dL/dE, dL/dB accumulate per tile in LDS over the tile plus a halo of `halo`
+// cells; packets outside it are listed in `spill` (np + 2 int32 of scratch: two counts,
+// then indices; this step counts in spill[parity]), and launch_step_backward_spilled
+// reverses them with global atomics.  launch_spill_clear zeroes both counts before the
+// first step of a sweep; each spilled launch zeroes the count the next step uses.
+// Needs step_backward_tiled_fits(t, halo).
 bool step_backward_tiled_fits(const Tiling& t, int halo);
 hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t s);
+hipError_t launch_spill_clear(int32_t* spill, hipStream_t s);
 template <typename T>
 hipError_t launch_step_backward_tiled(int shape, const Packets<T>& slab, const int32_t* offsets,
-                                      const Tiling& t, int halo, int32_t* spill, T* lam_x, T* lam_u, const T* E,
-                                      const T* B, const double* lam_dM, const double* lam_dE, double* gE, double* gB,
-                                      const RunConsts& k, hipStream_t s);
+                                      const Tiling& t, int halo, int32_t* spill, int parity, T* lam_x, T* lam_u,
+                                      const T* E, const T* B, const double* lam_dM, const double* lam_dE, double* gE,
+                                      double* gB, const RunConsts& k, hipStream_t s);
+template <typename T>
+hipError_t launch_step_backward_spilled(int shape, const Packets<T>& slab, int32_t* spill, int parity, T* lam_x,
+                                        T* lam_u, const T* E, const T* B, const double* lam_dM, const double* lam_dE,
+                                        double* gE, double* gB, const RunConsts& k, hipStream_t s);
 
 // rows x np arrays (row stride np): dst[r][j] = src[r][idx[j]], or with scatter
 // dst[r][idx[j]] = src[r][j]; idx is a permutation of 0..np-1.

@@ -32,7 +32,7 @@ struct rsol_ctx {
   float* B32;
   char* cells_base;     // cell-list buffers of the default step path
   int32_t* iota;        // 0..np-1: recorded packet indices for the adjoint's sort
-  int32_t* spill;       // packets a tiled reverse step leaves to the global kernel (count, then indices)
+  int32_t* spill;       // packets a tiled reverse step leaves to the global kernel (two counts, then indices)
   float* nn32;          // FP32 copy of the nucleon density (FP32 form with RSOL_FLAG_LOSSES)
   // registered caller arrays
   const double* E;
@@ -596,10 +596,13 @@ template <typename T>
 int backward_global(rsol_ctx* h, int32_t nsteps, const char* states, T* lam_x, T* lam_u, const double* lam_dM,
                     const double* lam_dE, double* gE, double* gB, const RunConsts& k) {
   const SlabLayout sl = slab_layout(h);
-  for (int32_t n = nsteps - 1; n >= 0; --n)
+  for (int32_t n = nsteps - 1; n >= 0; --n) {
+    const auto pr = timed_begin(h);
     RSOL_HIP(h, launch_step_backward<T>(h->p.shape, states + (size_t)n * sl.total + sl.state, h->np, lam_x, lam_u,
                                         field_E<T>(h), field_B<T>(h), lam_dM, lam_dE, gE, gB, k, h->stream),
              "step backward");
+    timed_end(h, pr, false);
+  }
   return RSOL_OK;
 }
 
@@ -616,6 +619,7 @@ int backward_tiled(rsol_ctx* h, int32_t nsteps, const char* states, T* lam_x, T*
   const int32_t* order = (const int32_t*)(first_slab(block) + sl.order);
   RSOL_HIP(h, launch_permute_rows<T>(lam_x, L0, order, np, 3, false, h->stream), "adjoint gather");
   RSOL_HIP(h, launch_permute_rows<T>(lam_u, L0 + 3 * np, order, np, 3, false, h->stream), "adjoint gather");
+  RSOL_HIP(h, launch_spill_clear(h->spill, h->stream), "spill clear");
   for (int32_t n = nsteps - 1; n >= 0; --n) {
     const int b = n / kAdjBlock;
     if (b != block) {
@@ -628,9 +632,16 @@ int backward_tiled(rsol_ctx* h, int32_t nsteps, const char* states, T* lam_x, T*
       block = b;
     }
     const int32_t* offsets = (const int32_t*)(first_slab(b) + sl.offsets);
-    RSOL_HIP(h, launch_step_backward_tiled<T>(h->p.shape, slab_packets<T>(h, states + (size_t)n * sl.total + sl.state),
-                                              offsets, h->tiling, kAdjHalo, h->spill, L0, L0 + 3 * np, field_E<T>(h),
-                                              field_B<T>(h), lam_dM, lam_dE, gE, gB, k, h->stream), "step backward");
+    const Packets<T> slab = slab_packets<T>(h, states + (size_t)n * sl.total + sl.state);
+    const int parity = n & 1;
+    const auto pr = timed_begin(h);
+    RSOL_HIP(h, launch_step_backward_tiled<T>(h->p.shape, slab, offsets, h->tiling, kAdjHalo, h->spill, parity, L0,
+                                              L0 + 3 * np, field_E<T>(h), field_B<T>(h), lam_dM, lam_dE, gE, gB, k,
+                                              h->stream), "step backward");
+    timed_end(h, pr, false);
+    RSOL_HIP(h, launch_step_backward_spilled<T>(h->p.shape, slab, h->spill, parity, L0, L0 + 3 * np, field_E<T>(h),
+                                                field_B<T>(h), lam_dM, lam_dE, gE, gB, k, h->stream),
+             "step backward spilled");
   }
   const int32_t* order0 = (const int32_t*)(states + sl.order);
   RSOL_HIP(h, launch_permute_rows<T>(L0, lam_x, order0, np, 3, true, h->stream), "adjoint scatter");
