@@ -706,7 +706,9 @@ hipError_t launch_step_backward_spilled(int shape, const Packets<T>& slab, int32
                                         T* lam_u, const T* E, const T* B, const double* lam_dM, const double* lam_dE,
                                         double* gE, double* gB, const RunConsts& k, hipStream_t s) {
   if (parity != 0 && parity != 1) return hipErrorInvalidValue;
-  const dim3 lgrid((unsigned)(grid_for(slab.np) < 256 ? grid_for(slab.np) : 256));
+  // strays are rare (packets that outran the staged halo since their block's sort): a
+  // small grid keeps the launch cheap when there are none
+  const dim3 lgrid((unsigned)(grid_for(slab.np) < 32 ? grid_for(slab.np) : 32));
   if (shape == kShapeCIC)
     hipLaunchKernelGGL((step_backward_list_kernel<2, T>), lgrid, dim3(kBlock), 0, s, slab, spill, parity, lam_x,
                        lam_u, E, B, lam_dM, lam_dE, gE, gB, k);

@@ -756,21 +756,25 @@ __global__ void __launch_bounds__(kThreads, (two_wave_step<T, WM>() ? 2 : 1))
     if (ost) store_packet<T, WGT>(So, oj, oxn, ofn, oun, ow, oid, ocell);
   };
   auto round = [&](const int rd) {
+    // A lane past its cell's count computes on the registers of its last packet (or the
+    // zeros they start with): finite values whose results are dropped, its exchange
+    // values being scaled by zero and its packet not stored.
     const bool act = 4 * rd + q < n;
     T f[3], u[3];
     double xa[3] = {0.0, 0.0, 0.0};
     const int32_t id = pid;
-    const T wv = act ? pw : T(1);
+    const T wv = pw;
+    const T pfa = act ? pf : T(0), efa = act ? ef : T(0);
     #pragma unroll
     for (int d = 0; d < 3; ++d) {
       if constexpr (is_fp64<T>()) {
         xa[d] = px[d];
         const double s = xa[d] * k.inv_dx;
-        f[d] = act ? s - floor(s) : 0.5;
+        f[d] = s - floor(s);
       } else {
-        f[d] = act ? (T)px[d] : T(0.5);
+        f[d] = (T)px[d];
       }
-      u[d] = act ? pu[d] : T(0);
+      u[d] = pu[d];
     }
     flush();
     fetch(rd + 1);
@@ -875,20 +879,20 @@ __global__ void __launch_bounds__(kThreads, (two_wave_step<T, WM>() ? 2 : 1))
       T* o = pkw + pk_at<T>(lane);
       if constexpr (LOSS) {
         const T wl = wv * lost;
-        o[12] = act ? pf * (wn * kq.dux - wl * u[0]) : T(0);
-        o[13] = act ? pf * (wn * kq.duy - wl * u[1]) : T(0);
-        o[14] = act ? pf * (wn * kq.duz - wl * u[2]) : T(0);
-        o[15] = act ? ef * (wn * kq.dg - wl * kq.g0) : T(0);
+        o[12] = pfa * (wn * kq.dux - wl * u[0]);
+        o[13] = pfa * (wn * kq.duy - wl * u[1]);
+        o[14] = pfa * (wn * kq.duz - wl * u[2]);
+        o[15] = efa * (wn * kq.dg - wl * kq.g0);
       } else if constexpr (WGT) {
-        o[12] = act ? pf * (wv * kq.dux) : T(0);
-        o[13] = act ? pf * (wv * kq.duy) : T(0);
-        o[14] = act ? pf * (wv * kq.duz) : T(0);
-        o[15] = act ? ef * (wv * kq.dg) : T(0);
+        o[12] = pfa * (wv * kq.dux);
+        o[13] = pfa * (wv * kq.duy);
+        o[14] = pfa * (wv * kq.duz);
+        o[15] = efa * (wv * kq.dg);
       } else {
-        o[12] = act ? pf * kq.dux : T(0);
-        o[13] = act ? pf * kq.duy : T(0);
-        o[14] = act ? pf * kq.duz : T(0);
-        o[15] = act ? ef * kq.dg : T(0);
+        o[12] = pfa * kq.dux;
+        o[13] = pfa * kq.duy;
+        o[14] = pfa * kq.duz;
+        o[15] = efa * kq.dg;
       }
       wave_sync();
       #pragma unroll
