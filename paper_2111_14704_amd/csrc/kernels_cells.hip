@@ -454,16 +454,15 @@ __device__ __forceinline__ uint32_t drift3(const RunConsts& k, const int home[3]
   const int n3[3] = {k.nx, k.ny, k.nz};
   if constexpr (is_fp64<T>()) {
     const double L3[3] = {k.Lx, k.Ly, k.Lz};
-    // periodic wrap with selects (a step moves less than one box length); one rare
-    // branch takes what is still outside [0, L) (a flagged runaway or non-finite step)
+    // periodic wrap and the cell index, each in a branch that only the lanes leaving
+    // the box (or landing on its upper face by rounding) take: a wave without such a
+    // lane skips it
     bool out = false;
     #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const double stp = s * un[d];
       bad |= fabs(stp) > k.max_step * k.dx;
-      double y = xa[d] + stp;
-      y = y < 0.0 ? y + L3[d] : y;
-      y = y >= L3[d] ? y - L3[d] : y;
+      const double y = xa[d] + stp;
       out |= !(y >= 0.0 && y < L3[d]);
       xn[d] = y;
       fn[d] = 0;
@@ -472,9 +471,18 @@ __device__ __forceinline__ uint32_t drift3(const RunConsts& k, const int home[3]
       #pragma unroll
       for (int d = 0; d < 3; ++d) xn[d] = wrap_coord(xn[d], L3[d]);
     }
+    bool hout = false;
     #pragma unroll
-    for (int d = 0; d < 3; ++d) h[d] = wrap_near((int)floor(xn[d] * k.inv_dx), n3[d]);
+    for (int d = 0; d < 3; ++d) {
+      h[d] = (int)floor(xn[d] * k.inv_dx);
+      hout |= (unsigned)h[d] >= (unsigned)n3[d];
+    }
+    if (hout) {
+      #pragma unroll
+      for (int d = 0; d < 3; ++d) h[d] = wrap_near(h[d], n3[d]);
+    }
   } else {
+    bool hout = false;
     #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const float stp = s * un[d];
@@ -487,9 +495,15 @@ __device__ __forceinline__ uint32_t drift3(const RunConsts& k, const int home[3]
         fo = 0.0f;
         hd += 1;
       }
-      h[d] = wrap_near(hd, n3[d]);
+      h[d] = hd;
+      hout |= (unsigned)hd >= (unsigned)n3[d];
       fn[d] = fo;
       xn[d] = 0.0;
+    }
+    // the periodic wrap of the cell index, in a branch only lanes leaving the box take
+    if (hout) {
+      #pragma unroll
+      for (int d = 0; d < 3; ++d) h[d] = wrap_near(h[d], n3[d]);
     }
   }
   if (!bad) return 0u;
