@@ -27,9 +27,9 @@
 // per-tile buffer, summed over the steps of one call, which a second kernel adds into
 // the grid.
 //
-// Slot stores are addressed by 32-bit byte offsets from per-component base pointers
-// (the host checks that every component array is below 4 GiB), so loads and stores
-// take their base from scalar registers.
+// A slot store holds one packet record per slot (plus id and weight arrays), addressed
+// from base pointers in scalar registers: records by 64-bit byte offsets, the 4- and
+// 8-byte arrays by 32-bit ones (the host checks that those stay below 4 GiB).
 //
 // Physics per packet as in the other step kernels: gather at x^n, relativistic Boris
 // kick of Eq. (11), exchange of Eq. (12) at x^n, drift with c_tilde beta (Sec. 2).
@@ -268,9 +268,9 @@ StepView step_view(const CellLists& L, bool accumulate) {
   return V;
 }
 
-// One slot store as arrays of 16-byte records, addressed by a slot index j: record j
-// of an array sits at base + 16 j (below 4 GiB), element j of the 4- or 8-byte arrays
-// at base + 4 j or base + 8 j.
+// One slot store, addressed by a slot index j: part a, b (and c) of record j sits at
+// base + kRec j (a, b, c being the record array plus 0, 16, 32 bytes), element j of
+// the 4- or 8-byte arrays at base + 4 j or base + 8 j (below 4 GiB).
 template <typename T>
 struct Slots {
   char* a;   // FP64: {x, y}; FP32: {off_x, off_y, off_z, id}
@@ -303,6 +303,21 @@ __device__ __forceinline__ void st(char* base, uint32_t j, X v) {
   *(X*)(base + boff(j, sizeof(X))) = v;
 }
 
+// Bytes of a slot's packet record (FP32 {off, id}, {u, cell}; FP64 {x, y}, {z, u_x},
+// {u_y, u_z}): one record per slot, so that a packet moved alone fills whole 32-byte
+// sectors (FP32) or nearly (FP64).  Records are addressed with 64-bit byte offsets.
+template <typename T>
+constexpr uint32_t kRec = is_fp64<T>() ? 48u : 32u;
+// Part `base` (a, b or c: the record plus 0, 16 or 32 bytes) of slot j's record.
+template <typename X, typename T>
+__device__ __forceinline__ X ldr(const char* base, uint32_t j) {
+  return *(const X*)(base + (size_t)j * kRec<T>);
+}
+template <typename X, typename T>
+__device__ __forceinline__ void str(char* base, uint32_t j, X v) {
+  *(X*)(base + (size_t)j * kRec<T>) = v;
+}
+
 // The packet of slot j: position (FP64 absolute x) or in-cell offset (FP32), momentum,
 // id, and (FP32) the home cell the slot records.
 template <typename T>
@@ -310,7 +325,7 @@ __device__ __forceinline__ void load_packet(const Slots<T>& S, uint32_t j,
                                             typename std::conditional<is_fp64<T>(), double, float>::type p[3], T u[3],
                                             int32_t& id, int32_t& cell) {
   if constexpr (is_fp64<T>()) {
-    const double2 A = ld<double2>(S.a, j), Bv = ld<double2>(S.b, j), C = ld<double2>(S.c, j);
+    const double2 A = ldr<double2, T>(S.a, j), Bv = ldr<double2, T>(S.b, j), C = ldr<double2, T>(S.c, j);
     p[0] = A.x;
     p[1] = A.y;
     p[2] = Bv.x;
@@ -320,7 +335,7 @@ __device__ __forceinline__ void load_packet(const Slots<T>& S, uint32_t j,
     id = ld<int32_t>(S.id, j);
     cell = 0;
   } else {
-    const float4 A = ld<float4>(S.a, j), Bv = ld<float4>(S.b, j);
+    const float4 A = ldr<float4, T>(S.a, j), Bv = ldr<float4, T>(S.b, j);
     p[0] = A.x;
     p[1] = A.y;
     p[2] = A.z;
@@ -337,13 +352,13 @@ template <typename T, bool WGT>
 __device__ __forceinline__ void store_packet(const Slots<T>& S, uint32_t j, const double x[3], const T f[3],
                                              const T u[3], T wv, int32_t id, int32_t cell) {
   if constexpr (is_fp64<T>()) {
-    st<double2>(S.a, j, make_double2(x[0], x[1]));
-    st<double2>(S.b, j, make_double2(x[2], u[0]));
-    st<double2>(S.c, j, make_double2(u[1], u[2]));
+    str<double2, T>(S.a, j, make_double2(x[0], x[1]));
+    str<double2, T>(S.b, j, make_double2(x[2], u[0]));
+    str<double2, T>(S.c, j, make_double2(u[1], u[2]));
     st<int32_t>(S.id, j, id);
   } else {
-    st<float4>(S.a, j, make_float4(f[0], f[1], f[2], __int_as_float(id)));
-    st<float4>(S.b, j, make_float4(u[0], u[1], u[2], __int_as_float(cell)));
+    str<float4, T>(S.a, j, make_float4(f[0], f[1], f[2], __int_as_float(id)));
+    str<float4, T>(S.b, j, make_float4(u[0], u[1], u[2], __int_as_float(cell)));
   }
   if constexpr (WGT) st<T>(S.w, j, wv);
 }
@@ -382,13 +397,13 @@ template <typename T>
 __device__ __forceinline__ void home_of(const Slots<T>& S, uint32_t j, const RunConsts& k, int h[3]) {
   if constexpr (is_fp64<T>()) {
     const int n3[3] = {k.nx, k.ny, k.nz};
-    const double2 A = ld<double2>(S.a, j);
-    const double z = *(const double*)(S.b + boff(j, 16));
+    const double2 A = ldr<double2, T>(S.a, j);
+    const double z = ldr<double, T>(S.b, j);
     h[0] = wrapm((int)floor(A.x * k.inv_dx), n3[0]);
     h[1] = wrapm((int)floor(A.y * k.inv_dx), n3[1]);
     h[2] = wrapm((int)floor(z * k.inv_dx), n3[2]);
   } else {
-    cell_coords(*(const int32_t*)(S.b + boff(j, 16) + 12), k, h);
+    cell_coords(ldr<int32_t, T>(S.b + 12, j), k, h);
   }
 }
 
@@ -1436,9 +1451,10 @@ SlotArrays carve_slots(Carver& cv, int64_t nslots, bool f32, bool weights) {
   SlotArrays S;
   S.stride = nslots;
   const size_t n = (size_t)nslots;
-  S.a = (void*)cv.take(16 * n);
-  S.b = (void*)cv.take(16 * n);
-  S.c = f32 ? nullptr : (void*)cv.take(16 * n);
+  char* rec = cv.take((f32 ? 32 : 48) * n);
+  S.a = (void*)rec;
+  S.b = (void*)(rec + 16);
+  S.c = f32 ? nullptr : (void*)(rec + 32);
   S.id = f32 ? nullptr : (int32_t*)cv.take(n * sizeof(int32_t));
   S.w = weights ? (void*)cv.take(n * (f32 ? sizeof(float) : sizeof(double))) : nullptr;
   return S;
@@ -1509,9 +1525,10 @@ size_t cell_list_bytes(int nx, int ny, int nz, int64_t np, int precision, bool w
 bool cell_list_fits(int nx, int ny, int nz, int64_t np, int precision) {
   int64_t slots = 0;
   (void)carve(nx, ny, nz, np, precision, false, 0, nullptr, &slots);
-  // the 16-byte record arrays of a slot store are addressed by 32-bit byte offsets
+  // the id and weight arrays of a slot store (up to 8 bytes per slot) are addressed by
+  // 32-bit byte offsets, the records by 64-bit ones
   (void)precision;
-  return slots * 16 < ((int64_t)1 << 32);
+  return slots * 8 < ((int64_t)1 << 32);
 }
 
 CellLists cell_list_carve(int nx, int ny, int nz, int64_t np, int precision, bool weights, char* base) {

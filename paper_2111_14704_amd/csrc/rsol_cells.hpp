@@ -21,13 +21,15 @@ constexpr int kSelfDir = 13;                         // offset (0, 0, 0)
 constexpr int kParts = kDirs + 1;                    // inbox parts of a tile: one per offset, then the return part
 constexpr int kReturnPart = kDirs;                   // filled with global atomics, from any workgroup
 
-// One packet store, as arrays of 16-byte records per slot so that a lane moves a
-// packet with a few 16-byte loads or stores:
-//   FP64: a = {x, y}, b = {z, u_x}, c = {u_y, u_z} (double pairs), id (int32)
-//   FP32: a = {off_x, off_y, off_z, id bits}, b = {u_x, u_y, u_z, home cell bits} (floats)
-// plus the packet weights (precision type) when the layout carries them.  A bucket
-// slot implies its cell; inbox and overflow slots keep it (FP32) or imply it by the
-// position (FP64).
+// One packet store: one record per slot, so that a lane moves a packet with a few
+// 16-byte loads or stores into one contiguous record and a packet stored alone (a
+// mover in an inbox part) fills whole 32-byte sectors:
+//   FP64 48 bytes: a = {x, y}, b = {z, u_x}, c = {u_y, u_z} (double pairs), then id (int32)
+//     in an array of its own
+//   FP32 32 bytes: a = {off_x, off_y, off_z, id bits}, b = {u_x, u_y, u_z, home cell bits}
+// (a, b, c point at the record array plus 0, 16, 32 bytes), plus the packet weights
+// (precision type) when the layout carries them.  A bucket slot implies its cell; inbox
+// and overflow slots keep it (FP32) or imply it by the position (FP64).
 struct SlotArrays {
   void* a;
   void* b;
@@ -74,8 +76,8 @@ struct CellLists {
 
 // Scratch bytes the layout needs (`weights`: the slot stores carry packet weights).
 size_t cell_list_bytes(int nx, int ny, int nz, int64_t np, int precision, bool weights);
-// Whether every component array of the layout's slot stores stays below 4 GiB (the
-// step kernel addresses them by 32-bit byte offsets).
+// Whether the id and weight arrays of the layout's slot stores stay below 4 GiB (the
+// step kernel addresses them by 32-bit byte offsets; records by 64-bit ones).
 bool cell_list_fits(int nx, int ny, int nz, int64_t np, int precision);
 // Carve the layout out of `base` (256-byte aligned, cell_list_bytes long).
 CellLists cell_list_carve(int nx, int ny, int nz, int64_t np, int precision, bool weights, char* base);
