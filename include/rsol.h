@@ -128,13 +128,17 @@ typedef struct rsol_params {
 
 typedef struct rsol_ctx* rsol_handle;
 
-/* Bytes of device scratch rsol_init needs for these parameters and np packets. */
+/* Bytes of device scratch rsol_init needs for these parameters and np packets; 0 when
+ * the default path's cell lists cannot hold them (their id and weight arrays, up to 8
+ * bytes per slot, are addressed by 32-bit byte offsets: at most 512M slots, about 100
+ * packets per cell on a 128^3 grid). */
 size_t rsol_scratch_bytes(const rsol_params* p, int64_t n_particles);
 
 /* Create a handle.  p is copied (host pointer).  stream: a hipStream_t (NULL = default
  * stream).  scratch: caller-owned device buffer of at least rsol_scratch_bytes() bytes,
  * 256-byte aligned, kept until rsol_destroy.  Errors: RSOL_EINVAL for out-of-range
- * parameters, RSOL_ESCRATCH if scratch_bytes is too small. */
+ * parameters or too many packets for the cell lists, RSOL_ESCRATCH if scratch_bytes is
+ * too small. */
 int rsol_init(const rsol_params* p, int64_t n_particles, void* stream, void* scratch,
               size_t scratch_bytes, rsol_handle* out);
 

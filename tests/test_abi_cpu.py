@@ -104,12 +104,14 @@ def test_null_handle_calls_fail_cleanly():
 
 
 def test_too_many_packets_for_the_cell_lists_are_refused():
-    """The default path addresses its 16-byte slot records with 32-bit byte offsets: a
-    problem whose slot stores would pass 4 GiB is refused before any device work."""
+    """The default path addresses the id and weight arrays of its slot stores (up to 8
+    bytes per slot) with 32-bit byte offsets: a problem whose slot count would take them
+    past 4 GiB is refused before any device work."""
     rsol, L = _lib()
     p = _params(rsol, nx=128, ny=128, nz=128).to_c()
     assert L.rsol_scratch_bytes(ctypes.byref(p), 32 * 128 ** 3) > 0
-    assert L.rsol_scratch_bytes(ctypes.byref(p), 64 * 128 ** 3) == 0
+    assert L.rsol_scratch_bytes(ctypes.byref(p), 96 * 128 ** 3) > 0
+    assert L.rsol_scratch_bytes(ctypes.byref(p), 128 * 128 ** 3) == 0
     h = ctypes.c_void_p()
-    assert L.rsol_init(ctypes.byref(p), 64 * 128 ** 3, None, ctypes.c_void_p(4096), 1 << 40, ctypes.byref(h)) == -1
+    assert L.rsol_init(ctypes.byref(p), 128 * 128 ** 3, None, ctypes.c_void_p(4096), 1 << 40, ctypes.byref(h)) == -1
     assert b"too many packets" in L.rsol_last_error(None)
