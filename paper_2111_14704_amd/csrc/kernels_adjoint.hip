@@ -681,11 +681,17 @@ hipError_t launch_step_backward_tiled(int shape, const Packets<T>& slab, const i
                                       const T* E, const T* B, const double* lam_dM, const double* lam_dE, double* gE,
                                       double* gB, const RunConsts& k, hipStream_t s) {
   if (!step_backward_tiled_fits(t, halo) || (parity != 0 && parity != 1)) return hipErrorInvalidValue;
-  // split a tile's packets over several workgroups when tiles are few and full
+  // one workgroup per tile once the tiles alone give each of the 256 CUs two workgroups
+  // (each workgroup stages and flushes its whole region, so splitting a tile costs a
+  // staging and a flush per part); fewer tiles are split over up to four workgroups,
+  // with at least 256 packets each, so that the chip still fills
   const int64_t ntiles = t.ntiles();
   const int64_t per_tile = (slab.np + ntiles - 1) / (ntiles > 0 ? ntiles : 1);
-  int parts = (int)((per_tile + 1023) / 1024);
-  parts = parts < 1 ? 1 : (parts > 4 ? 4 : parts);
+  constexpr int64_t kFill = 512;
+  int64_t want = ntiles >= kFill ? 1 : (kFill + ntiles - 1) / (ntiles > 0 ? ntiles : 1);
+  want = want > 4 ? 4 : want;
+  const int64_t most = per_tile / 256 < 1 ? 1 : per_tile / 256;
+  const int parts = (int)(want < most ? want : most);
   const dim3 grid((unsigned)(ntiles * parts));
   if (shape == kShapeCIC) {
     if (lam_dM)
