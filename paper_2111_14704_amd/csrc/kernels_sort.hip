@@ -9,10 +9,15 @@
 // atomics hit different addresses, while their HBM accesses stay contiguous.
 //
 // Phases: key + histogram, exclusive scan (bin offsets), per-tile rank tables,
-// scatter.  A packet's rank inside its cell comes from the scatter's per-bin
-// counter; ranks >= kRankCap go to an overflow area at the tile's end.  Packets
-// already in order hit the same bin in neighbouring lanes, so every atomic on a
-// bin counter is aggregated over the run of equal keys inside the wavefront.
+// placement, gather.  A packet's rank inside its cell comes from the histogram's
+// per-bin counter; ranks >= kRankCap go to an overflow area at the tile's end.  The
+// histogram counts each workgroup's chunk of packets in LDS over the 27 tiles around
+// the chunk's first packet (packets sorted by tile before, as between the blocks of
+// the differentiation form, stay within it) and adds each occupied bin to the global
+// counter once; a packet outside that window takes the global counter directly, with
+// one atomic per run of equal keys inside the wavefront.  The placement writes only
+// the inverse permutation; the gather then moves the packet state with scattered reads
+// and contiguous writes.
 #include "rsol_sort.hpp"
 
 namespace rsol {
@@ -25,6 +30,9 @@ constexpr int kMaskWords = 8;  // cells_per_tile <= 256
 constexpr int kScanThreads = 1024;
 constexpr int kScanItems = 4;
 constexpr int kScanChunk = kScanThreads * kScanItems;
+constexpr int kHistPer = 8;                     // packets per thread in the histogram
+constexpr int kHistChunk = kBlock * kHistPer;   // packets per histogram workgroup
+constexpr int kWinTiles = 27;                   // tiles of the histogram's LDS window
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
@@ -74,26 +82,84 @@ __device__ __forceinline__ void home_cell(const Packets<T>& P, int64_t i, const 
   }
 }
 
-// Bin of every packet, the bin histogram, and each packet's rank inside its bin (the
-// counter value its atomic returned).  Packets are read in the previous layout's order,
-// so packets that stayed in their cell tend to keep their rank and, with it, their
-// position: the scatter then writes mostly contiguous runs.
+// Offset of tile coordinate tc from the window centre c along an axis of n tiles: -1,
+// 0 or 1 through the periodic wrap (an axis of one or two tiles uses only 0 and 1, so
+// every tile has one offset), or 2 outside the window.
+__device__ __forceinline__ int window_offset(int tc, int c, int n) {
+  int d = tc - c;
+  if (d < 0) d += n;
+  if (d <= 1) return d;
+  return (n >= 3 && d == n - 1) ? -1 : 2;
+}
+
+// Bin of every packet, the bin histogram, and each packet's rank inside its bin.  One
+// workgroup per chunk of kHistChunk consecutive packets: those whose tile lies in the
+// 27-tile window around the chunk's first packet count in LDS (the LDS atomic's value
+// is the packet's rank within the chunk), then each occupied window bin is added to the
+// global histogram once and its previous value is the chunk's base there; the others
+// take the global counter directly.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) keys_hist_kernel(Packets<T> P, RunConsts k, Tiling t,
                                                            int32_t* __restrict__ keys, int32_t* __restrict__ ranks,
                                                            int32_t* hist) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < P.np; base += stride) {
-    const int64_t i = base + threadIdx.x;
-    int key = -1;
+  __shared__ int32_t cnt[kWinTiles * 32 * kMaskWords];  // per window bin: count, then base
+  __shared__ int sCentre;
+  const int cpt = t.cells_per_tile;
+  const int nwin = kWinTiles * cpt;
+  const int64_t c0 = (int64_t)blockIdx.x * kHistChunk;
+  for (int b = threadIdx.x; b < nwin; b += kBlock) cnt[b] = 0;
+  if (threadIdx.x == 0) {
+    int centre = 0;
+    if (c0 < P.np) {
+      int home[3];
+      home_cell(P, c0, k, home);
+      centre = tile_key(home, t) / cpt;
+    }
+    sCentre = centre;
+  }
+  __syncthreads();
+  const int ct = sCentre;
+  const int cx = ct % t.ntx, cy = (ct / t.ntx) % t.nty, cz = ct / (t.ntx * t.nty);
+  int key[kHistPer], bin[kHistPer], loc[kHistPer];
+  #pragma unroll
+  for (int m = 0; m < kHistPer; ++m) {
+    const int64_t i = c0 + (int64_t)m * kBlock + threadIdx.x;
+    key[m] = -1;
+    bin[m] = -1;
+    loc[m] = 0;
     if (i < P.np) {
       int home[3];
       home_cell(P, i, k, home);
-      key = tile_key(home, t);
-      keys[i] = key;
+      key[m] = tile_key(home, t);
+      keys[i] = key[m];
+      const int tile = key[m] / cpt, lc = key[m] - tile * cpt;
+      const int ox = window_offset(tile % t.ntx, cx, t.ntx);
+      const int oy = window_offset((tile / t.ntx) % t.nty, cy, t.nty);
+      const int oz = window_offset(tile / (t.ntx * t.nty), cz, t.ntz);
+      if (ox < 2 && oy < 2 && oz < 2) {
+        bin[m] = ((ox + 1) + 3 * ((oy + 1) + 3 * (oz + 1))) * cpt + lc;
+        loc[m] = atomicAdd(&cnt[bin[m]], 1);
+      }
     }
-    const int r = aggregated_slot(hist, key);
-    if (i < P.np) ranks[i] = r;
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nwin; b += kBlock) {
+    const int n = cnt[b];
+    if (n > 0) {
+      const int w = b / cpt, lc = b - w * cpt;
+      const int tx = (cx + w % 3 - 1 + t.ntx) % t.ntx;
+      const int ty = (cy + (w / 3) % 3 - 1 + t.nty) % t.nty;
+      const int tz = (cz + w / 9 - 1 + t.ntz) % t.ntz;
+      cnt[b] = atomicAdd(&hist[(tx + t.ntx * (ty + t.nty * tz)) * cpt + lc], n);
+    }
+  }
+  __syncthreads();
+  #pragma unroll
+  for (int m = 0; m < kHistPer; ++m) {
+    const int64_t i = c0 + (int64_t)m * kBlock + threadIdx.x;
+    // every lane of the wave takes part (keys outside the window only, -1 elsewhere)
+    const int rf = aggregated_slot(hist, bin[m] < 0 ? key[m] : -1);
+    if (i < P.np) ranks[i] = bin[m] >= 0 ? cnt[bin[m]] + loc[m] : rf;
   }
 }
 
@@ -141,51 +207,60 @@ __global__ void __launch_bounds__(256) tile_tables_kernel(const int32_t* __restr
   }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock) scatter_kernel(Packets<T> src, Packets<T> dst, Tiling t,
-                                                         const int32_t* __restrict__ keys,
-                                                         const int32_t* __restrict__ ranks,
-                                                         const int32_t* __restrict__ offsets,
-                                                         const int32_t* __restrict__ tables, int32_t* ovf,
-                                                         int32_t* __restrict__ pos_out) {
+// Position in the sorted order of every packet, from its bin, its rank and the tile's
+// rank tables: inv[j] = i (and pos_out[i] = j).
+__global__ void __launch_bounds__(kBlock) place_kernel(int64_t np, Tiling t, const int32_t* __restrict__ keys,
+                                                       const int32_t* __restrict__ ranks,
+                                                       const int32_t* __restrict__ offsets,
+                                                       const int32_t* __restrict__ tables, int32_t* ovf,
+                                                       int32_t* __restrict__ inv, int32_t* __restrict__ pos_out) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t np = src.np;
   const int cpt = t.cells_per_tile;
   const int tw = table_words(t);
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < np; base += stride) {
-    const int64_t i = base + threadIdx.x;
-    if (i < np) {
-      const int key = keys[i];
-      const int rank = ranks[i];
-      const int tile = key / cpt;
-      const int c = key - tile * cpt;
-      const int32_t* e = tables + ((int64_t)tile * (kRankCap + 1)) * tw;
-      int64_t j = offsets[(int64_t)tile * cpt];
-      if (rank < kRankCap) {
-        e += (int64_t)rank * tw;
-        int before = e[0];
-        const int wc = c >> 5;
-        for (int w = 0; w < wc; ++w) before += __popc((uint32_t)e[1 + w]);
-        before += __popc((uint32_t)e[1 + wc] & ((1u << (c & 31)) - 1u));
-        j += before;
-      } else {
-        j += e[(int64_t)kRankCap * tw] + atomicAdd(&ovf[tile], 1);
-      }
-      if (dst.u) {  // NULL: only the permutation (ids) is wanted
-        if constexpr (is_fp64<T>()) {
-          #pragma unroll
-          for (int d = 0; d < 3; ++d) dst.x[d * np + j] = src.x[d * np + i];
-        } else {
-          dst.cell[j] = src.cell[i];
-          #pragma unroll
-          for (int d = 0; d < 3; ++d) dst.off[d * np + j] = src.off[d * np + i];
-        }
-        #pragma unroll
-        for (int d = 0; d < 3; ++d) dst.u[d * np + j] = src.u[d * np + i];
-      }
-      dst.id[j] = src.id[i];
-      if (pos_out) pos_out[i] = (int32_t)j;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += stride) {
+    const int key = keys[i];
+    const int rank = ranks[i];
+    const int tile = key / cpt;
+    const int c = key - tile * cpt;
+    const int32_t* e = tables + ((int64_t)tile * (kRankCap + 1)) * tw;
+    int64_t j = offsets[(int64_t)tile * cpt];
+    if (rank < kRankCap) {
+      e += (int64_t)rank * tw;
+      int before = e[0];
+      const int wc = c >> 5;
+      for (int w = 0; w < wc; ++w) before += __popc((uint32_t)e[1 + w]);
+      before += __popc((uint32_t)e[1 + wc] & ((1u << (c & 31)) - 1u));
+      j += before;
+    } else {
+      j += e[(int64_t)kRankCap * tw] + atomicAdd(&ovf[tile], 1);
     }
+    inv[j] = (int32_t)i;
+    if (pos_out) pos_out[i] = (int32_t)j;
+  }
+}
+
+// dst[j] = src[inv[j]]: scattered reads, contiguous writes (dst.u NULL: the ids only).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) gather_kernel(Packets<T> src, Packets<T> dst,
+                                                        const int32_t* __restrict__ inv) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t np = src.np;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < np; j += stride) {
+    const int64_t i = inv[j];
+    if (i < 0 || i >= np) continue;  // not a placed position (only a corrupt sort leaves one)
+    if (dst.u) {
+      if constexpr (is_fp64<T>()) {
+        #pragma unroll
+        for (int d = 0; d < 3; ++d) dst.x[d * np + j] = src.x[d * np + i];
+      } else {
+        dst.cell[j] = src.cell[i];
+        #pragma unroll
+        for (int d = 0; d < 3; ++d) dst.off[d * np + j] = src.off[d * np + i];
+      }
+      #pragma unroll
+      for (int d = 0; d < 3; ++d) dst.u[d * np + j] = src.u[d * np + i];
+    }
+    dst.id[j] = src.id[i];
   }
 }
 
@@ -257,9 +332,9 @@ size_t sort_scratch_ints(const Tiling& t, int64_t np) {
   const int64_t nbins = t.nbins();
   const int64_t nblk = (nbins + kScanChunk - 1) / kScanChunk;
   const int64_t tw = 1 + (t.cells_per_tile + 31) / 32;
-  // offsets (nbins+1), block sums (nblk+16), keys (np), ranks (np), overflow (ntiles),
-  // rank tables (ntiles * (kRankCap+1) * tw)
-  return (size_t)(nbins + 1) + (size_t)(nblk + 16) + 2 * (size_t)np + (size_t)t.ntiles() +
+  // offsets (nbins+1), block sums (nblk+16), keys (np), ranks (np), inverse
+  // permutation (np), overflow (ntiles), rank tables (ntiles * (kRankCap+1) * tw)
+  return (size_t)(nbins + 1) + (size_t)(nblk + 16) + 3 * (size_t)np + (size_t)t.ntiles() +
          (size_t)t.ntiles() * (kRankCap + 1) * tw;
 }
 
@@ -275,11 +350,13 @@ hipError_t launch_sort(const Packets<T>& src, const Packets<T>& dst, const RunCo
   int32_t* sums = offsets + nbins + 1;     // nblk (+16 slack)
   int32_t* keys = sums + nblk + 16;        // np
   int32_t* ranks = keys + src.np;          // np
-  int32_t* ovf = ranks + src.np;           // ntiles
+  int32_t* inv = ranks + src.np;           // np
+  int32_t* ovf = inv + src.np;             // ntiles
   int32_t* tables = ovf + t.ntiles();      // ntiles * (kRankCap+1) * tw
   hipLaunchKernelGGL(zero_i32_kernel, dim3(grid_for(nbins + 1)), dim3(kBlock), 0, s, offsets, nbins + 1);
-  hipLaunchKernelGGL(keys_hist_kernel<T>, dim3(grid_for(src.np)), dim3(kBlock), 0, s, src, k, t, keys, ranks,
-                     offsets);
+  const int64_t hblocks = (src.np + kHistChunk - 1) / kHistChunk;
+  hipLaunchKernelGGL(keys_hist_kernel<T>, dim3((unsigned)(hblocks < 1 ? 1 : hblocks)), dim3(kBlock), 0, s, src, k,
+                     t, keys, ranks, offsets);
   // exclusive scan of the histogram in place
   hipLaunchKernelGGL(scan_chunk_kernel, dim3((unsigned)nblk), dim3(kScanThreads), 0, s, offsets, offsets, nbins,
                      sums);
@@ -289,8 +366,9 @@ hipError_t launch_sort(const Packets<T>& src, const Packets<T>& dst, const RunCo
   }
   hipLaunchKernelGGL(set_last_kernel, dim3(1), dim3(1), 0, s, offsets, nbins, (int32_t)src.np);
   hipLaunchKernelGGL(tile_tables_kernel, dim3((unsigned)t.ntiles()), dim3(256), 0, s, offsets, t, tables, ovf);
-  hipLaunchKernelGGL(scatter_kernel<T>, dim3(grid_for(src.np)), dim3(kBlock), 0, s, src, dst, t, keys, ranks,
-                     offsets, tables, ovf, pos_out);
+  hipLaunchKernelGGL(place_kernel, dim3(grid_for(src.np)), dim3(kBlock), 0, s, src.np, t, keys, ranks, offsets,
+                     tables, ovf, inv, pos_out);
+  hipLaunchKernelGGL(gather_kernel<T>, dim3(grid_for(src.np)), dim3(kBlock), 0, s, src, dst, inv);
   return hipGetLastError();
 }
 
