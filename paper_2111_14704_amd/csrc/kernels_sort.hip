@@ -239,10 +239,12 @@ __global__ void __launch_bounds__(kBlock) place_kernel(int64_t np, Tiling t, con
   }
 }
 
-// dst[j] = src[inv[j]]: scattered reads, contiguous writes (dst.u NULL: the ids only).
+// dst[j] = src[inv[j]]: scattered reads, contiguous writes (dst.u NULL: the ids only;
+// order_out, optional: a second copy of the ids).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) gather_kernel(Packets<T> src, Packets<T> dst,
-                                                        const int32_t* __restrict__ inv) {
+                                                        const int32_t* __restrict__ inv,
+                                                        int32_t* __restrict__ order_out) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t np = src.np;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < np; j += stride) {
@@ -261,6 +263,7 @@ __global__ void __launch_bounds__(kBlock) gather_kernel(Packets<T> src, Packets<
       for (int d = 0; d < 3; ++d) dst.u[d * np + j] = src.u[d * np + i];
     }
     dst.id[j] = src.id[i];
+    if (order_out) order_out[j] = src.id[i];
   }
 }
 
@@ -269,10 +272,12 @@ __global__ void zero_i32_kernel(int32_t* p, int64_t n) {
     p[i] = 0;
 }
 
-// Exclusive scan of a kScanChunk slice per block; block totals to sums[blockIdx.x].
+// Exclusive scan of a kScanChunk slice per block; block totals to sums[blockIdx.x]; copy
+// (optional) takes the same values, final when there is one block.
 __global__ void __launch_bounds__(kScanThreads) scan_chunk_kernel(const int32_t* __restrict__ in,
                                                                   int32_t* __restrict__ out, int64_t n,
-                                                                  int32_t* __restrict__ sums) {
+                                                                  int32_t* __restrict__ sums,
+                                                                  int32_t* __restrict__ copy) {
   __shared__ int32_t wave_tot[kScanThreads / 64];
   const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
   int32_t v[kScanItems];
@@ -306,20 +311,31 @@ __global__ void __launch_bounds__(kScanThreads) scan_chunk_kernel(const int32_t*
   int32_t excl = wave_tot[wave] + incl - local;
   #pragma unroll
   for (int j = 0; j < kScanItems; ++j) {
-    if (base + j < n) out[base + j] = excl;
+    if (base + j < n) {
+      out[base + j] = excl;
+      if (copy) copy[base + j] = excl;
+    }
     excl += v[j];
   }
 }
 
-__global__ void add_block_offsets_kernel(int32_t* __restrict__ out, int64_t n, const int32_t* __restrict__ sums) {
+__global__ void add_block_offsets_kernel(int32_t* __restrict__ out, int64_t n, const int32_t* __restrict__ sums,
+                                         int32_t* __restrict__ copy) {
   const int64_t base = (int64_t)blockIdx.x * kScanChunk;
   const int32_t add = sums[blockIdx.x];
   for (int j = threadIdx.x; j < kScanChunk; j += blockDim.x)
-    if (base + j < n) out[base + j] += add;
+    if (base + j < n) {
+      const int32_t v = out[base + j] + add;
+      out[base + j] = v;
+      if (copy) copy[base + j] = v;
+    }
 }
 
-// offsets[n] = total packet count
-__global__ void set_last_kernel(int32_t* offsets, int64_t n, int32_t total) { offsets[n] = total; }
+// offsets[n] = total packet count (and in copy, optional)
+__global__ void set_last_kernel(int32_t* offsets, int64_t n, int32_t total, int32_t* copy) {
+  offsets[n] = total;
+  if (copy) copy[n] = total;
+}
 
 inline int grid_for(int64_t n) {
   int64_t g = (n + kBlock - 1) / kBlock;
@@ -343,7 +359,7 @@ int max_cells_per_tile() { return 32 * kMaskWords; }
 
 template <typename T>
 hipError_t launch_sort(const Packets<T>& src, const Packets<T>& dst, const RunConsts& k, const Tiling& t,
-                       int32_t* ints, hipStream_t s, int32_t* pos_out) {
+                       int32_t* ints, hipStream_t s, int32_t* pos_out, int32_t* order_out, int32_t* offsets_out) {
   const int64_t nbins = t.nbins();
   const int64_t nblk = (nbins + kScanChunk - 1) / kScanChunk;
   int32_t* offsets = ints;                 // nbins + 1
@@ -357,18 +373,20 @@ hipError_t launch_sort(const Packets<T>& src, const Packets<T>& dst, const RunCo
   const int64_t hblocks = (src.np + kHistChunk - 1) / kHistChunk;
   hipLaunchKernelGGL(keys_hist_kernel<T>, dim3((unsigned)(hblocks < 1 ? 1 : hblocks)), dim3(kBlock), 0, s, src, k,
                      t, keys, ranks, offsets);
-  // exclusive scan of the histogram in place
+  // exclusive scan of the histogram in place, offsets[nbins] = np
   hipLaunchKernelGGL(scan_chunk_kernel, dim3((unsigned)nblk), dim3(kScanThreads), 0, s, offsets, offsets, nbins,
-                     sums);
+                     sums, nblk > 1 ? (int32_t*)nullptr : offsets_out);
   if (nblk > 1) {
-    hipLaunchKernelGGL(scan_chunk_kernel, dim3(1), dim3(kScanThreads), 0, s, sums, sums, nblk, (int32_t*)nullptr);
-    hipLaunchKernelGGL(add_block_offsets_kernel, dim3((unsigned)nblk), dim3(256), 0, s, offsets, nbins, sums);
+    hipLaunchKernelGGL(scan_chunk_kernel, dim3(1), dim3(kScanThreads), 0, s, sums, sums, nblk, (int32_t*)nullptr,
+                       (int32_t*)nullptr);
+    hipLaunchKernelGGL(add_block_offsets_kernel, dim3((unsigned)nblk), dim3(256), 0, s, offsets, nbins, sums,
+                       offsets_out);
   }
-  hipLaunchKernelGGL(set_last_kernel, dim3(1), dim3(1), 0, s, offsets, nbins, (int32_t)src.np);
+  hipLaunchKernelGGL(set_last_kernel, dim3(1), dim3(1), 0, s, offsets, nbins, (int32_t)src.np, offsets_out);
   hipLaunchKernelGGL(tile_tables_kernel, dim3((unsigned)t.ntiles()), dim3(256), 0, s, offsets, t, tables, ovf);
   hipLaunchKernelGGL(place_kernel, dim3(grid_for(src.np)), dim3(kBlock), 0, s, src.np, t, keys, ranks, offsets,
                      tables, ovf, inv, pos_out);
-  hipLaunchKernelGGL(gather_kernel<T>, dim3(grid_for(src.np)), dim3(kBlock), 0, s, src, dst, inv);
+  hipLaunchKernelGGL(gather_kernel<T>, dim3(grid_for(src.np)), dim3(kBlock), 0, s, src, dst, inv, order_out);
   return hipGetLastError();
 }
 
@@ -378,17 +396,20 @@ hipError_t launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int
   if (n <= 0) return hipSuccess;
   const int64_t nblk = (n + kScanChunk - 1) / kScanChunk;
   if (nblk > kScanChunk) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(scan_chunk_kernel, dim3((unsigned)nblk), dim3(kScanThreads), 0, s, in, out, n, tmp);
+  hipLaunchKernelGGL(scan_chunk_kernel, dim3((unsigned)nblk), dim3(kScanThreads), 0, s, in, out, n, tmp,
+                     (int32_t*)nullptr);
   if (nblk > 1) {
-    hipLaunchKernelGGL(scan_chunk_kernel, dim3(1), dim3(kScanThreads), 0, s, tmp, tmp, nblk, (int32_t*)nullptr);
-    hipLaunchKernelGGL(add_block_offsets_kernel, dim3((unsigned)nblk), dim3(256), 0, s, out, n, tmp);
+    hipLaunchKernelGGL(scan_chunk_kernel, dim3(1), dim3(kScanThreads), 0, s, tmp, tmp, nblk, (int32_t*)nullptr,
+                       (int32_t*)nullptr);
+    hipLaunchKernelGGL(add_block_offsets_kernel, dim3((unsigned)nblk), dim3(256), 0, s, out, n, tmp,
+                       (int32_t*)nullptr);
   }
   return hipGetLastError();
 }
 
 template hipError_t launch_sort<double>(const Packets<double>&, const Packets<double>&, const RunConsts&,
-                                        const Tiling&, int32_t*, hipStream_t, int32_t*);
+                                        const Tiling&, int32_t*, hipStream_t, int32_t*, int32_t*, int32_t*);
 template hipError_t launch_sort<float>(const Packets<float>&, const Packets<float>&, const RunConsts&,
-                                       const Tiling&, int32_t*, hipStream_t, int32_t*);
+                                       const Tiling&, int32_t*, hipStream_t, int32_t*, int32_t*, int32_t*);
 
 }  // namespace rsol

@@ -556,30 +556,27 @@ int record_global(rsol_ctx* h, int32_t nsteps, char* states, const RunConsts& k)
 template <typename T>
 int record_tiled(rsol_ctx* h, int32_t nsteps, char* states, const RunConsts& k) {
   const SlabLayout sl = slab_layout(h);
-  const size_t n_words = (size_t)h->np * sizeof(int32_t);
-  const size_t bin_words = ((size_t)h->tiling.nbins() + 1) * sizeof(int32_t);
   Packets<T> cur = perm_packets<T>(h), nxt = adj_packets2<T>(h);
   RSOL_HIP(h, launch_iota(h->iota, h->np, h->stream), "iota");
   for (int32_t n = 0; n < nsteps; ++n) {
     char* slab = states ? states + (size_t)n * sl.total : nullptr;
     if (n % kAdjBlock == 0) {
+      // the sort also writes the block's order and bin offsets into the step's slab
+      int32_t* order = slab ? (int32_t*)(slab + sl.order) : nullptr;
+      int32_t* offs = slab ? (int32_t*)(slab + sl.offsets) : nullptr;
       if (n == 0) {
         Packets<T> src = caller_packets<T>(h);
         src.id = h->iota;
         src.w = nullptr;
-        RSOL_HIP(h, launch_sort<T>(src, cur, k, h->tiling, h->sort_ints, h->stream), "record sort");
+        RSOL_HIP(h, launch_sort<T>(src, cur, k, h->tiling, h->sort_ints, h->stream, nullptr, order, offs),
+                 "record sort");
       } else {
         int32_t* pos = states ? (int32_t*)(states + (size_t)(n - kAdjBlock) * sl.total + sl.next) : nullptr;
-        RSOL_HIP(h, launch_sort<T>(cur, nxt, k, h->tiling, h->sort_ints, h->stream, pos), "record sort");
+        RSOL_HIP(h, launch_sort<T>(cur, nxt, k, h->tiling, h->sort_ints, h->stream, pos, order, offs),
+                 "record sort");
         const Packets<T> t = cur;
         cur = nxt;
         nxt = t;
-      }
-      if (slab) {
-        RSOL_HIP(h, hipMemcpyAsync(slab + sl.order, cur.id, n_words, hipMemcpyDeviceToDevice, h->stream),
-                 "record order");
-        RSOL_HIP(h, hipMemcpyAsync(slab + sl.offsets, h->sort_ints, bin_words, hipMemcpyDeviceToDevice, h->stream),
-                 "record offsets");
       }
     }
     auto ev = timed_begin(h);

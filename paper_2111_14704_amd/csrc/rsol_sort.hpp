@@ -45,9 +45,12 @@ hipError_t launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int
 // permutation, is written).  ints = scratch of
 // sort_scratch_ints words; on return ints[0..nbins] holds the exclusive bin offsets
 // (ints[nbins] = np), so tile t occupies [ints[t*cells_per_tile], ints[(t+1)*cells_per_tile]).
-// pos_out (optional, np words): the position in dst of each src packet.
+// pos_out (optional, np words): the position in dst of each src packet; order_out
+// (optional, np words): a copy of dst.id; offsets_out (optional, nbins + 1 words): a
+// copy of the bin offsets.
 template <typename T>
 hipError_t launch_sort(const Packets<T>& src, const Packets<T>& dst, const RunConsts& k, const Tiling& t,
-                       int32_t* ints, hipStream_t s, int32_t* pos_out = nullptr);
+                       int32_t* ints, hipStream_t s, int32_t* pos_out = nullptr, int32_t* order_out = nullptr,
+                       int32_t* offsets_out = nullptr);
 
 }  // namespace rsol
