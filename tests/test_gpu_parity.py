@@ -361,6 +361,57 @@ def test_sort_is_a_permutation_into_tile_segments(precision):
         assert np.all(np.diff(ranks) >= 0)
 
 
+def _check_tile_rank_major(sim, u_before, ids_before, pos_before, n, tile_edge=4):
+    """The state after rsol_sort is a bit-exact permutation of the state before it, in
+    tile order and rank-major inside each tile."""
+    ids = sim.ids.cpu().numpy()
+    assert np.array_equal(np.sort(ids), np.arange(sim.n_particles))
+    ib = ids_before.cpu().numpy()
+    inv = np.empty_like(ib)
+    inv[ib] = np.arange(len(ib))
+    src = inv[ids]
+    assert np.array_equal(sim.u.cpu().numpy(), u_before.cpu().numpy()[:, src])
+    pa = (sim.x if sim.x is not None else sim.cell).cpu().numpy()
+    assert np.array_equal(pa, pos_before.cpu().numpy()[..., src])
+    home = np.floor(sim.positions64().cpu().numpy()).astype(int) % n
+    nt = n // tile_edge
+    tile = (home[0] // tile_edge) + nt * ((home[1] // tile_edge) + nt * (home[2] // tile_edge))
+    assert np.all(np.diff(tile) >= 0)
+    cell = home[0] + n * (home[1] + n * home[2])
+    for t in np.unique(tile):
+        seen = {}
+        ranks = []
+        for c in cell[tile == t]:
+            ranks.append(seen.get(c, 0))
+            seen[c] = seen.get(c, 0) + 1
+        assert np.all(np.diff(ranks) >= 0)
+
+
+@pytest.mark.parametrize("n", [4, 8, 12])
+def test_sort_of_sorted_and_moved_packets(n):
+    """A sort whose input is already in tile order (the histogram's 27-tile window path,
+    on grids one, two and three tiles wide), then after every packet moved by up to 1.5
+    cells along each axis (some into neighbouring tiles, some across the periodic wrap):
+    each result is a bit-exact permutation in tile order, rank-major per tile."""
+    torch = _torch()
+    from paper_2111_14704_amd.sim import Simulation
+    w = make_workload(2, n=n, ppc=8, precision="fp64")
+    _say(f"sort of sorted and moved packets n={n}")
+    sim = Simulation.from_workload(w)
+    sim.handle.rsol_sort()
+    for moved in (False, True):
+        if moved:
+            g = torch.Generator(device="cpu").manual_seed(n)
+            step = (torch.rand(sim.x.shape, generator=g, dtype=torch.float64) * 3.0 - 1.5).to(sim.x.device)
+            sim.x.copy_(torch.remainder(sim.x + step * w.dx, n * w.dx))
+            sim.x[sim.x >= n * w.dx] = 0.0  # a remainder that rounded up to the box length
+            sim.handle.rsol_set_particles(sim.x, None, sim.u, sim.ids)
+        u0, i0, p0 = sim.u.clone(), sim.ids.clone(), sim.x.clone()
+        sim.handle.rsol_sort()
+        torch.cuda.synchronize()
+        _check_tile_rank_major(sim, u0, i0, p0, n)
+
+
 def test_exchange_conservation_at_full_size_config2():
     """Workload 2 at full size (64^3 x 64 ppc, 16.8M packets, TSC): one cell-list FP64 step;
     sum over the grid of the deposited momentum equals -(c/c_tilde) M c sum du over the
