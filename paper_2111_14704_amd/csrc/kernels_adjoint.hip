@@ -19,6 +19,8 @@
 // written), so that dL/dE and dL/dB accumulate in LDS.
 #include <math.h>
 
+#include <type_traits>
+
 #include "rsol_adjoint.hpp"
 #include "rsol_sort.hpp"
 
@@ -364,9 +366,41 @@ __global__ void __launch_bounds__(kBlock) step_backward_kernel(const void* __res
   }
 }
 
+// The adjoint of a packet in the tile-ordered sweeps: one record of six values per
+// packet, dL/dx then dL/du, moved with three 16-byte (FP64) or 8-byte (FP32) accesses.
+template <typename T>
+using Pair = typename std::conditional<is_fp64<T>(), double2, float2>::type;
+
+template <typename T>
+__device__ __forceinline__ void lam_load(const T* __restrict__ lam, int64_t i, T lx[3], T lu[3]) {
+  const Pair<T>* p = reinterpret_cast<const Pair<T>*>(lam + 6 * i);
+  const Pair<T> a = p[0], b = p[1], c = p[2];
+  lx[0] = a.x;
+  lx[1] = a.y;
+  lx[2] = b.x;
+  lu[0] = b.y;
+  lu[1] = c.x;
+  lu[2] = c.y;
+}
+
+template <typename T>
+__device__ __forceinline__ void lam_store(T* __restrict__ lam, int64_t i, const T lx[3], const T lu[3]) {
+  Pair<T>* p = reinterpret_cast<Pair<T>*>(lam + 6 * i);
+  Pair<T> a, b, c;
+  a.x = lx[0];
+  a.y = lx[1];
+  b.x = lx[2];
+  b.y = lu[0];
+  c.x = lu[1];
+  c.y = lu[2];
+  p[0] = a;
+  p[1] = b;
+  p[2] = c;
+}
+
 // Reverse of one step with the packets held in tile order: tile t's packets are entries
-// [offsets[t*cells_per_tile], offsets[(t+1)*cells_per_tile]) of the slab and of lam_x,
-// lam_u (a counting sort of a recorded state of this step or of one up to a few steps
+// [offsets[t*cells_per_tile], offsets[(t+1)*cells_per_tile]) of the slab and of the
+// adjoint records lam (a counting sort of a recorded state of this step or of one up to a few steps
 // earlier).  Each workgroup takes one part of one tile's packets, stages the fields of
 // the tile plus a halo of `halo` cells in LDS, accumulates dL/dE, dL/dB there and adds
 // the region to the grid with one atomic per node and component.  A packet whose
@@ -381,8 +415,7 @@ __global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> 
                                                                      const int32_t* __restrict__ offsets, Tiling tl,
                                                                      int halo, int parts, int32_t* __restrict__ spill,
                                                                      int parity,
-                                                                     T* __restrict__ lam_x,
-                                                                     T* __restrict__ lam_u, const T* __restrict__ E,
+                                                                     T* __restrict__ lam, const T* __restrict__ E,
                                                                      const T* __restrict__ B,
                                                                      const double* __restrict__ lam_dM,
                                                                      const double* __restrict__ lam_dE,
@@ -438,11 +471,8 @@ __global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> 
   auto load_in = [&](int64_t i, In& p) {
     load_position(slab, i, k, p.home, p.f);
     #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      p.u0[d] = slab.u[d * np + i];
-      p.lx[d] = lam_x[d * np + i];
-      p.lu[d] = lam_u[d * np + i];
-    }
+    for (int d = 0; d < 3; ++d) p.u0[d] = slab.u[d * np + i];
+    lam_load(lam, i, p.lx, p.lu);
   };
   // each thread's packets in turn; without the exchange adjoint (the variant with room
   // in its registers) the next packet's inputs load while the current one is reversed
@@ -473,11 +503,7 @@ __global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> 
       spill[2 + atomicAdd(&spill[parity], 1)] = (int32_t)i;
     } else {
       packet_backward<M, T>(acc, hu, cur.f, cur.u0, cur.lx, cur.lu, k);
-      #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        lam_x[d * np + i] = cur.lx[d];
-        lam_u[d * np + i] = cur.lu[d];
-      }
+      lam_store(lam, i, cur.lx, cur.lu);
     }
     if constexpr (kAhead) cur = nxt;
   }
@@ -501,8 +527,8 @@ __global__ void __launch_bounds__(kBlock) step_backward_tiled_kernel(Packets<T> 
 // on the same stream.
 template <int M, typename T>
 __global__ void __launch_bounds__(kBlock) step_backward_list_kernel(Packets<T> slab, int32_t* __restrict__ spill,
-                                                                    int parity, T* __restrict__ lam_x,
-                                                                    T* __restrict__ lam_u, const T* __restrict__ E,
+                                                                    int parity, T* __restrict__ lam,
+                                                                    const T* __restrict__ E,
                                                                     const T* __restrict__ B,
                                                                     const double* __restrict__ lam_dM,
                                                                     const double* __restrict__ lam_dE,
@@ -519,14 +545,10 @@ __global__ void __launch_bounds__(kBlock) step_backward_list_kernel(Packets<T> s
     load_position(slab, i, k, home, f);
     #pragma unroll
     for (int d = 0; d < 3; ++d) u0a[d] = slab.u[d * np + i];
-    T lx[3] = {lam_x[i], lam_x[np + i], lam_x[2 * np + i]};
-    T lu[3] = {lam_u[i], lam_u[np + i], lam_u[2 * np + i]};
+    T lx[3], lu[3];
+    lam_load(lam, i, lx, lu);
     packet_backward<M, T>(gacc, home, f, u0a, lx, lu, k);
-    #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      lam_x[d * np + i] = lx[d];
-      lam_u[d * np + i] = lu[d];
-    }
+    lam_store(lam, i, lx, lu);
   }
 }
 
@@ -599,17 +621,44 @@ __global__ void __launch_bounds__(kBlock) moments_backward_kernel(Packets<T> P, 
   }
 }
 
-// rows x np arrays: dst[r][j] = src[r][idx[j]] (gather) or dst[r][idx[j]] = src[r][j]
-// (scatter); idx is a permutation of 0..np-1.
+// Adjoint records between orders: dst[j] = src[idx[j]], or dst[idx[j]] = src[j] with
+// scatter; idx is a permutation of 0..np-1.
 template <typename T>
-__global__ void permute_rows_kernel(const T* __restrict__ src, T* __restrict__ dst, const int32_t* __restrict__ idx,
-                                    int64_t np, int rows, bool scatter) {
+__global__ void permute_records_kernel(const T* __restrict__ src, T* __restrict__ dst,
+                                       const int32_t* __restrict__ idx, int64_t np, bool scatter) {
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < np; j += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = idx[j];
-    if (i < 0 || i >= np) continue;  // not a permutation entry (the arrays are left alone there)
-    for (int r = 0; r < rows; ++r) {
-      if (scatter) dst[r * np + i] = src[r * np + j];
-      else dst[r * np + j] = src[r * np + i];
+    if (i < 0 || i >= np) continue;  // not a permutation entry (the record is left alone)
+    const Pair<T>* a = reinterpret_cast<const Pair<T>*>(src + 6 * (scatter ? j : i));
+    Pair<T>* b = reinterpret_cast<Pair<T>*>(dst + 6 * (scatter ? i : j));
+    const Pair<T> v0 = a[0], v1 = a[1], v2 = a[2];
+    b[0] = v0;
+    b[1] = v1;
+    b[2] = v2;
+  }
+}
+
+// The caller's adjoints (lam_x [3][np], lam_u [3][np]) and records in the same order,
+// one way or the other (to_rows).
+template <typename T>
+__global__ void records_rows_kernel(T* __restrict__ lam_x, T* __restrict__ lam_u, T* __restrict__ rec, int64_t np,
+                                    bool to_rows) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
+    T lx[3], lu[3];
+    if (to_rows) {
+      lam_load(rec, i, lx, lu);
+      #pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        lam_x[d * np + i] = lx[d];
+        lam_u[d * np + i] = lu[d];
+      }
+    } else {
+      #pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        lx[d] = lam_x[d * np + i];
+        lu[d] = lam_u[d * np + i];
+      }
+      lam_store(rec, i, lx, lu);
     }
   }
 }
@@ -634,11 +683,25 @@ __global__ void unsort_kernel(Packets<T> S, Packets<T> P) {
 }  // namespace
 
 template <typename T>
-hipError_t launch_permute_rows(const T* src, T* dst, const int32_t* idx, int64_t np, int rows, bool scatter,
-                               hipStream_t s) {
+hipError_t launch_permute_records(const T* src, T* dst, const int32_t* idx, int64_t np, hipStream_t s) {
   if (np > 0)
-    hipLaunchKernelGGL(permute_rows_kernel<T>, dim3(grid_for(np)), dim3(kBlock), 0, s, src, dst, idx, np, rows,
-                       scatter);
+    hipLaunchKernelGGL(permute_records_kernel<T>, dim3(grid_for(np)), dim3(kBlock), 0, s, src, dst, idx, np, false);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_records_rows(T* lam_x, T* lam_u, T* rec, T* tmp, const int32_t* order, int64_t np, bool to_rows,
+                               hipStream_t s) {
+  if (np <= 0) return hipSuccess;
+  // through records in the caller's order (contiguous transposes; the permutation then
+  // moves whole records)
+  if (to_rows) {
+    hipLaunchKernelGGL(permute_records_kernel<T>, dim3(grid_for(np)), dim3(kBlock), 0, s, rec, tmp, order, np, true);
+    hipLaunchKernelGGL(records_rows_kernel<T>, dim3(grid_for(np)), dim3(kBlock), 0, s, lam_x, lam_u, tmp, np, true);
+  } else {
+    hipLaunchKernelGGL(records_rows_kernel<T>, dim3(grid_for(np)), dim3(kBlock), 0, s, lam_x, lam_u, tmp, np, false);
+    hipLaunchKernelGGL(permute_records_kernel<T>, dim3(grid_for(np)), dim3(kBlock), 0, s, tmp, rec, order, np, false);
+  }
   return hipGetLastError();
 }
 
@@ -677,8 +740,8 @@ hipError_t launch_spill_clear(int32_t* spill, hipStream_t s) {
 
 template <typename T>
 hipError_t launch_step_backward_tiled(int shape, const Packets<T>& slab, const int32_t* offsets,
-                                      const Tiling& t, int halo, int32_t* spill, int parity, T* lam_x, T* lam_u,
-                                      const T* E, const T* B, const double* lam_dM, const double* lam_dE, double* gE,
+                                      const Tiling& t, int halo, int32_t* spill, int parity, T* lam, const T* E,
+                                      const T* B, const double* lam_dM, const double* lam_dE, double* gE,
                                       double* gB, const RunConsts& k, hipStream_t s) {
   if (!step_backward_tiled_fits(t, halo) || (parity != 0 && parity != 1)) return hipErrorInvalidValue;
   // one workgroup per tile once the tiles alone give each of the 256 CUs two workgroups
@@ -696,31 +759,31 @@ hipError_t launch_step_backward_tiled(int shape, const Packets<T>& slab, const i
   if (shape == kShapeCIC) {
     if (lam_dM)
       hipLaunchKernelGGL((step_backward_tiled_kernel<2, T, true>), grid, dim3(kBlock), 0, s, slab, offsets, t, halo,
-                         parts, spill, parity, lam_x, lam_u, E, B, lam_dM, lam_dE, gE, gB, k);
+                         parts, spill, parity, lam, E, B, lam_dM, lam_dE, gE, gB, k);
     else
       hipLaunchKernelGGL((step_backward_tiled_kernel<2, T, false>), grid, dim3(kBlock), 0, s, slab, offsets, t,
-                         halo, parts, spill, parity, lam_x, lam_u, E, B, lam_dM, lam_dE, gE, gB, k);
+                         halo, parts, spill, parity, lam, E, B, lam_dM, lam_dE, gE, gB, k);
   } else {
     hipLaunchKernelGGL((step_backward_tiled_kernel<3, T, true>), grid, dim3(kBlock), 0, s, slab, offsets, t, halo,
-                       parts, spill, parity, lam_x, lam_u, E, B, lam_dM, lam_dE, gE, gB, k);
+                       parts, spill, parity, lam, E, B, lam_dM, lam_dE, gE, gB, k);
   }
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_step_backward_spilled(int shape, const Packets<T>& slab, int32_t* spill, int parity, T* lam_x,
-                                        T* lam_u, const T* E, const T* B, const double* lam_dM, const double* lam_dE,
+hipError_t launch_step_backward_spilled(int shape, const Packets<T>& slab, int32_t* spill, int parity, T* lam,
+                                        const T* E, const T* B, const double* lam_dM, const double* lam_dE,
                                         double* gE, double* gB, const RunConsts& k, hipStream_t s) {
   if (parity != 0 && parity != 1) return hipErrorInvalidValue;
   // strays are rare (packets that outran the staged halo since their block's sort): a
   // small grid keeps the launch cheap when there are none
   const dim3 lgrid((unsigned)(grid_for(slab.np) < 32 ? grid_for(slab.np) : 32));
   if (shape == kShapeCIC)
-    hipLaunchKernelGGL((step_backward_list_kernel<2, T>), lgrid, dim3(kBlock), 0, s, slab, spill, parity, lam_x,
-                       lam_u, E, B, lam_dM, lam_dE, gE, gB, k);
+    hipLaunchKernelGGL((step_backward_list_kernel<2, T>), lgrid, dim3(kBlock), 0, s, slab, spill, parity, lam, E,
+                       B, lam_dM, lam_dE, gE, gB, k);
   else
-    hipLaunchKernelGGL((step_backward_list_kernel<3, T>), lgrid, dim3(kBlock), 0, s, slab, spill, parity, lam_x,
-                       lam_u, E, B, lam_dM, lam_dE, gE, gB, k);
+    hipLaunchKernelGGL((step_backward_list_kernel<3, T>), lgrid, dim3(kBlock), 0, s, slab, spill, parity, lam, E,
+                       B, lam_dM, lam_dE, gE, gB, k);
   return hipGetLastError();
 }
 
@@ -742,13 +805,14 @@ hipError_t launch_moments_backward(int shape, const Packets<T>& P, const double*
                                               hipStream_t);                                                    \
   template hipError_t launch_moments_backward<T>(int, const Packets<T>&, const double*, const double*,         \
                                                  const double*, T*, T*, const RunConsts&, hipStream_t);        \
-  template hipError_t launch_permute_rows<T>(const T*, T*, const int32_t*, int64_t, int, bool, hipStream_t);   \
+  template hipError_t launch_permute_records<T>(const T*, T*, const int32_t*, int64_t, hipStream_t);            \
+  template hipError_t launch_records_rows<T>(T*, T*, T*, T*, const int32_t*, int64_t, bool, hipStream_t);       \
   template hipError_t launch_unsort<T>(const Packets<T>&, const Packets<T>&, hipStream_t);                      \
   template hipError_t launch_step_backward_tiled<T>(int, const Packets<T>&, const int32_t*,                        \
-                                                    const Tiling&, int, int32_t*, int, T*, T*, const T*, const T*, \
+                                                    const Tiling&, int, int32_t*, int, T*, const T*, const T*,     \
                                                     const double*, const double*, double*, double*,                \
                                                     const RunConsts&, hipStream_t);                                \
-  template hipError_t launch_step_backward_spilled<T>(int, const Packets<T>&, int32_t*, int, T*, T*, const T*,     \
+  template hipError_t launch_step_backward_spilled<T>(int, const Packets<T>&, int32_t*, int, T*, const T*,         \
                                                       const T*, const double*, const double*, double*, double*,    \
                                                       const RunConsts&, hipStream_t);
 

@@ -51,18 +51,23 @@ hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_spill_clear(int32_t* spill, hipStream_t s);
 template <typename T>
 hipError_t launch_step_backward_tiled(int shape, const Packets<T>& slab, const int32_t* offsets,
-                                      const Tiling& t, int halo, int32_t* spill, int parity, T* lam_x, T* lam_u,
-                                      const T* E, const T* B, const double* lam_dM, const double* lam_dE, double* gE,
+                                      const Tiling& t, int halo, int32_t* spill, int parity, T* lam, const T* E,
+                                      const T* B, const double* lam_dM, const double* lam_dE, double* gE,
                                       double* gB, const RunConsts& k, hipStream_t s);
 template <typename T>
-hipError_t launch_step_backward_spilled(int shape, const Packets<T>& slab, int32_t* spill, int parity, T* lam_x,
-                                        T* lam_u, const T* E, const T* B, const double* lam_dM, const double* lam_dE,
+hipError_t launch_step_backward_spilled(int shape, const Packets<T>& slab, int32_t* spill, int parity, T* lam,
+                                        const T* E, const T* B, const double* lam_dM, const double* lam_dE,
                                         double* gE, double* gB, const RunConsts& k, hipStream_t s);
 
-// rows x np arrays (row stride np): dst[r][j] = src[r][idx[j]], or with scatter
-// dst[r][idx[j]] = src[r][j]; idx is a permutation of 0..np-1.
+// The tile-ordered sweeps hold the adjoints as records of six values per packet (dL/dx
+// then dL/du, 6 * np values).  launch_permute_records: dst[j] = src[idx[j]] (records;
+// idx a permutation of 0..np-1).  launch_records_rows: the caller's lam_x [3][np],
+// lam_u [3][np] into records in a tile order, rec[j] = packet order[j], or back into
+// the caller's arrays with to_rows; tmp holds 6 * np values of work space.
 template <typename T>
-hipError_t launch_permute_rows(const T* src, T* dst, const int32_t* idx, int64_t np, int rows, bool scatter,
+hipError_t launch_permute_records(const T* src, T* dst, const int32_t* idx, int64_t np, hipStream_t s);
+template <typename T>
+hipError_t launch_records_rows(T* lam_x, T* lam_u, T* rec, T* tmp, const int32_t* order, int64_t np, bool to_rows,
                                hipStream_t s);
 
 // Packets held in tile order back into the caller's arrays: P[S.id[j]] = S[j]

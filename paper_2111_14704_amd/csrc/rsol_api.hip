@@ -612,17 +612,16 @@ int backward_tiled(rsol_ctx* h, int32_t nsteps, const char* states, T* lam_x, T*
   T* L1 = adj_lam<T>(h, 1);
   auto first_slab = [&](int b) { return states + (size_t)b * kAdjBlock * sl.total; };
   int block = (nsteps - 1) / kAdjBlock;
-  // the caller's adjoints into the last block's order
+  // the caller's adjoints into records in the last block's order
   const int32_t* order = (const int32_t*)(first_slab(block) + sl.order);
-  RSOL_HIP(h, launch_permute_rows<T>(lam_x, L0, order, np, 3, false, h->stream), "adjoint gather");
-  RSOL_HIP(h, launch_permute_rows<T>(lam_u, L0 + 3 * np, order, np, 3, false, h->stream), "adjoint gather");
+  RSOL_HIP(h, launch_records_rows<T>(lam_x, lam_u, L0, L1, order, np, false, h->stream), "adjoint gather");
   RSOL_HIP(h, launch_spill_clear(h->spill, h->stream), "spill clear");
   for (int32_t n = nsteps - 1; n >= 0; --n) {
     const int b = n / kAdjBlock;
     if (b != block) {
       // from block b+1's order into block b's: position j of block b sits at next[j]
       const int32_t* next = (const int32_t*)(first_slab(b) + sl.next);
-      RSOL_HIP(h, launch_permute_rows<T>(L0, L1, next, np, 6, false, h->stream), "adjoint reorder");
+      RSOL_HIP(h, launch_permute_records<T>(L0, L1, next, np, h->stream), "adjoint reorder");
       T* t = L0;
       L0 = L1;
       L1 = t;
@@ -633,16 +632,15 @@ int backward_tiled(rsol_ctx* h, int32_t nsteps, const char* states, T* lam_x, T*
     const int parity = n & 1;
     const auto pr = timed_begin(h);
     RSOL_HIP(h, launch_step_backward_tiled<T>(h->p.shape, slab, offsets, h->tiling, kAdjHalo, h->spill, parity, L0,
-                                              L0 + 3 * np, field_E<T>(h), field_B<T>(h), lam_dM, lam_dE, gE, gB, k,
-                                              h->stream), "step backward");
+                                              field_E<T>(h), field_B<T>(h), lam_dM, lam_dE, gE, gB, k, h->stream),
+             "step backward");
     timed_end(h, pr, false);
-    RSOL_HIP(h, launch_step_backward_spilled<T>(h->p.shape, slab, h->spill, parity, L0, L0 + 3 * np, field_E<T>(h),
+    RSOL_HIP(h, launch_step_backward_spilled<T>(h->p.shape, slab, h->spill, parity, L0, field_E<T>(h),
                                                 field_B<T>(h), lam_dM, lam_dE, gE, gB, k, h->stream),
              "step backward spilled");
   }
   const int32_t* order0 = (const int32_t*)(states + sl.order);
-  RSOL_HIP(h, launch_permute_rows<T>(L0, lam_x, order0, np, 3, true, h->stream), "adjoint scatter");
-  RSOL_HIP(h, launch_permute_rows<T>(L0 + 3 * np, lam_u, order0, np, 3, true, h->stream), "adjoint scatter");
+  RSOL_HIP(h, launch_records_rows<T>(lam_x, lam_u, L0, L1, order0, np, true, h->stream), "adjoint scatter");
   return RSOL_OK;
 }
 
