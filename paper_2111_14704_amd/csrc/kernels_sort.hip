@@ -53,6 +53,14 @@ __device__ __forceinline__ int aggregated_slot(int32_t* counters, int key) {
   return key >= 0 ? base + (lane - start) : -1;
 }
 
+// Chunk of blockDim.x consecutive items for this workgroup: consecutive workgroups go
+// to different XCDs, so when the grid is a multiple of 8 each XCD takes a contiguous
+// range of chunks and the scattered accesses of its workgroups meet in its own L2.
+__device__ __forceinline__ int64_t xcd_chunk() {
+  const unsigned g = gridDim.x, b = blockIdx.x;
+  return (g & 7u) == 0 ? (int64_t)(b & 7u) * (g >> 3) + (b >> 3) : (int64_t)b;
+}
+
 __device__ __forceinline__ int tile_key(const int home[3], const Tiling& t) {
   const int tx = home[0] / t.tx, ty = home[1] / t.ty, tz = home[2] / t.tz;
   const int lx = home[0] - tx * t.tx, ly = home[1] - ty * t.ty, lz = home[2] - tz * t.tz;
@@ -217,7 +225,7 @@ __global__ void __launch_bounds__(kBlock) place_kernel(int64_t np, Tiling t, con
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int cpt = t.cells_per_tile;
   const int tw = table_words(t);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += stride) {
+  for (int64_t i = xcd_chunk() * blockDim.x + threadIdx.x; i < np; i += stride) {
     const int key = keys[i];
     const int rank = ranks[i];
     const int tile = key / cpt;
@@ -247,7 +255,7 @@ __global__ void __launch_bounds__(kBlock) gather_kernel(Packets<T> src, Packets<
                                                         int32_t* __restrict__ order_out) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t np = src.np;
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < np; j += stride) {
+  for (int64_t j = xcd_chunk() * blockDim.x + threadIdx.x; j < np; j += stride) {
     const int64_t i = inv[j];
     if (i < 0 || i >= np) continue;  // not a placed position (only a corrupt sort leaves one)
     if (dst.u) {
