@@ -621,14 +621,6 @@ __global__ void __launch_bounds__(kBlock) moments_backward_kernel(Packets<T> P, 
   }
 }
 
-// Chunk of blockDim.x consecutive items for this workgroup: consecutive workgroups go
-// to different XCDs, so when the grid is a multiple of 8 each XCD takes a contiguous
-// range of chunks and the scattered accesses of its workgroups meet in its own L2.
-__device__ __forceinline__ int64_t xcd_chunk() {
-  const unsigned g = gridDim.x, b = blockIdx.x;
-  return (g & 7u) == 0 ? (int64_t)(b & 7u) * (g >> 3) + (b >> 3) : (int64_t)b;
-}
-
 // Adjoint records between orders: dst[j] = src[idx[j]], or dst[idx[j]] = src[j] with
 // scatter; idx is a permutation of 0..np-1.
 template <typename T>

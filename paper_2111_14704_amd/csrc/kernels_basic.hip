@@ -536,8 +536,9 @@ __global__ void __launch_bounds__(kBlock) step_record_tiled_kernel(Packets<T> P,
                                                                    int halo, int parts, const T* __restrict__ E,
                                                                    const T* __restrict__ B, RunConsts k) {
   __shared__ T Fs[6 * kAdjRegion];
-  const int64_t tile = blockIdx.x / parts;
-  const int part = blockIdx.x - (int)(tile * parts);
+  const int64_t wg = xcd_chunk();  // neighbouring tiles on one XCD
+  const int64_t tile = wg / parts;
+  const int part = (int)(wg - tile * parts);
   const int ttx = (int)(tile % tl.ntx), tty = (int)((tile / tl.ntx) % tl.nty), ttz = (int)(tile / ((int64_t)tl.ntx * tl.nty));
   const int t0[3] = {ttx * tl.tx, tty * tl.ty, ttz * tl.tz};
   const int o[3] = {t0[0] - halo, t0[1] - halo, t0[2] - halo};

@@ -53,14 +53,6 @@ __device__ __forceinline__ int aggregated_slot(int32_t* counters, int key) {
   return key >= 0 ? base + (lane - start) : -1;
 }
 
-// Chunk of blockDim.x consecutive items for this workgroup: consecutive workgroups go
-// to different XCDs, so when the grid is a multiple of 8 each XCD takes a contiguous
-// range of chunks and the scattered accesses of its workgroups meet in its own L2.
-__device__ __forceinline__ int64_t xcd_chunk() {
-  const unsigned g = gridDim.x, b = blockIdx.x;
-  return (g & 7u) == 0 ? (int64_t)(b & 7u) * (g >> 3) + (b >> 3) : (int64_t)b;
-}
-
 __device__ __forceinline__ int tile_key(const int home[3], const Tiling& t) {
   const int tx = home[0] / t.tx, ty = home[1] / t.ty, tz = home[2] / t.tz;
   const int lx = home[0] - tx * t.tx, ly = home[1] - ty * t.ty, lz = home[2] - tz * t.tz;

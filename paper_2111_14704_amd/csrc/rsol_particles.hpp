@@ -63,6 +63,14 @@ __device__ __forceinline__ void load_position(const Packets<T>& P, int64_t i, co
   }
 }
 
+// Chunk of blockDim.x consecutive items for this workgroup: consecutive workgroups go
+// to different XCDs, so when the grid is a multiple of 8 each XCD takes a contiguous
+// range of chunks and the scattered accesses of its workgroups meet in its own L2.
+__device__ __forceinline__ int64_t xcd_chunk() {
+  const unsigned g = gridDim.x, b = blockIdx.x;
+  return (g & 7u) == 0 ? (int64_t)(b & 7u) * (g >> 3) + (b >> 3) : (int64_t)b;
+}
+
 // Copy packet i's state into a state slab: FP64 [6][np] doubles (x, u); FP32 [7][np]
 // 4-byte words (cell, off, u).
 template <typename T>
