@@ -664,11 +664,12 @@ __global__ void records_rows_kernel(T* __restrict__ lam_x, T* __restrict__ lam_u
 }
 
 // Packets in tile order back to the caller's order: P[S.id[j]] = S[j] (positions and
-// momenta; the caller's ids stay).
+// momenta; the caller's ids stay).  A caller order close to tile order (as rsol_sort
+// leaves it) keeps each XCD's writes within a few tiles' range.
 template <typename T>
 __global__ void unsort_kernel(Packets<T> S, Packets<T> P) {
   const int64_t np = P.np;
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < np; j += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t j = xcd_chunk() * blockDim.x + threadIdx.x; j < np; j += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = S.id[j];
     #pragma unroll
     for (int d = 0; d < 3; ++d) {
