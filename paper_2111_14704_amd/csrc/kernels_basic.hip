@@ -248,10 +248,11 @@ __global__ void deposit_kernel(Packets<T> P, const T* __restrict__ payload, doub
 }
 
 // A7: x^{n+1} = x^n + c_tilde dt u/gamma with periodic wrap (FP64), or the
-// cell + offset carry of the precision form (FP32).
+// cell + offset carry of the precision form (FP32); the position is read from P and the
+// new one written into Q (the same arrays for an update in place).
 template <typename T>
-__device__ __forceinline__ void drift_one(const Packets<T>& P, int64_t i, T ux, T uy, T uz,
-                                          const RunConsts& k) {
+__device__ __forceinline__ void drift_into(const Packets<T>& P, const Packets<T>& Q, int64_t i, T ux, T uy, T uz,
+                                           const RunConsts& k) {
   const int64_t np = P.np;
   bool fin;
   const T s = drift_scale<T>(ux, uy, uz, is_fp64<T>() ? (T)k.cdt : (T)k.cdt_dx, &fin);
@@ -263,7 +264,7 @@ __device__ __forceinline__ void drift_one(const Packets<T>& P, int64_t i, T ux, 
     for (int d = 0; d < 3; ++d) {
       const double step = s * u3[d];
       bad |= fabs(step) > k.max_step * k.dx;
-      P.x[d * np + i] = wrap_coord(P.x[d * np + i] + step, L[d]);
+      Q.x[d * np + i] = wrap_coord(P.x[d * np + i] + step, L[d]);
     }
   } else {
     const int n[3] = {k.nx, k.ny, k.nz};
@@ -288,11 +289,16 @@ __device__ __forceinline__ void drift_one(const Packets<T>& P, int64_t i, T ux, 
         hd += 1;
       }
       h[d] = wrap_index(hd, n[d]);
-      P.off[d * np + i] = f;
+      Q.off[d * np + i] = f;
     }
-    P.cell[i] = h[0] + k.nx * (h[1] + k.ny * h[2]);
+    Q.cell[i] = h[0] + k.nx * (h[1] + k.ny * h[2]);
   }
   if (bad) set_status(k.status, fin ? ERR_COURANT : ERR_NAN);
+}
+
+template <typename T>
+__device__ __forceinline__ void drift_one(const Packets<T>& P, int64_t i, T ux, T uy, T uz, const RunConsts& k) {
+  drift_into<T>(P, P, i, ux, uy, uz, k);
 }
 
 template <typename T>
@@ -526,12 +532,13 @@ __global__ void __launch_bounds__(kBlock) step_global_kernel(Packets<T> P, const
 // Recording step of the differentiation form on packets held in tile order (positions
 // [offsets[t*cells_per_tile], offsets[(t+1)*cells_per_tile]) belong to tile t): one
 // workgroup per part of a tile stages E and B of the tile plus a `halo`-cell border in
-// LDS; each packet's starting state goes to the state slab `rec` (when given) at its own
-// position, then the gather (the weights and summation order of step_global_kernel, so the
-// trajectory is the same to the bit), the Boris kick and the drift.  A packet whose
+// LDS; each packet's state is read from P and, after the gather (the weights and
+// summation order of step_global_kernel, so the trajectory is the same to the bit), the
+// Boris kick and the drift, written into Q at the same position (Q = P: in place; a
+// recording reads one step's state slab and writes the next).  A packet whose
 // stencil has left the staged region since the sort gathers from the grid instead.
 template <int M, typename T>
-__global__ void __launch_bounds__(kBlock) step_record_tiled_kernel(Packets<T> P, void* __restrict__ rec,
+__global__ void __launch_bounds__(kBlock) step_record_tiled_kernel(Packets<T> P, Packets<T> Q,
                                                                    const int32_t* __restrict__ offsets, Tiling tl,
                                                                    int halo, int parts, const T* __restrict__ E,
                                                                    const T* __restrict__ B, RunConsts k) {
@@ -570,7 +577,6 @@ __global__ void __launch_bounds__(kBlock) step_record_tiled_kernel(Packets<T> P,
     T f[3];
     load_position(P, j, k, home, f);
     const T ux = P.u[j], uy = P.u[np + j], uz = P.u[2 * np + j];
-    if (rec) store_state<T>(rec, P, j);
     // home in the tile's unwrapped frame; the stencil spans home-1 .. home+1
     bool inside = true;
     int hu[3];
@@ -630,10 +636,10 @@ __global__ void __launch_bounds__(kBlock) step_record_tiled_kernel(Packets<T> P,
     }
     const Kick<T> q = kick<kPushBoris, T>(ux, uy, uz, e[0], e[1], e[2], b[0], b[1], b[2], h, hb);
     const T nux = ux + q.dux, nuy = uy + q.duy, nuz = uz + q.duz;
-    P.u[j] = nux;
-    P.u[np + j] = nuy;
-    P.u[2 * np + j] = nuz;
-    drift_one<T>(P, j, nux, nuy, nuz, k);
+    Q.u[j] = nux;
+    Q.u[np + j] = nuy;
+    Q.u[2 * np + j] = nuz;
+    drift_into<T>(P, Q, j, nux, nuy, nuz, k);
   }
 }
 
@@ -802,7 +808,7 @@ bool step_record_tiled_fits(const Tiling& t, int halo) {
 }
 
 template <typename T>
-hipError_t launch_step_record_tiled(int shape, const Packets<T>& P, void* slab, const int32_t* offsets,
+hipError_t launch_step_record_tiled(int shape, const Packets<T>& P, const Packets<T>& Q, const int32_t* offsets,
                                     const Tiling& t, int halo, const T* E, const T* B, const RunConsts& k,
                                     hipStream_t s) {
   if (!step_record_tiled_fits(t, halo)) return hipErrorInvalidValue;
@@ -812,11 +818,11 @@ hipError_t launch_step_record_tiled(int shape, const Packets<T>& P, void* slab, 
   parts = parts < 1 ? 1 : (parts > 4 ? 4 : parts);
   const dim3 grid((unsigned)(ntiles * parts));
   if (shape == kShapeCIC)
-    hipLaunchKernelGGL((step_record_tiled_kernel<2, T>), grid, dim3(kBlock), 0, s, P, slab, offsets, t, halo, parts,
-                       E, B, k);
+    hipLaunchKernelGGL((step_record_tiled_kernel<2, T>), grid, dim3(kBlock), 0, s, P, Q, offsets, t, halo, parts, E,
+                       B, k);
   else
-    hipLaunchKernelGGL((step_record_tiled_kernel<3, T>), grid, dim3(kBlock), 0, s, P, slab, offsets, t, halo, parts,
-                       E, B, k);
+    hipLaunchKernelGGL((step_record_tiled_kernel<3, T>), grid, dim3(kBlock), 0, s, P, Q, offsets, t, halo, parts, E,
+                       B, k);
   return hipGetLastError();
 }
 
@@ -835,8 +841,9 @@ hipError_t launch_step_record_tiled(int shape, const Packets<T>& P, void* slab, 
                                             double*, const RunConsts&, hipStream_t);                           \
   template hipError_t launch_step_record<T>(int, const Packets<T>&, const T*, const T*, void*, const RunConsts&, \
                                             hipStream_t);                                                      \
-  template hipError_t launch_step_record_tiled<T>(int, const Packets<T>&, void*, const int32_t*, const Tiling&, \
-                                                  int, const T*, const T*, const RunConsts&, hipStream_t);     \
+  template hipError_t launch_step_record_tiled<T>(int, const Packets<T>&, const Packets<T>&, const int32_t*,    \
+                                                  const Tiling&, int, const T*, const T*, const RunConsts&,    \
+                                                  hipStream_t);                                                \
   template hipError_t launch_moments_tiled<T>(int, const Packets<T>&, const int32_t*, const int32_t*,          \
                                               const Tiling&, double*, double*, double*, const RunConsts&,      \
                                               hipStream_t);

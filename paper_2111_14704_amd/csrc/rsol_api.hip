@@ -552,36 +552,60 @@ int record_global(rsol_ctx* h, int32_t nsteps, char* states, const RunConsts& k)
 
 // Advance nsteps steps on tile-sorted copies (sorted every kAdjBlock steps) and return
 // the packets to the caller's arrays in their order; with states, record every step's
-// starting state and each block's ordering there.
+// starting state and each block's ordering there.  When recording, a step reads its
+// starting state from its own slab (where the sort or the previous step put it) and
+// writes the next state into the next step's slab, or into the scratch copy `cur` at
+// the end of a block (the next block's sort reads it) and of the call, so no step copies
+// its state separately; without states the steps advance `cur` in place.
 template <typename T>
 int record_tiled(rsol_ctx* h, int32_t nsteps, char* states, const RunConsts& k) {
   const SlabLayout sl = slab_layout(h);
   Packets<T> cur = perm_packets<T>(h), nxt = adj_packets2<T>(h);
+  auto slab_of = [&](int32_t n) { return states + (size_t)n * sl.total; };
+  // the state slab of step n as packet arrays carrying the current block's ids
+  auto slab_view = [&](int32_t n) {
+    Packets<T> P = slab_packets<T>(h, slab_of(n) + sl.state);
+    P.id = cur.id;
+    return P;
+  };
   RSOL_HIP(h, launch_iota(h->iota, h->np, h->stream), "iota");
   for (int32_t n = 0; n < nsteps; ++n) {
-    char* slab = states ? states + (size_t)n * sl.total : nullptr;
     if (n % kAdjBlock == 0) {
       // the sort also writes the block's order and bin offsets into the step's slab
-      int32_t* order = slab ? (int32_t*)(slab + sl.order) : nullptr;
-      int32_t* offs = slab ? (int32_t*)(slab + sl.offsets) : nullptr;
+      int32_t* order = states ? (int32_t*)(slab_of(n) + sl.order) : nullptr;
+      int32_t* offs = states ? (int32_t*)(slab_of(n) + sl.offsets) : nullptr;
+      int32_t* pos = (states && n > 0) ? (int32_t*)(slab_of(n - kAdjBlock) + sl.next) : nullptr;
+      Packets<T> src = cur;
       if (n == 0) {
-        Packets<T> src = caller_packets<T>(h);
+        src = caller_packets<T>(h);
         src.id = h->iota;
         src.w = nullptr;
-        RSOL_HIP(h, launch_sort<T>(src, cur, k, h->tiling, h->sort_ints, h->stream, nullptr, order, offs),
-                 "record sort");
+      }
+      Packets<T> dst = nxt;
+      if (states) {
+        dst = slab_packets<T>(h, slab_of(n) + sl.state);
+        dst.id = nxt.id;
+      }
+      RSOL_HIP(h, launch_sort<T>(src, dst, k, h->tiling, h->sort_ints, h->stream, pos, order, offs), "record sort");
+      if (states) {
+        // the block's ids now sit in nxt.id; cur keeps its arrays for the block's last step
+        int32_t* t = cur.id;
+        cur.id = nxt.id;
+        nxt.id = t;
       } else {
-        int32_t* pos = states ? (int32_t*)(states + (size_t)(n - kAdjBlock) * sl.total + sl.next) : nullptr;
-        RSOL_HIP(h, launch_sort<T>(cur, nxt, k, h->tiling, h->sort_ints, h->stream, pos, order, offs),
-                 "record sort");
         const Packets<T> t = cur;
         cur = nxt;
         nxt = t;
       }
     }
+    Packets<T> in = cur, out = cur;
+    if (states) {
+      in = slab_view(n);
+      if (n + 1 < nsteps && (n + 1) % kAdjBlock != 0) out = slab_view(n + 1);
+    }
     auto ev = timed_begin(h);
-    RSOL_HIP(h, launch_step_record_tiled<T>(h->p.shape, cur, slab ? slab + sl.state : nullptr, h->sort_ints,
-                                            h->tiling, kAdjHalo, field_E<T>(h), field_B<T>(h), k, h->stream),
+    RSOL_HIP(h, launch_step_record_tiled<T>(h->p.shape, in, out, h->sort_ints, h->tiling, kAdjHalo, field_E<T>(h),
+                                            field_B<T>(h), k, h->stream),
              "record step");
     timed_end(h, ev, false);
   }

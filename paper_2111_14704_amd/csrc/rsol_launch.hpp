@@ -91,11 +91,12 @@ template <typename T>
 hipError_t launch_step_record(int shape, const Packets<T>& P, const T* E, const T* B, void* slab,
                               const RunConsts& k, hipStream_t s);
 
-// The same recording step with the packets held in tile order (tile t's packets at
+// The same step with the packets held in tile order (tile t's packets at
 // [offsets[t*cells_per_tile], offsets[(t+1)*cells_per_tile]) of P, from a counting sort
 // at most a few steps old): E and B of each tile plus a `halo`-cell border are staged
-// in LDS, so gathers do not touch the grid; slab may be NULL (the step without
-// recording).  Needs step_record_tiled_fits(t, halo).
+// in LDS, so gathers do not touch the grid.  The state is read from P and the advanced
+// state written into Q at the same positions (Q may be P; a recording passes one step's
+// state slab as P and the next one's as Q).  Needs step_record_tiled_fits(t, halo).
 struct Tiling;
 bool step_record_tiled_fits(const Tiling& t, int halo);
 
@@ -108,7 +109,7 @@ hipError_t launch_moments_tiled(int shape, const Packets<T>& P, const int32_t* o
                                 const Tiling& t, double* rho, double* Pm, double* e, const RunConsts& k,
                                 hipStream_t s);
 template <typename T>
-hipError_t launch_step_record_tiled(int shape, const Packets<T>& P, void* slab, const int32_t* offsets,
+hipError_t launch_step_record_tiled(int shape, const Packets<T>& P, const Packets<T>& Q, const int32_t* offsets,
                                     const Tiling& t, int halo, const T* E, const T* B, const RunConsts& k,
                                     hipStream_t s);
 
