@@ -125,6 +125,10 @@ typedef struct rsol_params {
                                    the next call files again.  While the flag is set the
                                    caller reads the arrays only after rsol_sync_particles
                                    and writes them only followed by rsol_set_particles     */
+#define RSOL_FLAG_RECORD_ONLY 128 /* rsol_record_states records the states but leaves the
+                                   caller's packet arrays as it found them (the recorded
+                                   states are the same); for a reverse sweep that restores its
+                                   own checkpoints before each recording.                   */
 
 typedef struct rsol_ctx* rsol_handle;
 
@@ -305,7 +309,8 @@ size_t rsol_state_bytes(rsol_handle h);
 
 /* Advance nsteps steps without exchange deposit, writing the state BEFORE each step
  * into states[n] (device buffer of nsteps * rsol_state_bytes).  The caller's packet
- * arrays end advanced by nsteps steps, in their own order.  Internally the packets are
+ * arrays end advanced by nsteps steps, in their own order (with RSOL_FLAG_RECORD_ONLY
+ * they are left unchanged).  Internally the packets are
  * counting-sorted by tile every few steps into a scratch copy, which the steps advance
  * with each tile's E and B staged in on-chip memory; the recorded states are kept in
  * those orders, so that the reverse sweep reads them contiguously. */

@@ -20,7 +20,8 @@ from __future__ import annotations
 
 import torch
 
-from .rsol import RSOL_CIC, RSOL_FLAG_KEEP_ORDER, RSOL_FP32, RSOL_FP64, RSOL_TSC, Handle, Params
+from .rsol import (RSOL_CIC, RSOL_FLAG_KEEP_ORDER, RSOL_FLAG_RECORD_ONLY, RSOL_FP32, RSOL_FP64, RSOL_TSC, Handle,
+                   Params)
 
 
 def _params(spec):
@@ -112,6 +113,9 @@ class RSOLRollout(torch.autograd.Function):
             # and leave their summed milliseconds and count in the spec
             timing = bool(ctx.spec.get("time_reverse"))
             rev_ms, rev_n = 0.0, 0
+            # each segment restores its checkpoint before recording, so the recording
+            # need not bring the packets back into the run's arrays
+            h.rsol_set_flags(RSOL_FLAG_KEEP_ORDER | RSOL_FLAG_RECORD_ONLY)
             for snap, seg in reversed(ckpts):
                 run.restore(snap)
                 h.rsol_record_states(seg, states)
@@ -123,6 +127,7 @@ class RSOLRollout(torch.autograd.Function):
                     h.rsol_timing(False)
                     rev_ms += ms
                     rev_n += n
+            h.rsol_set_flags(RSOL_FLAG_KEEP_ORDER)
             if timing:
                 ctx.spec["reverse_ms"] = rev_ms
                 ctx.spec["reverse_launches"] = rev_n

@@ -118,7 +118,8 @@ bool fp32(const rsol_params& p) { return p.precision == RSOL_FP32; }
 bool naive(const rsol_params& p) { return (p.flags & RSOL_FLAG_NAIVE) != 0; }
 bool loss_layout(const rsol_params& p) { return (p.flags & RSOL_FLAG_LOSSES) != 0; }
 constexpr int32_t kKnownFlags = RSOL_FLAG_KEEP_ORDER | RSOL_FLAG_TILED | RSOL_FLAG_NAIVE | RSOL_FLAG_LOSSES |
-                                RSOL_FLAG_PUSHER_VAY | RSOL_FLAG_PUSHER_HC | RSOL_FLAG_RESIDENT;
+                                RSOL_FLAG_PUSHER_VAY | RSOL_FLAG_PUSHER_HC | RSOL_FLAG_RESIDENT |
+                                RSOL_FLAG_RECORD_ONLY;
 int pusher_of(int32_t flags) {
   return (flags & RSOL_FLAG_PUSHER_VAY) ? kPushVay : (flags & RSOL_FLAG_PUSHER_HC) ? kPushHC : kPushBoris;
 }
@@ -544,8 +545,25 @@ Packets<T> slab_packets(const rsol_ctx* h, const char* at) {
 template <typename T>
 int record_global(rsol_ctx* h, int32_t nsteps, char* states, const RunConsts& k) {
   const SlabLayout sl = slab_layout(h);
+  // RSOL_FLAG_RECORD_ONLY: advance a copy and leave the caller's arrays alone
+  Packets<T> P = caller_packets<T>(h);
+  if (h->p.flags & RSOL_FLAG_RECORD_ONLY) {
+    const Packets<T> c = perm_packets<T>(h);
+    const size_t n = (size_t)h->np;
+    if constexpr (is_fp64<T>()) {
+      RSOL_HIP(h, hipMemcpyAsync(c.x, P.x, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, h->stream), "copy x");
+    } else {
+      RSOL_HIP(h, hipMemcpyAsync(c.cell, P.cell, n * sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream), "copy cell");
+      RSOL_HIP(h, hipMemcpyAsync(c.off, P.off, 3 * n * sizeof(float), hipMemcpyDeviceToDevice, h->stream), "copy off");
+    }
+    RSOL_HIP(h, hipMemcpyAsync(c.u, P.u, 3 * n * sizeof(T), hipMemcpyDeviceToDevice, h->stream), "copy u");
+    P.x = c.x;
+    P.cell = c.cell;
+    P.off = c.off;
+    P.u = c.u;
+  }
   for (int32_t n = 0; n < nsteps; ++n)
-    RSOL_HIP(h, launch_step_record<T>(h->p.shape, caller_packets<T>(h), field_E<T>(h), field_B<T>(h),
+    RSOL_HIP(h, launch_step_record<T>(h->p.shape, P, field_E<T>(h), field_B<T>(h),
                                       states + (size_t)n * sl.total + sl.state, k, h->stream), "record step");
   return RSOL_OK;
 }
@@ -609,7 +627,8 @@ int record_tiled(rsol_ctx* h, int32_t nsteps, char* states, const RunConsts& k) 
              "record step");
     timed_end(h, ev, false);
   }
-  RSOL_HIP(h, launch_unsort<T>(cur, caller_packets<T>(h), h->stream), "record unsort");
+  if (!(states && (h->p.flags & RSOL_FLAG_RECORD_ONLY)))
+    RSOL_HIP(h, launch_unsort<T>(cur, caller_packets<T>(h), h->stream), "record unsort");
   return RSOL_OK;
 }
 

@@ -32,6 +32,7 @@ RSOL_FLAG_WEIGHTS = 8
 RSOL_FLAG_PUSHER_VAY = 16
 RSOL_FLAG_PUSHER_HC = 32
 RSOL_FLAG_RESIDENT = 64
+RSOL_FLAG_RECORD_ONLY = 128
 
 
 class RSOLError(RuntimeError):

@@ -56,7 +56,7 @@ def test_scratch_bytes_positive_and_grows_with_packets():
     dict(nx=0), dict(nx=2000), dict(shape=3), dict(precision=2), dict(sort_every=0), dict(sort_every=9),
     dict(dx=0.0), dict(c_tilde=2000.0), dict(c_tilde=0.0), dict(courant=0.0), dict(courant=0.9),
     dict(mass=-1.0), dict(dt=float("nan")),
-    dict(flags=128), dict(flags=16 | 32), dict(flags=2 | 16), dict(flags=2 | 32),
+    dict(flags=256), dict(flags=16 | 32), dict(flags=2 | 16), dict(flags=2 | 32),
 ])
 def test_invalid_parameters_are_rejected_before_any_device_work(bad):
     rsol, L = _lib()
