@@ -335,12 +335,16 @@ def test_reverse_sweep_over_a_prefix_of_the_recorded_steps():
     assert max_rel_momentum(a["u"], r["u"]) <= 1e-10
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_record_only_leaves_the_packets_and_records_the_same_steps(precision):
+@pytest.mark.parametrize("precision,tiles", [("fp64", None), ("fp32", None), ("fp64", "8,8,8")],
+                         ids=["fp64", "fp32", "fp64-caller-order"])
+def test_record_only_leaves_the_packets_and_records_the_same_steps(precision, tiles, monkeypatch):
     """With RSOL_FLAG_RECORD_ONLY, rsol_record_states leaves the caller's packet arrays
     bit for bit as they were, and the reverse sweep over what it recorded gives the
-    gradients of a recording without the flag (which advances the arrays)."""
+    gradients of a recording without the flag (which advances the arrays); on the tiled
+    recording and, with 8^3 tiles (RSOL_TILE), on the caller-order one."""
     import torch
+    if tiles:
+        monkeypatch.setenv("RSOL_TILE", tiles)
     from paper_2111_14704_amd.rsol import RSOL_FLAG_KEEP_ORDER, RSOL_FLAG_RECORD_ONLY
     from paper_2111_14704_amd.sim import Simulation
     w = make_workload(5, n=8, ppc=4, nsteps=9, precision=precision)
@@ -370,7 +374,7 @@ def test_record_only_leaves_the_packets_and_records_the_same_steps(precision):
         return same, dict(lx=lx.double().cpu().numpy(), lu=lu.double().cpu().numpy(), gE=gE.cpu().numpy(),
                           gB=gB.cpu().numpy())
 
-    _say(f"record only {precision}")
+    _say(f"record only {precision} tiles={tiles}")
     same_a, a = run(RSOL_FLAG_KEEP_ORDER | RSOL_FLAG_RECORD_ONLY)
     same_b, b = run(RSOL_FLAG_KEEP_ORDER)
     assert same_a and not same_b
